@@ -1,0 +1,117 @@
+"""Pins of the multigrid-preconditioned CG (Sect. 3.5 replacement) and of flexible GMRES
+(Sects. 4.1, 4.3)."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import workloads as W
+from oracle.residual import Problem
+from oracle.pbp import pressure_operator, thermal_operator
+from oracle.mg import Multigrid, pcg
+from oracle.krylov import fgmres
+
+
+def _state(shape, bc, seed=1, amp=0.3):
+    nd = len(shape)
+    g = tuple([0.0] * (nd - 1) + [-1.0]) if "wall" in bc else None
+    pd, X = W.random_state(shape, bc, seed=seed, g=g, chi_model="power", chi0=0.05, amp=amp)
+    return Problem.from_dict(pd), X
+
+
+def _stiff_dt(P, cfl=1000.0):
+    return cfl * min(P.dx) / np.sqrt(1.4 * 0.4)
+
+
+@pytest.mark.parametrize("shape,bc", [((8, 8), ("periodic", "periodic")), ((16, 8), ("periodic", "wall")),
+                                      ((8, 8, 8), ("periodic", "periodic", "wall"))])
+def test_vcycle_is_spd(shape, bc):
+    P, X = _state(shape, bc)
+    op = pressure_operator(P, X, _stiff_dt(P, 30.0))
+    mg = Multigrid(op)
+    assert len(mg.levels) >= 2
+    N = P.ncell
+    B = np.empty((N, N))
+    for k in range(N):
+        e = np.zeros(N)
+        e[k] = 1.0
+        B[:, k] = mg.vcycle(e.reshape(P.field_shape)).ravel()
+    assert np.max(np.abs(B - B.T)) <= 1e-12 * np.max(np.abs(B))
+    assert np.min(np.linalg.eigvalsh(0.5 * (B + B.T))) > 0
+
+
+@pytest.mark.parametrize("eta", [1e-4, 1e-10])
+def test_pcg_meets_stopping_rule_and_matches_direct(eta):
+    P, X = _state((32, 32), ("periodic", "wall"), seed=2)
+    op = pressure_operator(P, X, _stiff_dt(P, 100.0))
+    b = np.random.default_rng(3).uniform(-1, 1, P.field_shape)
+    its = []
+    x = pcg(op, b, eta=eta, maxit=100, stats=its)
+    A = op.to_sparse()
+    res = np.linalg.norm(b.ravel() - A @ x.ravel())
+    assert res < eta * np.linalg.norm(b)
+    xd = spla.spsolve(A.tocsc(), b.ravel())
+    ev = np.linalg.eigvalsh(A.toarray())
+    cond = ev[-1] / ev[0]
+    assert np.linalg.norm(x.ravel() - xd) <= eta * cond * np.linalg.norm(xd)
+    assert its[0] < 40
+
+
+def test_pcg_iterations_grid_independent():
+    counts = []
+    for n in (16, 32, 64, 128):
+        P, X = _state((n, n), ("periodic", "wall"), seed=4, amp=0.2)
+        op = pressure_operator(P, X, _stiff_dt(P, 1000.0))
+        b = np.random.default_rng(5).uniform(-1, 1, P.field_shape)
+        its = []
+        pcg(op, b, eta=1e-8, maxit=100, stats=its)
+        counts.append(its[0])
+    assert max(counts) <= 30 and counts[-1] <= 2 * counts[0] + 4, counts
+
+
+def test_pcg_fp32_variant():
+    """FP32 operator, vectors and dots: the normalised solve reaches ~1e-5 relative accuracy."""
+    P, X = _state((64, 64), ("periodic", "wall"), seed=6)
+    op = thermal_operator(P, X, _stiff_dt(P, 100.0))
+    b = 1e3 * np.random.default_rng(7).uniform(-1, 1, P.field_shape)
+    x32 = pcg(op, b, eta=1e-4, dtype=np.float32)
+    x64 = pcg(op, b, eta=1e-4)
+    A = op.to_sparse()
+    r32 = np.linalg.norm(b.ravel() - A @ x32.ravel()) / np.linalg.norm(b)
+    assert r32 < 2e-4
+    assert x32.dtype == np.float64
+    assert np.linalg.norm(x32 - x64) / np.linalg.norm(x64) < 1e-3
+
+
+def test_fgmres_small_exact():
+    rng = np.random.default_rng(1)
+    n = 20
+    A = np.eye(n) * 4 + rng.uniform(-1, 1, (n, n))
+    b = rng.uniform(-1, 1, n)
+    rec = []
+    x, info = fgmres(lambda z: A @ z, lambda v: v, b, eta=1e-14, m=30, record=rec)
+    assert info["converged"] and info["iters"] <= n
+    assert np.allclose(x, np.linalg.solve(A, b), rtol=0, atol=1e-12 * np.abs(x).max())
+    cyc = rec[0]
+    V = np.stack(cyc["V"], axis=1)
+    Z = np.stack(cyc["Z"], axis=1)
+    k = Z.shape[1]
+    H = cyc["H"]
+    # Arnoldi relation A Z_k = V_{k+1} H_k (happy breakdown may drop the last basis vector)
+    AZ = A @ Z
+    VH = V[:, : H.shape[0]] @ H[: V.shape[1]]
+    assert np.max(np.abs(AZ - VH)) <= 1e-12 * np.max(np.abs(AZ))
+    assert np.max(np.abs(V.T @ V - np.eye(V.shape[1]))) <= 1e-14
+
+
+def test_fgmres_restart_and_residual_estimates():
+    """Restarted FGMRES with a variable (noisy) preconditioner: residual estimates are
+    non-increasing within a cycle and the reported convergence is real."""
+    rng = np.random.default_rng(2)
+    n = 80
+    A = np.diag(np.linspace(1, 50, n)) + 0.3 * rng.uniform(-1, 1, (n, n))
+    b = rng.uniform(-1, 1, n)
+    D = np.diag(A)
+    prec = lambda v: v / D * (1 + 1e-3 * rng.uniform(-1, 1, n))
+    x, info = fgmres(lambda z: A @ z, prec, b, eta=1e-8, m=10, maxit=300)
+    assert info["converged"]
+    assert np.linalg.norm(b - A @ x) < 1e-8 * np.linalg.norm(b) * 1.0001
