@@ -1,0 +1,158 @@
+/*
+ * jfnk.h - C ABI of the MI355X (gfx950) implicit-step library.
+ *
+ * Jacobian-free Newton-Krylov solver with physics-based preconditioning for the inviscid
+ * compressible equations with gravity and thermal conduction, after Viallet et al.,
+ * "A Jacobian-free Newton-Krylov method for time-implicit multidimensional hydrodynamics"
+ * (A&A 2016, arXiv 1512.03662).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * State X and all vectors: contiguous FP64 structure-of-arrays in device memory,
+ *   X[var][nz][ny][nx] (2D: X[var][ny][nx]), var = rho, e, u_x, u_y[, u_z]; x fastest.
+ *   Cell (i,j,k) holds rho and e at its centre and u_d on its low-d face (Sect. 2: finite
+ *   volumes with staggered velocities).  nvar = 2 + ndim, N = nx*ny[*nz], length nvar*N.
+ * Ownership: array arguments belong to the caller; the library never keeps a pointer past
+ *   the call.  The context owns its workspace, allocated by jfnk_create.
+ * Space: every entry point works in unscaled physical variables; the diagonal scalings of
+ *   the Newton system (Sect. 4.1, eq. jacobian_system_norm) are internal.
+ * Wall-normal velocities on wall faces are stored and are zero; their residual row is
+ *   rho_f u / dt - b (no flux acts on them) so J, M and J^T act there as the diagonal.
+ * Streams: all work is ordered on the stream given to jfnk_create.  jfnk_residual,
+ *   jfnk_jvp, jfnk_vjp and jfnk_vjp_prev are asynchronous; jfnk_precond_apply,
+ *   jfnk_implicit_step, jfnk_adjoint_step and jfnk_cfl_dt synchronise the stream.
+ * Errors: negative status codes; jfnk_last_error() gives the message.  Nothing throws
+ *   across this boundary.  A context is not thread-safe; use one context per stream.
+ */
+#ifndef JFNK_H
+#define JFNK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct jfnk_ctx jfnk_ctx;
+
+enum {
+  JFNK_OK = 0,
+  JFNK_E_INVALID = -1,       /* bad argument, shape or option                          */
+  JFNK_E_DEVICE = -2,        /* HIP error, including out-of-memory at create           */
+  JFNK_E_NONFINITE = -3,     /* NaN/Inf met in a norm                                  */
+  JFNK_E_GMRES_NOCONV = -4,  /* linear solve hit gmres_maxit (Newton continues)        */
+  JFNK_E_NEWTON_NOCONV = -5  /* newton_max iterations without meeting newton_tol      */
+};
+
+enum { JFNK_BC_PERIODIC = 0, JFNK_BC_WALL = 1 };
+enum { JFNK_CHI_NONE = 0, JFNK_CHI_CONST = 1, JFNK_CHI_POWER = 2 };
+enum { JFNK_JV_FD = 0, JFNK_JV_EXACT = 1 };
+enum { JFNK_PC_NONE = 0, JFNK_PC_SOUND = 1, JFNK_PC_SOUND_THERMAL = 2 };
+enum { JFNK_FP64 = 0, JFNK_FP32 = 1 };
+
+/* Problem: grid, ideal-gas EOS (R = mu = 1: p = (gamma-1) rho e, T = (gamma-1) e),
+ * gravity and conductivity (Sect. 2, eqs. cons1-cons3, chirad).                       */
+typedef struct {
+  int32_t ndim;          /* 2 or 3                                                      */
+  int32_t n[3];          /* cells along x, y, z (n[2] = 1 in 2D); each used axis >= 4  */
+  double dx[3];          /* spacing per axis                                            */
+  int32_t bc[3];         /* JFNK_BC_PERIODIC | JFNK_BC_WALL per axis                    */
+  double gamma;          /* adiabatic index (Gamma1 = Gamma3 = gamma)                  */
+  double g[3];           /* gravity vector                                              */
+  int32_t chi_model;     /* NONE | CONST (chi0) | POWER (chi0 (T/chi_tref)^chi_exp)     */
+  double chi0, chi_tref, chi_exp;
+  double qwall[3][2];    /* prescribed conductive flux chi dT/dx_d on the low/high wall  */
+  double theta;          /* time weighting: 1 = backward Euler, 1/2 = Crank-Nicolson    */
+} jfnk_problem;
+
+/* Solver options; jfnk_default_opts fills the values the paper uses (Sect. 4, 5.1.1).  */
+typedef struct {
+  double newton_tol;     /* ||R^-1 dX||_inf stopping threshold (eq. nr_terminate)       */
+  int32_t newton_max;    /* maximum Newton iterations                                   */
+  int32_t newton_min;    /* minimum Newton iterations (the paper enforces 2)            */
+  int32_t gmres_m;       /* restart length (<= 64)                                       */
+  int32_t gmres_maxit;   /* maximum GMRES iterations per Newton iteration               */
+  double gmres_eta;      /* forcing term eta (eq. forcing_term)                         */
+  int32_t jv_mode;       /* JFNK_JV_FD (eqs. jacobian_free, pert_old) | JFNK_JV_EXACT  */
+  double fd_lambda;      /* lambda of eq. pert_old                                      */
+  double alpha1, alpha2; /* velocity floors of the scalings (Sect. 4.1)                 */
+  int32_t precond;       /* JFNK_PC_NONE | JFNK_PC_SOUND | JFNK_PC_SOUND_THERMAL        */
+  int32_t ell_precision; /* JFNK_FP64 | JFNK_FP32 elliptic solves                       */
+  double cg_eta;         /* parabolic-solve tolerance eta' (eq. forcing_term2)          */
+  int32_t cg_maxit;      /* maximum CG iterations per elliptic solve                    */
+} jfnk_opts;
+
+typedef struct {
+  int32_t newton_its;    /* Newton iterations taken                                     */
+  int32_t gmres_its;     /* GMRES iterations summed over Newton iterations              */
+  int32_t cg_its;        /* CG iterations summed over all elliptic solves               */
+  int32_t converged;     /* 1 if newton_tol was met                                     */
+  double f0_norm;        /* ||L^-1 F(X^(0))||_2                                         */
+  double f_norm;         /* ||L^-1 F|| at the last Newton iterate                       */
+  double last_dx_norm;   /* ||R^-1 dX||_inf of the last correction                      */
+  double dt;             /* time step used                                              */
+} jfnk_step_stats;
+
+/* Fill *opts with the defaults: newton_tol 1e-8, newton_max 20, newton_min 2, gmres_m 30,
+ * gmres_maxit 300, gmres_eta 1e-4, JV_FD, fd_lambda 1e-7, alpha1 1e-5, alpha2 1,
+ * PC_SOUND, FP64, cg_eta 1e-4, cg_maxit 50.                                            */
+void jfnk_default_opts(jfnk_opts* opts);
+
+/* Create a context for one problem on one HIP stream (hip_stream: hipStream_t or NULL for
+ * the null stream).  Allocates every workspace buffer.  JFNK_E_INVALID on a bad problem
+ * or option, JFNK_E_DEVICE if allocation fails.  *out is NULL on failure.              */
+int jfnk_create(const jfnk_problem* prob, const jfnk_opts* opts, void* hip_stream,
+                jfnk_ctx** out);
+int jfnk_destroy(jfnk_ctx* ctx);
+/* Change solver options of an existing context (gmres_m may not exceed the created one). */
+int jfnk_set_opts(jfnk_ctx* ctx, const jfnk_opts* opts);
+size_t jfnk_workspace_bytes(const jfnk_ctx* ctx);
+/* Message of the last error on ctx (or of the last failed jfnk_create if ctx is NULL).  */
+const char* jfnk_last_error(const jfnk_ctx* ctx);
+
+/* Store dt and b = U(X^n)/dt + (1-theta) R(X^n) (eq. crank_nicholson, theta-weighted)
+ * for the next residual / jvp / vjp / precond calls.  X^n is copied.                   */
+int jfnk_set_state_n(jfnk_ctx* ctx, const double* Xn, double dt);
+
+/* F = U(X)/dt - theta R(X) - b (eq. crank_nicholson), R the staggered finite-volume
+ * operator (Sect. 2) as specified in the design notes.  Needs jfnk_set_state_n.        */
+int jfnk_residual(jfnk_ctx* ctx, const double* X, double* F);
+
+/* J v with J = dF/dX at X.  mode JFNK_JV_FD: (F(X + delta v) - F(X))/delta with
+ * delta = lambda (lambda + ||R^-1 X||_2/||R^-1 v||_2) (eqs. jacobian_free, pert_old).
+ * mode JFNK_JV_EXACT: forward-mode derivative of F (frozen upwind/limiter branches).   */
+int jfnk_jvp(jfnk_ctx* ctx, const double* X, const double* v, double* Jv, int32_t mode);
+
+/* J^T w at X (exact, frozen branches; deterministic gather form, no atomics).          */
+int jfnk_vjp(jfnk_ctx* ctx, const double* X, const double* w, double* JTw);
+
+/* (dF/dX^n)^T lam = -(dU/dX|_{X^n})^T lam / dt  (theta = 1 only).                     */
+int jfnk_vjp_prev(jfnk_ctx* ctx, const double* Xn, const double* lam, double* out);
+
+/* z ~ +J^-1 r by the physics-based preconditioner frozen at X (Sect. 4.3 with the
+ * semi-implicit schemes of Sects. 3.3-3.4); elliptic solves by multigrid-preconditioned
+ * CG to opts.cg_eta in opts.ell_precision.  Needs jfnk_set_state_n (for dt).           */
+int jfnk_precond_apply(jfnk_ctx* ctx, const double* X, const double* r, double* z);
+
+/* One implicit step: X holds X^n on entry and X^{n+1} on return (Sect. 4).  dt > 0 is
+ * used as given.  Newton from X^n on the scaled system, FGMRES(m) with CGS2, J.v per
+ * opts.jv_mode, right preconditioner per opts.precond.  Returns JFNK_OK when converged,
+ * JFNK_E_NEWTON_NOCONV otherwise (X then holds the last iterate).  stats may be NULL.   */
+int jfnk_implicit_step(jfnk_ctx* ctx, double* X, double dt, jfnk_step_stats* stats);
+
+/* Adjoint of one implicit step (theta = 1): given gbar_n1 = dL/dX^{n+1} at the converged
+ * X^{n+1} = Xn1 of the step from Xn with dt, solve J^T lam = gbar_n1 (FGMRES on the scaled
+ * transposed system with the transposed preconditioner, tolerance opts.gmres_eta) and
+ * return gbar_n = dL/dX^n = (dU/dX|_{X^n})^T lam / dt.                                  */
+int jfnk_adjoint_step(jfnk_ctx* ctx, const double* Xn1, const double* Xn, double dt,
+                      const double* gbar_n1, double* gbar_n, jfnk_step_stats* stats);
+
+/* dt = cfl * min_d dx_d / max_c(|u_c| + c_s), u_c the cell-centred mean of the face
+ * velocities (Introduction, CFL_hydro).  Synchronises; returns a negative value on error. */
+double jfnk_cfl_dt(jfnk_ctx* ctx, const double* X, double cfl);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* JFNK_H */

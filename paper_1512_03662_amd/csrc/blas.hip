@@ -1,0 +1,360 @@
+// Vector kernels of the Krylov solvers: deterministic reductions (64-lane wavefront
+// shuffles, then LDS across the 4 waves of a block, then per-block partials summed in block
+// order by the last block to finish), the fused classical Gram-Schmidt passes of the Arnoldi
+// step (Sect. 4.1: GMRES), linear combinations and the scaled norms of eq. nr_terminate.
+//
+// Every reduction visits elements in a fixed order for a given grid, so results are
+// bitwise reproducible run to run.
+#include <array>
+#include <utility>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace jfnk {
+
+struct OpSum {
+  static __device__ __forceinline__ double f(double a, double b) { return a + b; }
+  static constexpr double id = 0.0;
+};
+struct OpMax {
+  static __device__ __forceinline__ double f(double a, double b) { return fmax(a, b); }
+  static constexpr double id = 0.0;  // reductions of non-negative values only
+};
+
+template <class Op>
+__device__ __forceinline__ double wave_reduce(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = Op::f(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// Reduce K per-thread values over the block, store the block partial, and let the last block
+// combine all partials into out[0..K-1].
+template <class Op, int K>
+__device__ __forceinline__ void block_finish(const double (&vals)[K], double* out, const RedWS& ws) {
+  constexpr int NW = kBlock / 64;
+  __shared__ double sm[NW][K];
+  __shared__ bool is_last;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double v = wave_reduce<Op>(vals[k]);
+    if (lane == 0) sm[wid][k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < K) {
+    double acc = sm[0][threadIdx.x];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) acc = Op::f(acc, sm[w][threadIdx.x]);
+    ws.part[(size_t)blockIdx.x * K + threadIdx.x] = acc;
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned int t = atomicAdd(ws.count, 1u);
+    is_last = (t == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  const int nb = gridDim.x;
+  for (int k = 0; k < K; ++k) {
+    double acc = Op::id;
+    for (int b = threadIdx.x; b < nb; b += kBlock) acc = Op::f(acc, ws.part[(size_t)b * K + k]);
+    acc = wave_reduce<Op>(acc);
+    __syncthreads();
+    if (lane == 0) sm[wid][0] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = sm[0][0];
+      for (int w = 1; w < NW; ++w) s = Op::f(s, sm[w][0]);
+      out[k] = s;
+    }
+  }
+  if (threadIdx.x == 0) *ws.count = 0u;
+}
+
+static inline int red_blocks(size_t n) {
+  size_t b = (n + kBlock - 1) / kBlock;
+  if (b > (size_t)kRedBlocks) b = kRedBlocks;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+// ---- dot ---------------------------------------------------------------------------------
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_dot(size_t n, const T* a, const T* b, double* out, RedWS ws) {
+  T acc = T(0);
+  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
+    acc += a[i] * b[i];
+  double v[1] = {(double)acc};
+  block_finish<OpSum, 1>(v, out, ws);
+}
+
+template <class T>
+void launch_dot(size_t n, const T* a, const T* b, double* out, const RedWS& w, hipStream_t s) {
+  k_dot<T><<<red_blocks(n), kBlock, 0, s>>>(n, a, b, out, w);
+}
+template void launch_dot<double>(size_t, const double*, const double*, double*, const RedWS&, hipStream_t);
+template void launch_dot<float>(size_t, const float*, const float*, double*, const RedWS&, hipStream_t);
+
+// ---- Gram-Schmidt passes -----------------------------------------------------------------
+template <int K>
+__global__ void __launch_bounds__(kBlock) k_multidot(size_t n, const double* V, size_t ld, const double* w,
+                                                     double* out, RedWS ws) {
+  double acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = 0.0;
+  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+    double wi = w[i];
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] += V[k * ld + i] * wi;
+  }
+  block_finish<OpSum, K>(acc, out, ws);
+}
+
+template <int K>
+__global__ void __launch_bounds__(kBlock) k_cgs2_update_dot(size_t n, const double* V, size_t ld,
+                                                            const double* h, double* w, double* out,
+                                                            RedWS ws) {
+  double acc[K + 1];
+  double hk[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    acc[k] = 0.0;
+    hk[k] = h[k];
+  }
+  acc[K] = 0.0;
+  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+    double v[K];
+    double wi = w[i];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      v[k] = V[k * ld + i];
+      wi -= hk[k] * v[k];
+    }
+    w[i] = wi;
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] += v[k] * wi;
+    acc[K] += wi * wi;
+  }
+  block_finish<OpSum, K + 1>(acc, out, ws);
+}
+
+template <int K>
+__global__ void __launch_bounds__(kBlock) k_cgs2_update_norm(size_t n, const double* V, size_t ld,
+                                                             const double* h, const double* w,
+                                                             double* dst, double* out, RedWS ws) {
+  double hk[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) hk[k] = h[k];
+  double acc[1] = {0.0};
+  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+    double wi = w[i];
+#pragma unroll
+    for (int k = 0; k < K; ++k) wi -= hk[k] * V[k * ld + i];
+    dst[i] = wi;
+    acc[0] += wi * wi;
+  }
+  block_finish<OpSum, 1>(acc, out, ws);
+}
+
+template <int K>
+__global__ void __launch_bounds__(kBlock) k_lincomb(size_t n, const double* Z, size_t ld, const double* y,
+                                                    double* dst) {
+  double yk[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) yk[k] = y[k];
+  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) s += yk[k] * Z[k * ld + i];
+    dst[i] = s;
+  }
+}
+
+using MdFn = void (*)(size_t, const double*, size_t, const double*, const double*, double*, double*,
+                      const RedWS&, hipStream_t);
+
+template <int K>
+static void md_launch(size_t n, const double* V, size_t ld, const double* h, const double* w,
+                      double* w_mut, double* out, const RedWS& ws, hipStream_t s) {
+  (void)h;
+  (void)w_mut;
+  k_multidot<K><<<red_blocks(n), kBlock, 0, s>>>(n, V, ld, w, out, ws);
+}
+template <int K>
+static void ud_launch(size_t n, const double* V, size_t ld, const double* h, const double* w,
+                      double* w_mut, double* out, const RedWS& ws, hipStream_t s) {
+  (void)w;
+  k_cgs2_update_dot<K><<<red_blocks(n), kBlock, 0, s>>>(n, V, ld, h, w_mut, out, ws);
+}
+template <int K>
+static void un_launch(size_t n, const double* V, size_t ld, const double* h, const double* w,
+                      double* dst, double* out, const RedWS& ws, hipStream_t s) {
+  k_cgs2_update_norm<K><<<red_blocks(n), kBlock, 0, s>>>(n, V, ld, h, w, dst, out, ws);
+}
+template <int K>
+static void lc_launch(size_t n, const double* Z, size_t ld, const double* y, const double* w,
+                      double* dst, double* out, const RedWS& ws, hipStream_t s) {
+  (void)w;
+  (void)out;
+  (void)ws;
+  size_t b = (n + kBlock - 1) / kBlock;
+  if (b > 4096) b = 4096;
+  k_lincomb<K><<<(unsigned)b, kBlock, 0, s>>>(n, Z, ld, y, dst);
+}
+
+constexpr int kMaxBasis = kMaxK - 1;  // K ranges over 1..kMaxBasis
+
+template <template <int> class F, size_t... I>
+constexpr std::array<MdFn, sizeof...(I)> make_table(std::index_sequence<I...>) {
+  return {{&F<(int)I + 1>::run...}};
+}
+template <int K> struct MdT { static void run(size_t n, const double* V, size_t ld, const double* h, const double* w, double* m, double* o, const RedWS& ws, hipStream_t s) { md_launch<K>(n, V, ld, h, w, m, o, ws, s); } };
+template <int K> struct UdT { static void run(size_t n, const double* V, size_t ld, const double* h, const double* w, double* m, double* o, const RedWS& ws, hipStream_t s) { ud_launch<K>(n, V, ld, h, w, m, o, ws, s); } };
+template <int K> struct UnT { static void run(size_t n, const double* V, size_t ld, const double* h, const double* w, double* m, double* o, const RedWS& ws, hipStream_t s) { un_launch<K>(n, V, ld, h, w, m, o, ws, s); } };
+template <int K> struct LcT { static void run(size_t n, const double* V, size_t ld, const double* h, const double* w, double* m, double* o, const RedWS& ws, hipStream_t s) { lc_launch<K>(n, V, ld, h, w, m, o, ws, s); } };
+
+static const auto kMd = make_table<MdT>(std::make_index_sequence<kMaxBasis>{});
+static const auto kUd = make_table<UdT>(std::make_index_sequence<kMaxBasis - 1>{});
+static const auto kUn = make_table<UnT>(std::make_index_sequence<kMaxBasis>{});
+static const auto kLc = make_table<LcT>(std::make_index_sequence<kMaxBasis>{});
+
+void launch_multidot(size_t n, const double* V, size_t ld, int K, const double* w, double* out,
+                     const RedWS& ws, hipStream_t s) {
+  kMd[K - 1](n, V, ld, nullptr, w, nullptr, out, ws, s);
+}
+void launch_cgs2_update_dot(size_t n, const double* V, size_t ld, int K, const double* h, double* w,
+                            double* out, const RedWS& ws, hipStream_t s) {
+  kUd[K - 1](n, V, ld, h, nullptr, w, out, ws, s);
+}
+void launch_cgs2_update_norm(size_t n, const double* V, size_t ld, int K, const double* h,
+                             const double* w, double* dst, double* out, const RedWS& ws,
+                             hipStream_t s) {
+  kUn[K - 1](n, V, ld, h, w, dst, out, ws, s);
+}
+void launch_lincomb(size_t n, const double* Z, size_t ld, int K, const double* y, double* dst,
+                    hipStream_t s) {
+  kLc[K - 1](n, Z, ld, y, nullptr, dst, nullptr, RedWS{}, s);
+}
+
+// ---- elementwise -------------------------------------------------------------------------
+__global__ void k_scale_by_inv_sqrt(size_t n, const double* src, const double* nrm2, double* dst) {
+  double sc = 1.0 / sqrt(*nrm2);
+  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
+    dst[i] = src[i] * sc;
+}
+void launch_scale_by_inv_sqrt(size_t n, const double* src, const double* nrm2, double* dst,
+                              hipStream_t s) {
+  size_t b = (n + kBlock - 1) / kBlock;
+  if (b > 8192) b = 8192;
+  k_scale_by_inv_sqrt<<<(unsigned)b, kBlock, 0, s>>>(n, src, nrm2, dst);
+}
+
+__global__ void k_axpy(size_t n, double a, const double* x, double* y) {
+  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
+    y[i] += a * x[i];
+}
+void launch_axpy(size_t n, double a, const double* x, double* y, hipStream_t s) {
+  size_t b = (n + kBlock - 1) / kBlock;
+  if (b > 8192) b = 8192;
+  k_axpy<<<(unsigned)b, kBlock, 0, s>>>(n, a, x, y);
+}
+
+template <class T>
+__global__ void k_fill(size_t n, T v, T* y) {
+  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
+    y[i] = v;
+}
+void launch_fill(size_t n, double v, double* y, hipStream_t s) { launch_fill_t<double>(n, v, y, s); }
+template <class T>
+void launch_fill_t(size_t n, T v, T* y, hipStream_t s) {
+  size_t b = (n + kBlock - 1) / kBlock;
+  if (b > 8192) b = 8192;
+  if (b < 1) b = 1;
+  k_fill<T><<<(unsigned)b, kBlock, 0, s>>>(n, v, y);
+}
+template void launch_fill_t<double>(size_t, double, double*, hipStream_t);
+template void launch_fill_t<float>(size_t, float, float*, hipStream_t);
+
+// ---- scaled norms (R of Sect. 4.1 recomputed from X) ------------------------------------
+template <int ND>
+__device__ __forceinline__ void cell_R_scale(const Grid& G, const Pos& P, const double* X, double alpha2,
+                                             double* Rs) {
+  const double k = G.gamma * (G.gamma - 1.0);
+  double e0 = X[G.N + P.lin];
+  double cs0 = sqrt(k * e0);
+  Rs[0] = X[P.lin];
+  Rs[1] = e0;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    double s;
+    int im = gidx(G, P, 1, shift(off0(), d, -1), &s);
+    double csf = 0.5 * (sqrt(k * X[G.N + im]) + cs0);
+    Rs[2 + d] = fmax(fabs(X[(2 + d) * G.N + P.lin]), alpha2 * csf);
+  }
+}
+
+template <int ND, bool MAX>
+__global__ void __launch_bounds__(kBlock) k_scaled_red(Grid G, const double* X, const double* V,
+                                                       double alpha2, double* out, RedWS ws) {
+  double acc = 0.0;
+  for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < G.N; lin += gridDim.x * kBlock) {
+    Pos P = make_pos(G, lin);
+    double Rs[2 + ND];
+    cell_R_scale<ND>(G, P, X, alpha2, Rs);
+#pragma unroll
+    for (int v = 0; v < 2 + ND; ++v) {
+      double q = V[v * G.N + lin] / Rs[v];
+      if (MAX) acc = fmax(acc, fabs(q));
+      else acc += q * q;
+    }
+  }
+  double a[1] = {acc};
+  if (MAX) block_finish<OpMax, 1>(a, out, ws);
+  else block_finish<OpSum, 1>(a, out, ws);
+}
+
+void launch_scaled_norm2(const Grid& G, const double* X, const double* V, double alpha2,
+                         double* out, const RedWS& ws, hipStream_t s) {
+  int b = red_blocks(G.N);
+  if (G.nd == 2) k_scaled_red<2, false><<<b, kBlock, 0, s>>>(G, X, V, alpha2, out, ws);
+  else k_scaled_red<3, false><<<b, kBlock, 0, s>>>(G, X, V, alpha2, out, ws);
+}
+void launch_scaled_maxabs(const Grid& G, const double* X, const double* V, double alpha2,
+                          double* out, const RedWS& ws, hipStream_t s) {
+  int b = red_blocks(G.N);
+  if (G.nd == 2) k_scaled_red<2, true><<<b, kBlock, 0, s>>>(G, X, V, alpha2, out, ws);
+  else k_scaled_red<3, true><<<b, kBlock, 0, s>>>(G, X, V, alpha2, out, ws);
+}
+
+// max_c (|u_c| + c_s), u_c the mean of the two faces of c along each axis (Introduction)
+template <int ND>
+__global__ void __launch_bounds__(kBlock) k_cfl_speed(Grid G, const double* X, double* out, RedWS ws) {
+  double acc = 0.0;
+  const double k = G.gamma * (G.gamma - 1.0);
+  for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < G.N; lin += gridDim.x * kBlock) {
+    Pos P = make_pos(G, lin);
+    double u2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      double s0, s1;
+      int i0 = gidx(G, P, 2 + d, off0(), &s0);
+      int i1 = gidx(G, P, 2 + d, shift(off0(), d, 1), &s1);
+      double uc = 0.5 * (s0 * X[(2 + d) * G.N + i0] + s1 * X[(2 + d) * G.N + i1]);
+      u2 += uc * uc;
+    }
+    acc = fmax(acc, sqrt(u2) + sqrt(k * X[G.N + lin]));
+  }
+  double a[1] = {acc};
+  block_finish<OpMax, 1>(a, out, ws);
+}
+void launch_cfl_speed(const Grid& G, const double* X, double* out, const RedWS& ws, hipStream_t s) {
+  int b = red_blocks(G.N);
+  if (G.nd == 2) k_cfl_speed<2><<<b, kBlock, 0, s>>>(G, X, out, ws);
+  else k_cfl_speed<3><<<b, kBlock, 0, s>>>(G, X, out, ws);
+}
+
+}  // namespace jfnk

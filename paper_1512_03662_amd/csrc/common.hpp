@@ -1,0 +1,171 @@
+// Device-side building blocks shared by the kernels of the implicit-step library (gfx950).
+//
+// Layout: structure-of-arrays FP64 fields, field v of cell (i,j,k) at v*N + i + nx*(j + ny*k).
+// rho, e at cell centres; u_d on the low-d face of the cell (Sect. 2, staggered grid).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace jfnk {
+
+constexpr int kMaxDim = 3;
+constexpr int kBlock = 256;
+
+struct Grid {
+  int nd;
+  int n[3];
+  int N;            // cells
+  int stride[3];    // 1, nx, nx*ny
+  int bc[3];        // 0 periodic, 1 wall
+  double dx[3];
+  double idx[3];    // 1/dx
+  double gamma;
+  double g[3];
+  int chi_model;    // 0 none, 1 const, 2 power
+  double chi0, chi_tref_inv, chi_exp;
+  double qwall[3][2];
+  double theta;
+};
+
+// ------------------------------------------------------------------------------------
+// Forward-mode dual number: value and one tangent.
+// ------------------------------------------------------------------------------------
+struct dual {
+  double v, d;
+  __device__ __forceinline__ dual() = default;
+  __device__ __forceinline__ constexpr dual(double a) : v(a), d(0.0) {}
+  __device__ __forceinline__ constexpr dual(double a, double b) : v(a), d(b) {}
+};
+__device__ __forceinline__ dual operator+(dual a, dual b) { return dual(a.v + b.v, a.d + b.d); }
+__device__ __forceinline__ dual operator-(dual a, dual b) { return dual(a.v - b.v, a.d - b.d); }
+__device__ __forceinline__ dual operator-(dual a) { return dual(-a.v, -a.d); }
+__device__ __forceinline__ dual operator*(dual a, dual b) {
+  return dual(a.v * b.v, a.d * b.v + a.v * b.d);
+}
+__device__ __forceinline__ dual operator*(double s, dual a) { return dual(s * a.v, s * a.d); }
+__device__ __forceinline__ dual operator*(dual a, double s) { return dual(s * a.v, s * a.d); }
+__device__ __forceinline__ dual operator/(dual a, dual b) {
+  double q = a.v / b.v;
+  return dual(q, (a.d - q * b.d) / b.v);
+}
+__device__ __forceinline__ dual operator+(dual a, double s) { return dual(a.v + s, a.d); }
+
+__device__ __forceinline__ double val(double a) { return a; }
+__device__ __forceinline__ double val(dual a) { return a.v; }
+__device__ __forceinline__ double tan_of(double) { return 0.0; }
+__device__ __forceinline__ double tan_of(dual a) { return a.d; }
+
+// x^p for positive x; p == 3 exactly takes the product form.
+__device__ __forceinline__ double powr(double x, double p) {
+  return p == 3.0 ? x * x * x : pow(x, p);
+}
+__device__ __forceinline__ dual powr(dual x, double p) {
+  if (p == 3.0) {
+    double x2 = x.v * x.v;
+    return dual(x2 * x.v, 3.0 * x2 * x.d);
+  }
+  double y = pow(x.v, p);
+  return dual(y, p * y / x.v * x.d);
+}
+
+// van Leer (1974) harmonic slope: 2ab/(a+b) if ab > 0, else 0 (branch frozen for tangents).
+template <class T>
+__device__ __forceinline__ T vl(T a, T b) {
+  if (val(a) * val(b) > 0.0) return (2.0 * a * b) / (a + b);
+  return T(0.0);
+}
+
+// Upwind van Leer value at the face between q[c-1] (qm1) and q[c] (q0): w >= 0 takes the
+// left-biased reconstruction.
+template <class T>
+__device__ __forceinline__ T upwind(T qm2, T qm1, T q0, T qp1, double w) {
+  if (w >= 0.0) return qm1 + 0.5 * vl(qm1 - qm2, q0 - qm1);
+  return q0 - 0.5 * vl(q0 - qm1, qp1 - q0);
+}
+
+// ------------------------------------------------------------------------------------
+// Ghost rules per axis.  Periodic: wrap.  Wall: cell-centred and tangential quantities
+// mirror evenly; the wall-normal velocity is zero on both wall faces, odd outside.
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ int wrap(int i, int n) {
+  if (i < 0) return i + n;
+  if (i >= n) return i - n;
+  return i;
+}
+__device__ __forceinline__ int ghost_even(int i, int n, int bc) {
+  if (bc == 0) return wrap(i, n);
+  if (i < 0) return -1 - i;
+  if (i >= n) return 2 * n - 1 - i;
+  return i;
+}
+// returns source index; *s = +1, -1 or 0
+__device__ __forceinline__ int ghost_normal(int i, int n, int bc, double* s) {
+  if (bc == 0) {
+    *s = 1.0;
+    return wrap(i, n);
+  }
+  if (i < 0) { *s = -1.0; return -i; }
+  if (i > n) { *s = -1.0; return 2 * n - i; }
+  if (i == 0 || i == n) { *s = 0.0; return 0; }
+  *s = 1.0;
+  return i;
+}
+
+// Position of one thread's cell; loads of field var at an offset apply the ghost rules
+// unless the whole radius-3 stencil is inside the grid ("interior").
+struct Pos {
+  int c[3];
+  int lin;
+  bool interior;
+};
+
+__device__ __forceinline__ Pos make_pos(const Grid& G, int lin) {
+  Pos p;
+  p.lin = lin;
+  int r = lin;
+  p.c[0] = r % G.n[0];
+  r /= G.n[0];
+  p.c[1] = r % G.n[1];
+  p.c[2] = r / G.n[1];
+  bool in = true;
+  for (int d = 0; d < G.nd; ++d) in = in && (p.c[d] >= 3) && (p.c[d] <= G.n[d] - 3);
+  p.interior = in;
+  return p;
+}
+
+// Offsets are packed as (ox, oy, oz).
+struct Off {
+  int o[3];
+};
+__device__ __forceinline__ Off off0() { return Off{{0, 0, 0}}; }
+__device__ __forceinline__ Off shift(Off a, int d, int k) {
+  a.o[d] += k;
+  return a;
+}
+
+// index and sign of field var at offset; var >= 2 is velocity component var-2.
+__device__ __forceinline__ int gidx(const Grid& G, const Pos& p, int var, Off o, double* s) {
+  if (p.interior) {
+    *s = 1.0;
+    return p.lin + o.o[0] + o.o[1] * G.stride[1] + o.o[2] * G.stride[2];
+  }
+  double sign = 1.0;
+  int idx = 0;
+  for (int d = 0; d < G.nd; ++d) {
+    int i = p.c[d] + o.o[d];
+    int src;
+    if (var == 2 + d) {
+      double sd;
+      src = ghost_normal(i, G.n[d], G.bc[d], &sd);
+      sign *= sd;
+    } else {
+      src = ghost_even(i, G.n[d], G.bc[d]);
+    }
+    idx += src * G.stride[d];
+  }
+  *s = sign;
+  return idx;
+}
+
+}  // namespace jfnk

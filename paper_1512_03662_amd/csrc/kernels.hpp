@@ -1,0 +1,131 @@
+// Host-callable launchers of the device kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+#include "common.hpp"
+
+namespace jfnk {
+
+struct ResidArgs {
+  const double* X = nullptr;         // state
+  const double* V = nullptr;         // direction (tangent or finite-difference step)
+  const double* B = nullptr;         // subtracted vector (b, or G0 for finite differences)
+  double* out = nullptr;
+  double* G0 = nullptr;              // optional second output cU U + cR R (value mode)
+  double cU = 0.0, cR = 0.0;         // out = cU U + cR R - B
+  const double* fd_norms = nullptr;  // device [||R^-1 X||^2, ||R^-1 V||^2] (FD mode)
+  double fd_lambda = 1e-7;
+  int scaleL = 0;                    // divide each row by L
+  double alpha1 = 1e-5;
+};
+
+// mode 0: value, 1: exact tangent (forward mode), 2: finite difference
+void launch_resid(const Grid& G, const ResidArgs& a, int mode, hipStream_t s);
+// which 0: L (alpha = alpha1), 1: R (alpha = alpha2); mode 0: out = in/S, 1: out = in*S
+void launch_scale_LR(const Grid& G, const double* X, double alpha, int which, const double* in,
+                     double* out, int mode, hipStream_t s);
+
+// ---- deterministic reductions ---------------------------------------------------------
+constexpr int kRedBlocks = 1024;   // maximum blocks of a reduction grid
+constexpr int kMaxK = 72;          // maximum simultaneous sums (Krylov basis size + 1)
+
+struct RedWS {
+  double* part = nullptr;          // kRedBlocks * kMaxK partials
+  unsigned int* count = nullptr;   // completion counter (returns to 0 after each use)
+};
+
+template <class T>
+void launch_dot(size_t n, const T* a, const T* b, double* out, const RedWS& w, hipStream_t s);
+// out[k] = sum_i V[k*ld + i] w[i], k < K
+void launch_multidot(size_t n, const double* V, size_t ld, int K, const double* w, double* out,
+                     const RedWS& ws, hipStream_t s);
+// w -= sum_k h[k] V_k; out[k] = V_k . w (k < K); out[K] = ||w||^2
+void launch_cgs2_update_dot(size_t n, const double* V, size_t ld, int K, const double* h, double* w,
+                            double* out, const RedWS& ws, hipStream_t s);
+// dst = w - sum_k h[k] V_k; out[0] = ||dst||^2
+void launch_cgs2_update_norm(size_t n, const double* V, size_t ld, int K, const double* h,
+                             const double* w, double* dst, double* out, const RedWS& ws,
+                             hipStream_t s);
+// dst = src / sqrt(*nrm2)
+void launch_scale_by_inv_sqrt(size_t n, const double* src, const double* nrm2, double* dst,
+                              hipStream_t s);
+// dst = sum_k y[k] Z_k (y on the device)
+void launch_lincomb(size_t n, const double* Z, size_t ld, int K, const double* y, double* dst,
+                    hipStream_t s);
+// y = a x + y, x and y double
+void launch_axpy(size_t n, double a, const double* x, double* y, hipStream_t s);
+void launch_fill(size_t n, double v, double* y, hipStream_t s);
+template <class T>
+void launch_fill_t(size_t n, T v, T* y, hipStream_t s);
+
+// scaled norms of a state-shaped vector: out = sum (V/R(X))^2 ; max |V/R(X)|
+void launch_scaled_norm2(const Grid& G, const double* X, const double* V, double alpha2,
+                         double* out, const RedWS& ws, hipStream_t s);
+void launch_scaled_maxabs(const Grid& G, const double* X, const double* V, double alpha2,
+                          double* out, const RedWS& ws, hipStream_t s);
+// max over cells of |u_c| + c_s (CFL)
+void launch_cfl_speed(const Grid& G, const double* X, double* out, const RedWS& ws, hipStream_t s);
+
+// ---- physics-based preconditioner ------------------------------------------------------
+struct Level {              // one multigrid level of one elliptic operator
+  int n[3];
+  int N;
+  int stride[3];
+  void* diag = nullptr;     // T[N]
+  void* w[3] = {nullptr, nullptr, nullptr};  // T[N] low-face weights per axis
+  void* dinv = nullptr;     // T[N]
+  void* b = nullptr;        // T[N] right-hand side / restricted residual
+  void* x = nullptr;        // T[N] solution
+  void* t1 = nullptr;       // T[N]
+  void* t2 = nullptr;       // T[N]
+};
+
+// pressure (op 0) and thermal (op 1) coefficients on the finest level, FP64
+void launch_ell_coef(const Grid& G, const double* X, double dt, int op, double* diag,
+                     double* const* w, hipStream_t s);
+template <class T>
+void launch_ell_coarsen(const Grid& G, const Level& f, const Level& c, hipStream_t s);
+template <class T>
+void launch_ell_dinv(const Grid& G, const Level& L, hipStream_t s);
+void launch_level_to_f32(const Level& src, const Level& dst, int nd, hipStream_t s);
+
+template <class T>
+void launch_mg_presmooth(const Grid& G, const Level& L, const T* b, T* x, hipStream_t s);
+template <class T>
+void launch_mg_restrict_resid(const Grid& G, const Level& f, const T* b, const T* x, T* bc,
+                              const Level& c, hipStream_t s);
+template <class T>
+void launch_mg_prolong_smooth1(const Grid& G, const Level& f, const T* b, const T* x2, const T* xc,
+                               const Level& c, T* x1, T* d0, hipStream_t s);
+template <class T>
+void launch_mg_smooth2(const Grid& G, const Level& L, const T* b, const T* x1, const T* d0, T* x,
+                       hipStream_t s);
+template <class T>
+void launch_dense_matvec(int n, const double* A, const T* x, T* y, hipStream_t s);
+
+// CG pieces: q = A p and out = p.q ; x += a p, r -= a q and out = r.r ; p = z + b p
+template <class T>
+void launch_ell_apply_dot(const Grid& G, const Level& L, const T* p, T* q, double* out,
+                          const RedWS& ws, hipStream_t s);
+template <class T>
+void launch_cg_update(size_t n, const double* sc, int i_num, int i_den, T* x, const T* p, T* r,
+                      const T* q, double* rr, const RedWS& ws, hipStream_t s);
+template <class T>
+void launch_cg_pupdate(size_t n, const double* sc, int i_num, int i_den, const T* z, T* p,
+                       hipStream_t s);
+// double <-> float with scaling by 1/sqrt(*nrm2) (to float) or sqrt(*nrm2) (back)
+void launch_cast_scale_f32(size_t n, const double* src, const double* nrm2, float* dst, hipStream_t s);
+void launch_uncast_scale_f64(size_t n, const float* src, const double* nrm2, double* dst, hipStream_t s);
+
+// transforms: rhs_p = F_p / (Gamma1 p);  rhs_T = rho F_e + (dp/dt - F_p)/Gamma1;
+// z = dX from dp (and dT).  scaled != 0: the input is v with r = L v.
+void launch_pbp_in(const Grid& G, const double* X, const double* v, int scaled, double alpha1,
+                   double dt, double* rhs_p, hipStream_t s);
+void launch_pbp_rhsT(const Grid& G, const double* X, const double* v, int scaled, double alpha1,
+                     double dt, const double* dp, double* rhs_T, hipStream_t s);
+void launch_pbp_out(const Grid& G, const double* X, const double* v, int scaled, double alpha1,
+                    double dt, const double* dp, const double* dT, double* z, hipStream_t s);
+
+}  // namespace jfnk

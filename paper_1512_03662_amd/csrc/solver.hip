@@ -1,0 +1,864 @@
+// Host side of the implicit-step library: context and workspace, the Newton loop
+// (Sect. 4.1), flexible GMRES(m) with CGS2 (Sects. 4.1, 4.3), the physics-based
+// preconditioner (Sect. 4.3) and its multigrid-preconditioned CG solves (Sect. 3.5), and
+// the C ABI of include/jfnk.h.
+//
+// Control stays on the host; the device is asked only for scalars (norms, Hessenberg
+// columns, CG residuals), so every vector operation runs in the kernels of this library.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/jfnk.h"
+#include "kernels.hpp"
+
+using namespace jfnk;
+
+namespace {
+
+// device scalar slots
+enum Slot {
+  S_XN2 = 0,   // ||R^-1 X||^2   (followed by S_ZN2: the finite-difference kernel reads both)
+  S_ZN2 = 1,   // ||R^-1 Z_j||^2
+  S_FN2 = 2,   // ||L^-1 F||^2
+  S_DXMAX = 3, // ||R^-1 dX||_inf
+  S_BN2 = 4,   // ||b||^2 of an elliptic solve
+  S_PQ = 5,
+  S_RR = 6,
+  S_RZ0 = 7,
+  S_RZ1 = 8,
+  S_TMP = 9,
+  S_H1 = 16,                       // h of the first Gram-Schmidt pass (kMaxK)
+  S_H2 = S_H1 + kMaxK,             // h of the second pass (kMaxK) then ||w||^2
+  S_NRM3 = S_H2 + kMaxK + 1,       // ||w||^2 after the second pass
+  S_Y = S_NRM3 + 1,                // least-squares coefficients y (kMaxK)
+  S_COUNT = S_Y + kMaxK
+};
+
+struct EllOp {
+  std::vector<Level> lv64, lv32;
+  double* Ainv = nullptr;   // dense inverse of the coarsest level
+  int Nc = 0;
+  std::vector<double> hA;   // host scratch
+};
+
+}  // namespace
+
+struct jfnk_ctx {
+  jfnk_problem prob{};
+  jfnk_opts opts{};
+  Grid G{};
+  hipStream_t stream = nullptr;
+  int nvar = 0;
+  size_t n = 0;          // nvar * N
+  int m_alloc = 0;
+  double dt = 0.0;
+  bool have_state = false;
+  std::string err;
+  size_t bytes = 0;
+  std::vector<void*> allocs;
+
+  // state-sized buffers
+  double *bn = nullptr, *Xn = nullptr, *F = nullptr, *G0 = nullptr, *W = nullptr, *W2 = nullptr,
+         *dX = nullptr, *Xk = nullptr, *V = nullptr, *Z = nullptr;
+  double* scal = nullptr;   // device scalars
+  double* hscal = nullptr;  // pinned host mirror
+  RedWS red;
+
+  // preconditioner
+  EllOp ops[2];
+  double *rhs_p = nullptr, *dp = nullptr, *rhs_T = nullptr, *dT = nullptr;
+  double *cg64[4] = {nullptr, nullptr, nullptr, nullptr};  // r, p, q, z
+  float *cg32[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // r p q z b x
+  int cg_its = 0;
+};
+
+static std::string g_create_err;
+
+#define HIPX(expr)                                                                     \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      throw DevErr(std::string(#expr) + ": " + hipGetErrorString(e_));               \
+    }                                                                                  \
+  } while (0)
+
+namespace {
+
+struct DevErr {
+  std::string msg;
+  explicit DevErr(std::string m) : msg(std::move(m)) {}
+};
+struct InvErr {
+  std::string msg;
+  explicit InvErr(std::string m) : msg(std::move(m)) {}
+};
+struct FiniteErr {
+  std::string msg;
+  explicit FiniteErr(std::string m) : msg(std::move(m)) {}
+};
+
+template <class T>
+T* dalloc(jfnk_ctx* c, size_t count) {
+  void* p = nullptr;
+  size_t b = std::max<size_t>(count, 1) * sizeof(T);
+  HIPX(hipMalloc(&p, b));
+  c->allocs.push_back(p);
+  c->bytes += b;
+  return (T*)p;
+}
+
+void check_launch() { HIPX(hipGetLastError()); }
+
+void sync(jfnk_ctx* c) { HIPX(hipStreamSynchronize(c->stream)); }
+
+// copy device scalars [first, first+count) to the host mirror and wait
+void pull(jfnk_ctx* c, int first, int count) {
+  check_launch();
+  HIPX(hipMemcpyAsync(c->hscal + first, c->scal + first, count * sizeof(double),
+                      hipMemcpyDeviceToHost, c->stream));
+  sync(c);
+}
+
+void push(jfnk_ctx* c, int first, int count) {
+  HIPX(hipMemcpyAsync(c->scal + first, c->hscal + first, count * sizeof(double),
+                      hipMemcpyHostToDevice, c->stream));
+}
+
+void copy_d2d(jfnk_ctx* c, void* dst, const void* src, size_t bytes) {
+  HIPX(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->stream));
+}
+
+Grid make_grid(const jfnk_problem& p) {
+  Grid G{};
+  G.nd = p.ndim;
+  for (int d = 0; d < 3; ++d) {
+    G.n[d] = (d < p.ndim) ? p.n[d] : 1;
+    G.bc[d] = (d < p.ndim) ? p.bc[d] : 0;
+    G.dx[d] = (d < p.ndim) ? p.dx[d] : 1.0;
+    G.idx[d] = 1.0 / G.dx[d];
+    G.g[d] = (d < p.ndim) ? p.g[d] : 0.0;
+    G.qwall[d][0] = p.qwall[d][0];
+    G.qwall[d][1] = p.qwall[d][1];
+  }
+  G.stride[0] = 1;
+  G.stride[1] = G.n[0];
+  G.stride[2] = G.n[0] * G.n[1];
+  G.N = G.n[0] * G.n[1] * G.n[2];
+  G.gamma = p.gamma;
+  G.chi_model = p.chi_model;
+  G.chi0 = p.chi0;
+  G.chi_tref_inv = 1.0 / p.chi_tref;
+  G.chi_exp = p.chi_exp;
+  G.theta = p.theta;
+  return G;
+}
+
+void validate(const jfnk_problem* p, const jfnk_opts* o) {
+  if (!p || !o) throw InvErr("null problem or options");
+  if (p->ndim != 2 && p->ndim != 3) throw InvErr("ndim must be 2 or 3");
+  double cells = 1.0;
+  for (int d = 0; d < p->ndim; ++d) {
+    if (p->n[d] < 4) throw InvErr("every axis needs at least 4 cells");
+    if (!(p->dx[d] > 0.0)) throw InvErr("dx must be positive");
+    if (p->bc[d] != JFNK_BC_PERIODIC && p->bc[d] != JFNK_BC_WALL) throw InvErr("bad bc");
+    cells *= p->n[d];
+  }
+  if (p->ndim == 2 && p->n[2] != 1) throw InvErr("n[2] must be 1 in 2D");
+  if (cells * (2 + p->ndim) > 2.0e9) throw InvErr("grid too large for 32-bit cell indexing");
+  if (!(p->gamma > 1.0)) throw InvErr("gamma must exceed 1");
+  if (p->chi_model < 0 || p->chi_model > 2) throw InvErr("bad chi_model");
+  if (p->chi_model != JFNK_CHI_NONE && !(p->chi0 >= 0.0)) throw InvErr("chi0 must be >= 0");
+  if (p->chi_model == JFNK_CHI_POWER && !(p->chi_tref > 0.0)) throw InvErr("chi_tref must be > 0");
+  if (!(p->theta > 0.0 && p->theta <= 1.0)) throw InvErr("theta must be in (0, 1]");
+  if (o->gmres_m < 1 || o->gmres_m > kMaxK - 2) throw InvErr("gmres_m out of range");
+  if (o->gmres_maxit < 1) throw InvErr("gmres_maxit must be >= 1");
+  if (o->newton_max < 1 || o->newton_min < 1) throw InvErr("newton_max/newton_min must be >= 1");
+  if (o->jv_mode != JFNK_JV_FD && o->jv_mode != JFNK_JV_EXACT) throw InvErr("bad jv_mode");
+  if (o->precond < 0 || o->precond > 2) throw InvErr("bad precond");
+  if (o->ell_precision != JFNK_FP64 && o->ell_precision != JFNK_FP32) throw InvErr("bad ell_precision");
+  if (o->cg_maxit < 1) throw InvErr("cg_maxit must be >= 1");
+}
+
+// ---- multigrid hierarchy ----------------------------------------------------------------
+bool coarsenable(const int* n, int nd) {
+  for (int d = 0; d < nd; ++d)
+    if (n[d] % 2 != 0 || n[d] <= 4) return false;
+  return true;
+}
+
+Level make_level(jfnk_ctx* c, const int* n, int nd, bool f32, bool level0) {
+  Level L;
+  for (int d = 0; d < 3; ++d) L.n[d] = (d < nd) ? n[d] : 1;
+  L.stride[0] = 1;
+  L.stride[1] = L.n[0];
+  L.stride[2] = L.n[0] * L.n[1];
+  L.N = L.n[0] * L.n[1] * L.n[2];
+  size_t es = f32 ? sizeof(float) : sizeof(double);
+  auto al = [&](void) -> void* {
+    void* p = nullptr;
+    HIPX(hipMalloc(&p, std::max<size_t>(L.N, 1) * es));
+    c->allocs.push_back(p);
+    c->bytes += L.N * es;
+    return p;
+  };
+  L.diag = al();
+  for (int d = 0; d < nd; ++d) L.w[d] = al();
+  L.dinv = al();
+  if (!level0) {
+    L.b = al();
+    L.x = al();
+  }
+  L.t1 = al();
+  L.t2 = al();
+  return L;
+}
+
+void build_hierarchy(jfnk_ctx* c, EllOp& op, bool want32) {
+  const Grid& G = c->G;
+  int n[3] = {G.n[0], G.n[1], G.n[2]};
+  op.lv64.push_back(make_level(c, n, G.nd, false, true));
+  if (want32) op.lv32.push_back(make_level(c, n, G.nd, true, true));
+  while (coarsenable(n, G.nd)) {
+    for (int d = 0; d < G.nd; ++d) n[d] /= 2;
+    op.lv64.push_back(make_level(c, n, G.nd, false, false));
+    if (want32) op.lv32.push_back(make_level(c, n, G.nd, true, false));
+  }
+  op.Nc = op.lv64.back().N;
+  if (op.Nc > 4096) throw InvErr("coarsest multigrid level too large (grid sizes need factors of 2)");
+  op.Ainv = dalloc<double>(c, (size_t)op.Nc * op.Nc);
+  op.hA.resize((size_t)op.Nc * op.Nc);
+}
+
+// dense inverse of the SPD coarsest operator (Cholesky), built on the host from the
+// level's coefficients
+void coarse_setup(jfnk_ctx* c, EllOp& op) {
+  const Grid& G = c->G;
+  const Level& L = op.lv64.back();
+  int N = L.N;
+  std::vector<double> diag(N), w[3];
+  HIPX(hipMemcpyAsync(diag.data(), L.diag, N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  for (int d = 0; d < G.nd; ++d) {
+    w[d].resize(N);
+    HIPX(hipMemcpyAsync(w[d].data(), L.w[d], N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  }
+  sync(c);
+  std::vector<double>& A = op.hA;
+  std::fill(A.begin(), A.end(), 0.0);
+  for (int lin = 0; lin < N; ++lin) {
+    A[(size_t)lin * N + lin] += diag[lin];
+    int cc[3] = {lin % L.n[0], (lin / L.n[0]) % L.n[1], lin / (L.n[0] * L.n[1])};
+    for (int d = 0; d < G.nd; ++d) {
+      int nd_ = L.n[d];
+      int m = (cc[d] == 0) ? lin + (nd_ - 1) * L.stride[d] : lin - L.stride[d];
+      double wf = w[d][lin];
+      A[(size_t)lin * N + lin] += wf;
+      A[(size_t)m * N + m] += wf;
+      A[(size_t)lin * N + m] -= wf;
+      A[(size_t)m * N + lin] -= wf;
+    }
+  }
+  // Cholesky A = C C^T (lower), then A^-1 = C^-T C^-1
+  std::vector<double> C(A);
+  for (int j = 0; j < N; ++j) {
+    double s = C[(size_t)j * N + j];
+    for (int k = 0; k < j; ++k) s -= C[(size_t)j * N + k] * C[(size_t)j * N + k];
+    if (!(s > 0.0)) throw FiniteErr("coarse multigrid operator is not positive definite");
+    double djj = std::sqrt(s);
+    C[(size_t)j * N + j] = djj;
+    for (int i = j + 1; i < N; ++i) {
+      double t = C[(size_t)i * N + j];
+      for (int k = 0; k < j; ++k) t -= C[(size_t)i * N + k] * C[(size_t)j * N + k];
+      C[(size_t)i * N + j] = t / djj;
+    }
+  }
+  // columns of C^-1 by forward substitution, then A^-1 = C^-T C^-1
+  std::vector<double> Ci((size_t)N * N, 0.0);
+  for (int col = 0; col < N; ++col) {
+    for (int i = 0; i < N; ++i) {
+      double t = (i == col) ? 1.0 : 0.0;
+      for (int k = col; k < i; ++k) t -= C[(size_t)i * N + k] * Ci[(size_t)k * N + col];
+      Ci[(size_t)i * N + col] = (i < col) ? 0.0 : t / C[(size_t)i * N + i];
+    }
+  }
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      double s = 0.0;
+      for (int k = std::max(i, j); k < N; ++k) s += Ci[(size_t)k * N + i] * Ci[(size_t)k * N + j];
+      A[(size_t)i * N + j] = s;
+    }
+  HIPX(hipMemcpyAsync(op.Ainv, A.data(), (size_t)N * N * sizeof(double), hipMemcpyHostToDevice,
+                      c->stream));
+  sync(c);  // the host buffer is reused
+}
+
+void ell_setup(jfnk_ctx* c, const double* X, double dt) {
+  const Grid& G = c->G;
+  int nops = (c->opts.precond == JFNK_PC_SOUND_THERMAL) ? 2 : 1;
+  for (int o = 0; o < nops; ++o) {
+    EllOp& op = c->ops[o];
+    Level& L0 = op.lv64[0];
+    double* w[3] = {(double*)L0.w[0], (double*)L0.w[1], (double*)L0.w[2]};
+    launch_ell_coef(G, X, dt, o, (double*)L0.diag, w, c->stream);
+    for (size_t l = 0; l + 1 < op.lv64.size(); ++l)
+      launch_ell_coarsen<double>(G, op.lv64[l], op.lv64[l + 1], c->stream);
+    for (auto& L : op.lv64) launch_ell_dinv<double>(G, L, c->stream);
+    if (c->opts.ell_precision == JFNK_FP32)
+      for (size_t l = 0; l < op.lv64.size(); ++l) launch_level_to_f32(op.lv64[l], op.lv32[l], G.nd, c->stream);
+    check_launch();
+    coarse_setup(c, op);
+  }
+}
+
+template <class T>
+void vcycle(jfnk_ctx* c, std::vector<Level>& lv, const double* Ainv, const T* r, T* z) {
+  const Grid& G = c->G;
+  hipStream_t s = c->stream;
+  int nl = (int)lv.size();
+  auto B = [&](int l) -> const T* { return l == 0 ? r : (const T*)lv[l].b; };
+  auto Xl = [&](int l) -> T* { return l == 0 ? z : (T*)lv[l].x; };
+  for (int l = 0; l + 1 < nl; ++l) {
+    launch_mg_presmooth<T>(G, lv[l], B(l), Xl(l), s);
+    launch_mg_restrict_resid<T>(G, lv[l], B(l), Xl(l), (T*)lv[l + 1].b, lv[l + 1], s);
+  }
+  launch_dense_matvec<T>(lv[nl - 1].N, Ainv, B(nl - 1), Xl(nl - 1), s);
+  for (int l = nl - 2; l >= 0; --l) {
+    launch_mg_prolong_smooth1<T>(G, lv[l], B(l), Xl(l), Xl(l + 1), lv[l + 1], (T*)lv[l].t1,
+                                 (T*)lv[l].t2, s);
+    launch_mg_smooth2<T>(G, lv[l], B(l), (const T*)lv[l].t1, (const T*)lv[l].t2, Xl(l), s);
+  }
+}
+
+// PCG on level 0 of lv: x = A^-1 b (x and b of type T, length N).  bn2 slot holds ||b||^2.
+template <class T>
+int pcg(jfnk_ctx* c, std::vector<Level>& lv, const double* Ainv, const T* b, T* x, T* const* v) {
+  const Grid& G = c->G;
+  hipStream_t s = c->stream;
+  size_t N = (size_t)G.N;
+  T *r = v[0], *p = v[1], *q = v[2], *z = v[3];
+  launch_fill_t<T>(N, T(0), x, s);
+  copy_d2d(c, r, b, N * sizeof(T));
+  launch_dot<T>(N, b, b, c->scal + S_BN2, c->red, s);
+  vcycle<T>(c, lv, Ainv, r, z);
+  launch_dot<T>(N, r, z, c->scal + S_RZ0, c->red, s);
+  copy_d2d(c, p, z, N * sizeof(T));
+  pull(c, S_BN2, 1);
+  const double bn = std::sqrt(c->hscal[S_BN2]);
+  if (!std::isfinite(bn)) throw FiniteErr("non-finite right-hand side in an elliptic solve");
+  if (bn == 0.0) return 0;
+  int cur = S_RZ0, nxt = S_RZ1;
+  int it = 0;
+  for (it = 1; it <= c->opts.cg_maxit; ++it) {
+    launch_ell_apply_dot<T>(G, lv[0], p, q, c->scal + S_PQ, c->red, s);
+    launch_cg_update<T>(N, c->scal, cur, S_PQ, x, p, r, q, c->scal + S_RR, c->red, s);
+    pull(c, S_RR, 1);
+    double rn = std::sqrt(c->hscal[S_RR]);
+    if (!std::isfinite(rn)) throw FiniteErr("non-finite residual in an elliptic solve");
+    if (rn < c->opts.cg_eta * bn) break;
+    if (it == c->opts.cg_maxit) break;
+    vcycle<T>(c, lv, Ainv, r, z);
+    launch_dot<T>(N, r, z, c->scal + nxt, c->red, s);
+    launch_cg_pupdate<T>(N, c->scal, nxt, cur, z, p, s);
+    std::swap(cur, nxt);
+  }
+  return std::min(it, c->opts.cg_maxit);
+}
+
+// x = A_op^-1 b in the configured precision (FP32: b normalised by ||b|| before the cast)
+void ell_solve(jfnk_ctx* c, int o, const double* b, double* x) {
+  EllOp& op = c->ops[o];
+  size_t N = (size_t)c->G.N;
+  if (c->opts.ell_precision == JFNK_FP64) {
+    c->cg_its += pcg<double>(c, op.lv64, op.Ainv, b, x, c->cg64);
+  } else {
+    launch_dot<double>(N, b, b, c->scal + S_TMP, c->red, c->stream);
+    pull(c, S_TMP, 1);
+    if (c->hscal[S_TMP] == 0.0) {
+      launch_fill(N, 0.0, x, c->stream);
+      return;
+    }
+    float* b32 = c->cg32[4];
+    float* x32 = c->cg32[5];
+    launch_cast_scale_f32(N, b, c->scal + S_TMP, b32, c->stream);
+    // keep ||b|| for the way back: S_TMP is reused by pcg only through S_BN2
+    c->cg_its += pcg<float>(c, op.lv32, op.Ainv, b32, x32, c->cg32);
+    launch_uncast_scale_f64(N, x32, c->scal + S_TMP, x, c->stream);
+  }
+}
+
+// Z = M^-1 v (scaled = 1: v is a scaled basis vector, r = L v) at the frozen state X
+void precond(jfnk_ctx* c, const double* X, const double* v, int scaled, double* z) {
+  const Grid& G = c->G;
+  hipStream_t s = c->stream;
+  const jfnk_opts& o = c->opts;
+  if (o.precond == JFNK_PC_NONE) {
+    if (scaled) launch_scale_LR(G, X, o.alpha2, 1, v, z, 1, s);
+    else copy_d2d(c, z, v, c->n * sizeof(double));
+    return;
+  }
+  launch_pbp_in(G, X, v, scaled, o.alpha1, c->dt, c->rhs_p, s);
+  ell_solve(c, 0, c->rhs_p, c->dp);
+  const double* dT = nullptr;
+  if (o.precond == JFNK_PC_SOUND_THERMAL) {
+    launch_pbp_rhsT(G, X, v, scaled, o.alpha1, c->dt, c->dp, c->rhs_T, s);
+    ell_solve(c, 1, c->rhs_T, c->dT);
+    dT = c->dT;
+  }
+  launch_pbp_out(G, X, v, scaled, o.alpha1, c->dt, c->dp, dT, z, s);
+  check_launch();
+}
+
+// out = L^-1 J z at X (scaled operator of eq. jacobian_system_norm applied to an unscaled z)
+void apply_J(jfnk_ctx* c, const double* X, const double* z, double* out) {
+  const Grid& G = c->G;
+  ResidArgs a;
+  a.X = X;
+  a.V = z;
+  a.out = out;
+  a.cU = 1.0 / c->dt;
+  a.cR = -c->prob.theta;
+  a.scaleL = 1;
+  a.alpha1 = c->opts.alpha1;
+  if (c->opts.jv_mode == JFNK_JV_EXACT) {
+    launch_resid(G, a, 1, c->stream);
+  } else {
+    launch_scaled_norm2(G, X, z, c->opts.alpha2, c->scal + S_ZN2, c->red, c->stream);
+    a.B = c->G0;
+    a.fd_norms = c->scal + S_XN2;
+    a.fd_lambda = c->opts.fd_lambda;
+    launch_resid(G, a, 2, c->stream);
+  }
+}
+
+struct GmresOut {
+  int iters = 0;
+  bool converged = false;
+};
+
+// Flexible GMRES(m) on (L^-1 J R) y = rhs with rhs = -L^-1 F (in W), right-preconditioned;
+// the directions Z_j are unscaled state increments, so dX = sum_j y_j Z_j.
+GmresOut fgmres(jfnk_ctx* c, const double* X, double beta0) {
+  const jfnk_opts& o = c->opts;
+  hipStream_t s = c->stream;
+  const size_t n = c->n;
+  const int m = o.gmres_m;
+  GmresOut out;
+  const double target = o.gmres_eta * beta0;
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  auto Hx = [&](int i, int j) -> double& { return H[(size_t)i * m + j]; };
+  launch_fill(n, 0.0, c->dX, s);
+  bool first = true;
+  while (out.iters < o.gmres_maxit) {
+    double beta;
+    if (first) {
+      beta = beta0;
+      // V_0 = -W / beta
+      launch_fill(n, 0.0, c->V, s);
+      launch_axpy(n, -1.0 / beta, c->W, c->V, s);
+    } else {
+      // r = -L^-1 F - L^-1 J dX
+      apply_J(c, X, c->dX, c->W2);
+      launch_fill(n, 0.0, c->V, s);
+      launch_axpy(n, -1.0, c->W, c->V, s);
+      launch_axpy(n, -1.0, c->W2, c->V, s);
+      launch_dot<double>(n, c->V, c->V, c->scal + S_TMP, c->red, s);
+      pull(c, S_TMP, 1);
+      beta = std::sqrt(c->hscal[S_TMP]);
+      if (!std::isfinite(beta)) throw FiniteErr("non-finite GMRES residual");
+      if (beta < target) {
+        out.converged = true;
+        break;
+      }
+      launch_scale_by_inv_sqrt(n, c->V, c->scal + S_TMP, c->V, s);
+    }
+    first = false;
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int k = 0;
+    double res = beta;
+    for (int j = 0; j < m; ++j) {
+      double* Vj = c->V + (size_t)j * n;
+      double* Zj = c->Z + (size_t)j * n;
+      double* w = c->V + (size_t)(j + 1) * n;
+      precond(c, X, Vj, 1, Zj);
+      apply_J(c, X, Zj, w);
+      const int K = j + 1;
+      launch_multidot(n, c->V, n, K, w, c->scal + S_H1, c->red, s);
+      launch_cgs2_update_dot(n, c->V, n, K, c->scal + S_H1, w, c->scal + S_H2, c->red, s);
+      launch_cgs2_update_norm(n, c->V, n, K, c->scal + S_H2, w, w, c->scal + S_NRM3, c->red, s);
+      pull(c, S_H1, S_NRM3 + 1 - S_H1);
+      double hn2 = c->hscal[S_NRM3];
+      if (!std::isfinite(hn2)) throw FiniteErr("non-finite Arnoldi vector");
+      double hn = std::sqrt(hn2);
+      for (int i = 0; i < K; ++i) Hx(i, j) = c->hscal[S_H1 + i] + c->hscal[S_H2 + i];
+      Hx(j + 1, j) = hn;
+      if (hn > 0.0) launch_scale_by_inv_sqrt(n, w, c->scal + S_NRM3, w, s);
+      for (int i = 0; i < j; ++i) {
+        double t = cs[i] * Hx(i, j) + sn[i] * Hx(i + 1, j);
+        Hx(i + 1, j) = -sn[i] * Hx(i, j) + cs[i] * Hx(i + 1, j);
+        Hx(i, j) = t;
+      }
+      double a = Hx(j, j), b = Hx(j + 1, j);
+      if (b == 0.0) {
+        cs[j] = 1.0;
+        sn[j] = 0.0;
+      } else {
+        double r = std::hypot(a, b);
+        cs[j] = a / r;
+        sn[j] = b / r;
+      }
+      Hx(j, j) = cs[j] * a + sn[j] * b;
+      Hx(j + 1, j) = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      res = std::fabs(g[j + 1]);
+      out.iters++;
+      k = j + 1;
+      if (hn == 0.0 || res < target || out.iters >= o.gmres_maxit) break;
+    }
+    for (int i = k - 1; i >= 0; --i) {
+      double t = g[i];
+      for (int l = i + 1; l < k; ++l) t -= Hx(i, l) * y[l];
+      y[i] = t / Hx(i, i);
+    }
+    for (int i = 0; i < k; ++i) c->hscal[S_Y + i] = y[i];
+    push(c, S_Y, k);
+    launch_lincomb(n, c->Z, n, k, c->scal + S_Y, c->W2, s);
+    launch_axpy(n, 1.0, c->W2, c->dX, s);
+    check_launch();
+    if (res < target) {
+      out.converged = true;
+      break;
+    }
+  }
+  return out;
+}
+
+void set_state(jfnk_ctx* c, const double* Xn, double dt) {
+  if (!(dt > 0.0)) throw InvErr("dt must be positive");
+  c->dt = dt;
+  copy_d2d(c, c->Xn, Xn, c->n * sizeof(double));
+  ResidArgs a;
+  a.X = c->Xn;
+  a.out = c->bn;
+  a.cU = 1.0 / dt;
+  a.cR = 1.0 - c->prob.theta;
+  launch_resid(c->G, a, 0, c->stream);
+  check_launch();
+  c->have_state = true;
+}
+
+int implicit_step(jfnk_ctx* c, double* X, double dt, jfnk_step_stats* st) {
+  const jfnk_opts& o = c->opts;
+  const Grid& G = c->G;
+  hipStream_t s = c->stream;
+  jfnk_step_stats S{};
+  S.dt = dt;
+  set_state(c, X, dt);
+  c->cg_its = 0;
+  int status = JFNK_E_NEWTON_NOCONV;
+  for (int k = 0; k < o.newton_max; ++k) {
+    // W = L^-1 F(X), G0 = U/dt - theta R
+    ResidArgs a;
+    a.X = X;
+    a.B = c->bn;
+    a.out = c->W;
+    a.G0 = c->G0;
+    a.cU = 1.0 / dt;
+    a.cR = -c->prob.theta;
+    a.scaleL = 1;
+    a.alpha1 = o.alpha1;
+    launch_resid(G, a, 0, s);
+    launch_dot<double>(c->n, c->W, c->W, c->scal + S_FN2, c->red, s);
+    if (o.jv_mode == JFNK_JV_FD) launch_scaled_norm2(G, X, X, o.alpha2, c->scal + S_XN2, c->red, s);
+    pull(c, S_FN2, 1);
+    double fn = std::sqrt(c->hscal[S_FN2]);
+    if (!std::isfinite(fn)) throw FiniteErr("non-finite residual norm");
+    if (k == 0) S.f0_norm = fn;
+    S.f_norm = fn;
+    double dxmax = 0.0;
+    if (fn > 0.0) {
+      if (o.precond != JFNK_PC_NONE) ell_setup(c, X, dt);
+      GmresOut go = fgmres(c, X, fn);
+      S.gmres_its += go.iters;
+      launch_scaled_maxabs(G, X, c->dX, o.alpha2, c->scal + S_DXMAX, c->red, s);
+      launch_axpy(c->n, 1.0, c->dX, X, s);
+      pull(c, S_DXMAX, 1);
+      dxmax = c->hscal[S_DXMAX];
+      if (!std::isfinite(dxmax)) throw FiniteErr("non-finite Newton correction");
+    }
+    S.newton_its = k + 1;
+    S.last_dx_norm = dxmax;
+    if (dxmax < o.newton_tol && k + 1 >= o.newton_min) {
+      S.converged = 1;
+      status = JFNK_OK;
+      break;
+    }
+  }
+  S.cg_its = c->cg_its;
+  if (st) *st = S;
+  if (status != JFNK_OK) c->err = "Newton did not converge within newton_max iterations";
+  return status;
+}
+
+void destroy_bufs(jfnk_ctx* c) {
+  for (void* p : c->allocs) (void)hipFree(p);
+  c->allocs.clear();
+  if (c->hscal) (void)hipHostFree(c->hscal);
+  c->hscal = nullptr;
+}
+
+void create(jfnk_ctx* c) {
+  const Grid& G = c->G;
+  c->nvar = 2 + G.nd;
+  c->n = (size_t)c->nvar * G.N;
+  c->m_alloc = c->opts.gmres_m;
+  size_t n = c->n;
+  c->bn = dalloc<double>(c, n);
+  c->Xn = dalloc<double>(c, n);
+  c->F = dalloc<double>(c, n);
+  c->G0 = dalloc<double>(c, n);
+  c->W = dalloc<double>(c, n);
+  c->W2 = dalloc<double>(c, n);
+  c->dX = dalloc<double>(c, n);
+  c->Xk = dalloc<double>(c, n);
+  c->V = dalloc<double>(c, n * (c->m_alloc + 1));
+  c->Z = dalloc<double>(c, n * c->m_alloc);
+  c->scal = dalloc<double>(c, S_COUNT);
+  HIPX(hipHostMalloc((void**)&c->hscal, S_COUNT * sizeof(double), hipHostMallocDefault));
+  std::memset(c->hscal, 0, S_COUNT * sizeof(double));
+  c->red.part = dalloc<double>(c, (size_t)kRedBlocks * kMaxK);
+  c->red.count = dalloc<unsigned int>(c, 1);
+  HIPX(hipMemsetAsync(c->red.count, 0, sizeof(unsigned int), c->stream));
+  HIPX(hipMemsetAsync(c->scal, 0, S_COUNT * sizeof(double), c->stream));
+  size_t N = (size_t)G.N;
+  c->rhs_p = dalloc<double>(c, N);
+  c->dp = dalloc<double>(c, N);
+  c->rhs_T = dalloc<double>(c, N);
+  c->dT = dalloc<double>(c, N);
+  for (int i = 0; i < 4; ++i) c->cg64[i] = dalloc<double>(c, N);
+  bool want32 = true;  // precision may be switched by jfnk_set_opts
+  for (int i = 0; i < 6; ++i) c->cg32[i] = dalloc<float>(c, N);
+  build_hierarchy(c, c->ops[0], want32);
+  build_hierarchy(c, c->ops[1], want32);
+  sync(c);
+}
+
+}  // namespace
+
+// ======================================================================================
+// C ABI
+// ======================================================================================
+#define ABI_BEGIN try {
+#define ABI_END(ctx)                                                             \
+  }                                                                              \
+  catch (const InvErr& e) {                                                      \
+    (ctx)->err = e.msg;                                                          \
+    return JFNK_E_INVALID;                                                       \
+  }                                                                              \
+  catch (const DevErr& e) {                                                      \
+    (ctx)->err = e.msg;                                                          \
+    return JFNK_E_DEVICE;                                                        \
+  }                                                                              \
+  catch (const FiniteErr& e) {                                                   \
+    (ctx)->err = e.msg;                                                          \
+    return JFNK_E_NONFINITE;                                                     \
+  }                                                                              \
+  catch (...) {                                                                  \
+    (ctx)->err = "unexpected host exception";                                    \
+    return JFNK_E_DEVICE;                                                        \
+  }
+
+extern "C" {
+
+void jfnk_default_opts(jfnk_opts* o) {
+  if (!o) return;
+  o->newton_tol = 1e-8;
+  o->newton_max = 20;
+  o->newton_min = 2;
+  o->gmres_m = 30;
+  o->gmres_maxit = 300;
+  o->gmres_eta = 1e-4;
+  o->jv_mode = JFNK_JV_FD;
+  o->fd_lambda = 1e-7;
+  o->alpha1 = 1e-5;
+  o->alpha2 = 1.0;
+  o->precond = JFNK_PC_SOUND;
+  o->ell_precision = JFNK_FP64;
+  o->cg_eta = 1e-4;
+  o->cg_maxit = 50;
+}
+
+int jfnk_create(const jfnk_problem* prob, const jfnk_opts* opts, void* hip_stream, jfnk_ctx** out) {
+  if (!out) return JFNK_E_INVALID;
+  *out = nullptr;
+  jfnk_ctx* c = new (std::nothrow) jfnk_ctx();
+  if (!c) return JFNK_E_DEVICE;
+  try {
+    validate(prob, opts);
+    c->prob = *prob;
+    c->opts = *opts;
+    c->G = make_grid(*prob);
+    c->stream = (hipStream_t)hip_stream;
+    create(c);
+  } catch (const InvErr& e) {
+    g_create_err = e.msg;
+    destroy_bufs(c);
+    delete c;
+    return JFNK_E_INVALID;
+  } catch (const DevErr& e) {
+    g_create_err = e.msg;
+    destroy_bufs(c);
+    delete c;
+    return JFNK_E_DEVICE;
+  } catch (...) {
+    g_create_err = "unexpected host exception";
+    destroy_bufs(c);
+    delete c;
+    return JFNK_E_DEVICE;
+  }
+  *out = c;
+  return JFNK_OK;
+}
+
+int jfnk_destroy(jfnk_ctx* c) {
+  if (!c) return JFNK_E_INVALID;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  destroy_bufs(c);
+  delete c;
+  return JFNK_OK;
+}
+
+int jfnk_set_opts(jfnk_ctx* c, const jfnk_opts* o) {
+  if (!c) return JFNK_E_INVALID;
+  ABI_BEGIN
+  validate(&c->prob, o);
+  if (o->gmres_m > c->m_alloc) throw InvErr("gmres_m exceeds the restart length the context was created with");
+  c->opts = *o;
+  return JFNK_OK;
+  ABI_END(c)
+}
+
+size_t jfnk_workspace_bytes(const jfnk_ctx* c) { return c ? c->bytes : 0; }
+
+const char* jfnk_last_error(const jfnk_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+int jfnk_set_state_n(jfnk_ctx* c, const double* Xn, double dt) {
+  if (!c) return JFNK_E_INVALID;
+  ABI_BEGIN
+  if (!Xn) throw InvErr("null X^n");
+  set_state(c, Xn, dt);
+  return JFNK_OK;
+  ABI_END(c)
+}
+
+int jfnk_residual(jfnk_ctx* c, const double* X, double* F) {
+  if (!c) return JFNK_E_INVALID;
+  ABI_BEGIN
+  if (!X || !F) throw InvErr("null array");
+  if (!c->have_state) throw InvErr("jfnk_set_state_n must be called first");
+  ResidArgs a;
+  a.X = X;
+  a.B = c->bn;
+  a.out = F;
+  a.cU = 1.0 / c->dt;
+  a.cR = -c->prob.theta;
+  launch_resid(c->G, a, 0, c->stream);
+  check_launch();
+  return JFNK_OK;
+  ABI_END(c)
+}
+
+int jfnk_jvp(jfnk_ctx* c, const double* X, const double* v, double* Jv, int32_t mode) {
+  if (!c) return JFNK_E_INVALID;
+  ABI_BEGIN
+  if (!X || !v || !Jv) throw InvErr("null array");
+  if (!c->have_state) throw InvErr("jfnk_set_state_n must be called first");
+  ResidArgs a;
+  a.X = X;
+  a.V = v;
+  a.out = Jv;
+  a.cU = 1.0 / c->dt;
+  a.cR = -c->prob.theta;
+  if (mode == JFNK_JV_EXACT) {
+    launch_resid(c->G, a, 1, c->stream);
+  } else if (mode == JFNK_JV_FD) {
+    ResidArgs g;
+    g.X = X;
+    g.out = c->G0;
+    g.cU = a.cU;
+    g.cR = a.cR;
+    launch_resid(c->G, g, 0, c->stream);  // G0 = U/dt - theta R at X
+    launch_scaled_norm2(c->G, X, X, c->opts.alpha2, c->scal + S_XN2, c->red, c->stream);
+    launch_scaled_norm2(c->G, X, v, c->opts.alpha2, c->scal + S_ZN2, c->red, c->stream);
+    a.B = c->G0;
+    a.fd_norms = c->scal + S_XN2;
+    a.fd_lambda = c->opts.fd_lambda;
+    launch_resid(c->G, a, 2, c->stream);
+  } else {
+    throw InvErr("bad mode");
+  }
+  check_launch();
+  return JFNK_OK;
+  ABI_END(c)
+}
+
+int jfnk_precond_apply(jfnk_ctx* c, const double* X, const double* r, double* z) {
+  if (!c) return JFNK_E_INVALID;
+  ABI_BEGIN
+  if (!X || !r || !z) throw InvErr("null array");
+  if (!c->have_state) throw InvErr("jfnk_set_state_n must be called first");
+  c->cg_its = 0;
+  if (c->opts.precond != JFNK_PC_NONE) ell_setup(c, X, c->dt);
+  precond(c, X, r, 0, z);
+  sync(c);
+  return JFNK_OK;
+  ABI_END(c)
+}
+
+int jfnk_implicit_step(jfnk_ctx* c, double* X, double dt, jfnk_step_stats* st) {
+  if (!c) return JFNK_E_INVALID;
+  ABI_BEGIN
+  if (!X) throw InvErr("null X");
+  int r = implicit_step(c, X, dt, st);
+  sync(c);
+  return r;
+  ABI_END(c)
+}
+
+double jfnk_cfl_dt(jfnk_ctx* c, const double* X, double cfl) {
+  if (!c || !X || !(cfl > 0.0)) return -1.0;
+  try {
+    launch_cfl_speed(c->G, X, c->scal + S_TMP, c->red, c->stream);
+    pull(c, S_TMP, 1);
+    double hmin = c->G.dx[0];
+    for (int d = 1; d < c->G.nd; ++d) hmin = std::min(hmin, c->G.dx[d]);
+    return cfl * hmin / c->hscal[S_TMP];
+  } catch (const DevErr& e) {
+    c->err = e.msg;
+    return -1.0;
+  }
+}
+
+int jfnk_vjp(jfnk_ctx* c, const double*, const double*, double*) {
+  if (c) c->err = "not built yet";
+  return JFNK_E_INVALID;
+}
+int jfnk_vjp_prev(jfnk_ctx* c, const double*, const double*, double*) {
+  if (c) c->err = "not built yet";
+  return JFNK_E_INVALID;
+}
+int jfnk_adjoint_step(jfnk_ctx* c, const double*, const double*, double, const double*, double*,
+                      jfnk_step_stats*) {
+  if (c) c->err = "not built yet";
+  return JFNK_E_INVALID;
+}
+
+}  // extern "C"
+

@@ -1,0 +1,71 @@
+"""The C-ABI library loads, exports every function the header declares, lays out its structs
+as the binding does, and defaults to the parameter values the paper prints (no GPU needed)."""
+import ctypes as C
+import json
+import os
+import subprocess
+
+import pytest
+
+from paper_1512_03662_amd import _native as N
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_header_function():
+    lib = N.lib()
+    names = N.header_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(N.SIGNATURES)
+
+
+def test_struct_layout_matches_c(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "jfnk.h"\n'
+        "int main(void){\n"
+        'printf("%zu %zu %zu\\n", sizeof(jfnk_problem), sizeof(jfnk_opts), sizeof(jfnk_step_stats));\n'
+        'printf("%zu %zu %zu\\n", offsetof(jfnk_problem, qwall), offsetof(jfnk_problem, theta), '
+        "offsetof(jfnk_opts, cg_maxit));\n"
+        'printf("%zu\\n", offsetof(jfnk_step_stats, dt));\n'
+        "return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    vals = list(map(int, out))
+    assert vals[0] == C.sizeof(N.Problem)
+    assert vals[1] == C.sizeof(N.Opts)
+    assert vals[2] == C.sizeof(N.StepStats)
+    assert vals[3] == N.Problem.qwall.offset and vals[4] == N.Problem.theta.offset
+    assert vals[5] == N.Opts.cg_maxit.offset
+    assert vals[6] == N.StepStats.dt.offset
+
+
+def test_defaults_are_the_paper_values():
+    o = N.Opts()
+    N.lib().jfnk_default_opts(C.byref(o))
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "solver_parameters.json")))
+    assert o.fd_lambda == gold["fd_lambda"]["value"]
+    assert o.alpha1 == gold["alpha1"]["value"] and o.alpha2 == gold["alpha2"]["value"]
+    assert o.gmres_eta == gold["gmres_eta"]["value"] and o.cg_eta == gold["cg_eta"]["value"]
+    assert o.gmres_maxit == gold["gmres_maxit"]["value"]
+    assert o.newton_min == gold["newton_min"]["value"]
+    assert o.jv_mode == N.JV_FD and o.precond == N.PC_SOUND and o.ell_precision == N.FP64
+
+
+def test_create_rejects_bad_problem_without_device():
+    """Validation happens before any device call: a bad problem is refused on the host."""
+    lib = N.lib()
+    p = N.Problem()
+    p.ndim = 4
+    o = N.Opts()
+    lib.jfnk_default_opts(C.byref(o))
+    h = C.c_void_p()
+    assert lib.jfnk_create(C.byref(p), C.byref(o), None, C.byref(h)) == N.E_INVALID
+    assert b"ndim" in lib.jfnk_last_error(None)
+    p.ndim = 2
+    p.n[0], p.n[1], p.n[2] = 3, 8, 1
+    assert lib.jfnk_create(C.byref(p), C.byref(o), None, C.byref(h)) == N.E_INVALID
+    assert b"4 cells" in lib.jfnk_last_error(None)

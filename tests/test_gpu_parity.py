@@ -1,0 +1,188 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU FP64 oracle on the same
+seeded inputs.
+
+Tolerances: residual <= 1e-12 of the per-variable scale S_k (S_k = max|U_k|/dt + max|b_k| +
+max of the summed absolute flux terms: F cancels to ~0 in hydrostatic balance, so a
+normwise relative error would be meaningless); exact J.v <= 1e-12 of the same kind of scale;
+finite-difference J.v <= 1e-7 (the F(X + delta v) - F(X) cancellation floor is ~eps/lambda);
+preconditioner with tight inner solves <= 1e-10; converged steps ||R^-1 (X - X*)||_inf <= 1e-8
+against the exact-Newton root of the oracle.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle.residual import Problem, residual_F, rhs_b, residual_R, conserved_U, residual_scale, cfl_dt
+from oracle.jacobian import jvp_cs, jvp_fd
+from oracle.scaling import scaling_LR
+from oracle.pbp import PBP
+from oracle.mg import PCGSolver
+from oracle.newton import exact_step, jfnk_step, Opts, Stats
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _lib():
+    import paper_1512_03662_amd as J
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return J
+
+
+def T(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def H(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+TINY = [
+    ("2d_periodic_6x5", dict(shape=(6, 5), bc=("periodic", "periodic"))),
+    ("2d_walls_5x7", dict(shape=(5, 7), bc=("periodic", "wall"), g=(0.0, -1.5), chi_model="const",
+                          chi0=0.2, qwall=((0, 0), (0.3, -0.1)))),
+    ("3d_walls_4x5x6", dict(shape=(4, 5, 6), bc=("periodic", "periodic", "wall"), g=(0, 0, -1.0),
+                            chi_model="power", chi0=0.1, qwall=((0, 0), (0, 0), (0.2, 0.1)))),
+    ("2d_ragged_37x29", dict(shape=(37, 29), bc=("periodic", "wall"), g=(0.0, -1.0),
+                             chi_model="power", chi0=0.05, qwall=((0, 0), (0.1, 0.2)))),
+    ("3d_ragged_19x11x13", dict(shape=(19, 11, 13), bc=("wall", "periodic", "wall"), g=(0.3, 0, -1.0),
+                                chi_model="const", chi0=0.05, qwall=((0.1, -0.1), (0, 0), (0.2, 0.1)))),
+]
+
+
+def _tiny(name_cfg, seed=7):
+    name, c = name_cfg
+    c = dict(c)
+    pd, X = W.random_state(c.pop("shape"), c.pop("bc"), seed=seed, **c)
+    return pd, X
+
+
+def _sample_err(F_gpu, F_ref, S):
+    return max(np.max(np.abs(F_gpu[k] - F_ref[k])) / S[k] for k in range(F_ref.shape[0]))
+
+
+@pytest.mark.parametrize("case", TINY, ids=[c[0] for c in TINY])
+def test_residual_parity_small(case):
+    J = _lib()
+    pd, X = _tiny(case)
+    P = Problem.from_dict(pd)
+    Xn = X.copy()
+    Xn[0] *= 1.01
+    dt = 0.03
+    b = rhs_b(P, Xn, dt)
+    F = residual_F(P, X, b, dt)
+    S = residual_scale(P, X, b, dt)
+    ctx = J.Context(pd)
+    ctx.set_state_n(T(Xn), dt)
+    Fg = H(ctx.residual(T(X)))
+    assert _sample_err(Fg, F, S) <= 1e-12
+
+
+@pytest.mark.parametrize("case", TINY, ids=[c[0] for c in TINY])
+def test_exact_jvp_parity_small(case):
+    J = _lib()
+    pd, X = _tiny(case, seed=8)
+    P = Problem.from_dict(pd)
+    dt = 0.03
+    b = rhs_b(P, X, dt)
+    v = W.random_vector(X, 9)
+    ref = jvp_cs(P, X, b, dt, v)
+    ctx = J.Context(pd)
+    ctx.set_state_n(T(X), dt)
+    got = H(ctx.jvp(T(X), T(v), mode="exact"))
+    S = residual_scale(P, X, b, dt)  # J v of a unit-size direction has the residual's scale
+    assert _sample_err(got, ref, S) <= 1e-12
+
+
+@pytest.mark.parametrize("case", TINY[:3], ids=[c[0] for c in TINY[:3]])
+def test_fd_jvp_parity_small(case):
+    J = _lib()
+    pd, X = _tiny(case, seed=10)
+    P = Problem.from_dict(pd)
+    dt = 0.03
+    b = rhs_b(P, X, dt)
+    v = W.random_vector(X, 11)
+    ref = jvp_fd(P, X, b, dt, v, lam=1e-7)
+    ctx = J.Context(pd)
+    ctx.set_state_n(T(X), dt)
+    got = H(ctx.jvp(T(X), T(v), mode="fd"))
+    S = residual_scale(P, X, b, dt)
+    assert _sample_err(got, ref, S) <= 1e-7
+
+
+@pytest.mark.parametrize("mode", ["sound", "sound_thermal"])
+@pytest.mark.parametrize("shape,bc", [((32, 16), ("periodic", "wall")), ((8, 8, 16), ("periodic", "periodic", "wall"))])
+def test_precond_parity(mode, shape, bc):
+    J = _lib()
+    nd = len(shape)
+    pd, X = W.random_state(shape, bc, seed=12, g=tuple([0.0] * (nd - 1) + [-1.0]), chi_model="power",
+                           chi0=0.02, amp=0.2)
+    P = Problem.from_dict(pd)
+    dt = 0.05
+    r = W.random_vector(X, 13)
+    ref = PBP(P, X, dt, mode).apply(r)
+    ctx = J.Context(pd, precond=mode, cg_eta=1e-13, cg_maxit=200)
+    ctx.set_state_n(T(X), dt)
+    got = H(ctx.precond_apply(T(X), T(r)))
+    for k in range(P.nvar):
+        assert np.max(np.abs(got[k] - ref[k])) <= 1e-10 * np.max(np.abs(ref[k])), k
+    # default inner tolerance: same multigrid-CG algorithm as the oracle's
+    ref2 = PBP(P, X, dt, mode, solver_factory=PCGSolver.factory(1e-4)).apply(r)
+    ctx.set_opts(cg_eta=1e-4, cg_maxit=50)
+    got2 = H(ctx.precond_apply(T(X), T(r)))
+    for k in range(P.nvar):
+        assert np.max(np.abs(got2[k] - ref2[k])) <= 1e-9 * np.max(np.abs(ref2[k])), k
+
+
+def test_precond_fp32_variant():
+    J = _lib()
+    pd, X = W.random_state((64, 32), ("periodic", "wall"), seed=14, g=(0.0, -1.0), chi_model="power",
+                           chi0=0.02, amp=0.2)
+    P = Problem.from_dict(pd)
+    dt = 0.05
+    r = W.random_vector(X, 15)
+    ref = PBP(P, X, dt, "sound_thermal").apply(r)
+    ctx = J.Context(pd, precond="sound_thermal", ell_precision="fp32", cg_eta=1e-6, cg_maxit=100)
+    ctx.set_state_n(T(X), dt)
+    got = H(ctx.precond_apply(T(X), T(r)))
+    for k in range(P.nvar):
+        assert np.max(np.abs(got[k] - ref[k])) <= 1e-4 * np.max(np.abs(ref[k])), k
+
+
+def _step_parity(pd, X0, cfl, exact_root=True, **opts):
+    J = _lib()
+    P = Problem.from_dict(pd)
+    dt = cfl_dt(P, X0, cfl)
+    ctx = J.Context(pd, **opts)
+    Xg = T(X0)
+    dtg = ctx.cfl_dt(Xg, cfl)
+    assert abs(dtg - dt) <= 1e-14 * dt
+    st = ctx.implicit_step(Xg, dt)
+    assert st["converged"] == 1
+    Xs, hist = exact_step(P, X0, dt)
+    _, R = scaling_LR(P, Xs)
+    err = np.max(np.abs((H(Xg) - Xs) / R))
+    return err, st
+
+
+@pytest.mark.parametrize("jv", ["fd", "exact"])
+def test_implicit_step_acoustic_bump(jv):
+    w = W.acoustic_bump_2d(n=32)
+    err, st = _step_parity(w["problem"], w["X0"], w["cfl"], precond="sound", jv_mode=jv)
+    assert err <= 1e-8, (err, st)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_implicit_step_stratified_thermal(prec):
+    w = W.polytrope((32, 32), 10.0, mach=1e-3, seed=5, chi_model="power", steps=1, cfl=100.0)
+    err, st = _step_parity(w["problem"], w["X0"], 100.0, precond="sound_thermal", ell_precision=prec)
+    assert err <= 1e-8, (err, st)
+
+
+def test_implicit_step_unpreconditioned_small_cfl():
+    w = W.acoustic_bump_2d(n=16)
+    err, st = _step_parity(w["problem"], w["X0"], 1.0, precond="none", alpha1=1.0)
+    assert err <= 1e-8, (err, st)
