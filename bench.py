@@ -1,0 +1,243 @@
+"""Benchmark: implicit steps/s of the JFNK + physics-based-preconditioner step on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload c2] [--gpus 1]
+
+A step is one implicit time step X^n -> X^{n+1} (CFL time step from X^n, Newton to
+||R^-1 dX||_inf < 1e-8, FGMRES(30) with CGS2, finite-difference J.v, physics-based
+preconditioner with multigrid CG).  Default workload: 2D stratified polytrope 256x256 (x
+periodic, walls in y, density contrast 10, constant conductivity, Mach 1e-3 velocity
+noise), CFL_hydro = 100, sound + thermal preconditioner, FP64 throughout.  W warm-up steps
+run from X^0 and are discarded; then K steps are timed from X^0 (the workload's 10 steps
+when K = 10).
+
+Also reported on the same state: residual and J.v cell-updates/s (HIP events around each
+kernel launch on the library's stream), the HBM roofline of the dominant kernel, and the
+CPU oracle timed on a bounded sample.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "implicit steps/s and J·v cell-updates/s at fixed Newton tol; % HBM peak"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--jv", default=None, choices=["fd", "exact"])
+    ap.add_argument("--ell", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-kernels-3d", dest="kernels_3d", action="store_false",
+                    help="skip the kernel rates at the 256^3 production size")
+    ap.add_argument("--cpu-budget-s", type=float, default=30.0)
+    return ap.parse_args()
+
+
+def workload(name):
+    import workloads as W
+    w = W.CONFIGS[name]()
+    return w
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU domain decomposition is a design, not an implementation.",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1512_03662_amd as J
+
+    dev = torch.device("cuda:0")
+    w = workload(args.workload)
+    pd = w["problem"]
+    jv = args.jv or w["jv_mode"]
+    precond = w["precond"]
+    X0 = torch.tensor(w["X0"], dtype=torch.float64, device=dev)
+    N = int(np.prod(pd["shape"]))
+    nvar = 2 + len(pd["shape"])
+    ctx = J.Context(pd, precond=precond, jv_mode=jv, ell_precision=args.ell)
+    cfl = w["cfl"]
+
+    def run_steps(k):
+        X = X0.clone()
+        stats = []
+        for _ in range(k):
+            dt = ctx.cfl_dt(X, cfl)
+            stats.append(ctx.implicit_step(X, dt))
+        return X, stats
+
+    print(f"# workload {w['name']}: warm-up {args.warmup} step(s)", file=sys.stderr, flush=True)
+    run_steps(args.warmup)
+    torch.cuda.synchronize()
+    print(f"# timing {args.steps} step(s)", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    Xk, stats = run_steps(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sec = t1 - t0
+    steps_per_s = args.steps / sec
+
+    # ---- probe pass: the same K steps with every kernel launch timed by HIP events -------
+    print("# probe pass", file=sys.stderr, flush=True)
+    from paper_1512_03662_amd import _native as Nat
+    Nat.probe_enable(True)
+    run_steps(args.steps)
+    torch.cuda.synchronize()
+    probes = Nat.probe_results()
+    Nat.probe_enable(False)
+    dom = max(probes.items(), key=lambda kv: kv[1][0])
+    dom_name, (dom_ms, dom_n, dom_bytes) = dom
+    avg_s = dom_ms * 1e-3 / dom_n
+    achieved = dom_bytes / dom_n / avg_s / 1e9
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom_name,
+                "launches": dom_n, "avg_us": avg_s * 1e6,
+                "share_of_kernel_time": dom_ms / sum(v[0] for v in probes.values())}
+
+    # ---- kernel rates: residual, exact and FD J.v, vjp on X^0 of this workload -------------
+    kernels = kernel_rates(J, ctx, X0, cfl, N, nvar, args.kernel_reps, prefix="")
+    # and at the full 3D production size (256^3 convective box, 5 variables)
+    if args.kernels_3d:
+        import workloads as Wl
+        w5 = Wl.convective_box_3d(n=256)
+        X5 = torch.tensor(w5["X0"], dtype=torch.float64, device=dev)
+        ctx5 = J.Context(w5["problem"], gmres_m=1, precond="none")
+        kernels.update(kernel_rates(J, ctx5, X5, w5["cfl"], int(np.prod(w5["problem"]["shape"])), 5,
+                                    args.kernel_reps, prefix="3d256_"))
+        ctx5.close()
+        del X5
+
+    rec = {
+        "metric": METRIC,
+        "value": steps_per_s,
+        "unit": "implicit steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * sec / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.ell == "fp64" else "f64 (fp32 elliptic solves)",
+        "data": "synthetic",
+        "config": {"workload": w["name"], "grid": list(pd["shape"]), "cfl_hydro": cfl,
+                   "jv": jv, "precond": precond, "elliptic": args.ell, "newton_tol": 1e-8,
+                   "gmres": "FGMRES(30)+CGS2, eta 1e-4", "cg_eta": 1e-4},
+        "solver": {"newton_its": sum(s["newton_its"] for s in stats),
+                   "gmres_its": sum(s["gmres_its"] for s in stats),
+                   "cg_its": sum(s["cg_its"] for s in stats),
+                   "converged_steps": sum(s["converged"] for s in stats)},
+        "roofline": roofline,
+        "kernels": kernels,
+        "probe_ms": {k: round(v[0], 3) for k, v in sorted(probes.items(), key=lambda kv: -kv[1][0])},
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"], rec["error_vs_oracle"] = cpu_baseline(w, args, Xk_first=first_step(ctx, X0, cfl))
+    print(json.dumps(rec), flush=True)
+
+
+def first_step(ctx, X0, cfl):
+    X = X0.clone()
+    dt = ctx.cfl_dt(X, cfl)
+    ctx.implicit_step(X, dt)
+    return X.cpu().numpy()
+
+
+def kernel_rates(J, ctx, X0, cfl, N, nvar, reps, prefix):
+    """Cell-updates/s and achieved GB/s (algorithmic bytes) of single-launch kernels, timed
+    with HIP events on the library's stream."""
+    import torch
+    dt0 = ctx.cfl_dt(X0, cfl)
+    ctx.set_state_n(X0, dt0)
+    g = torch.Generator(device=X0.device)
+    g.manual_seed(7)
+    v = torch.rand(X0.shape, dtype=torch.float64, device=X0.device, generator=g) - 0.5
+    out = torch.empty_like(X0)
+
+    def time_call(fn):
+        s = ctx.stream
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        fn()
+        e0.record(s)
+        for _ in range(reps):
+            fn()
+        e1.record(s)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    t_res = time_call(lambda: ctx.residual(X0, out))
+    t_jex = time_call(lambda: ctx.jvp(X0, v, "exact", out))
+    t_jfd = time_call(lambda: ctx.jvp(X0, v, "fd", out))
+    t_vjp = time_call(lambda: ctx.vjp(X0, v, out))
+    # algorithmic bytes per cell: residual reads X and b and writes F (24 nvar); the exact
+    # J.v reads X and v and writes J v (24 nvar); the FD call also evaluates F(X) and two
+    # scaled norms (4 kernels); the vjp reads X and w and writes J^T w (24 nvar)
+    B = 24.0 * nvar * N
+    r = {
+        prefix + "cells": N,
+        prefix + "residual_cell_updates_per_s": N / t_res,
+        prefix + "residual_GBps": B / t_res / 1e9,
+        prefix + "residual_hbm_frac": B / t_res / 1e9 / HBM_PEAK_GBS,
+        prefix + "jv_exact_cell_updates_per_s": N / t_jex,
+        prefix + "jv_exact_GBps": B / t_jex / 1e9,
+        prefix + "jv_exact_hbm_frac": B / t_jex / 1e9 / HBM_PEAK_GBS,
+        prefix + "jv_fd_call_cell_updates_per_s": N / t_jfd,
+        prefix + "vjp_cell_updates_per_s": N / t_vjp,
+        prefix + "vjp_GBps": B / t_vjp / 1e9,
+    }
+    return r
+
+
+def cpu_baseline(w, args, Xk_first):
+    """The CPU oracle (NumPy, one thread) on the first implicit steps of the same workload,
+    stopped once args.cpu_budget_s/3 of CPU time is spent (at most 3 steps)."""
+    import numpy as np
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    from oracle.newton import jfnk_step, Opts, Stats
+    from oracle.residual import Problem, cfl_dt
+    from oracle.scaling import scaling_LR
+    P = Problem.from_dict(w["problem"])
+    X = w["X0"].copy()
+    t0 = time.perf_counter()
+    steps = 0
+    err = None
+    while steps < 3:
+        dt = cfl_dt(P, X, w["cfl"])
+        X = jfnk_step(P, X, dt, Opts(precond=w["precond"], jv_mode=w["jv_mode"], elliptic="pcg"), Stats())
+        steps += 1
+        if steps == 1:
+            _, R = scaling_LR(P, X)
+            err = float(np.max(np.abs((Xk_first - X) / R)))
+        if time.perf_counter() - t0 > args.cpu_budget_s / 3:
+            break
+    sec = time.perf_counter() - t0
+    try:
+        cores_avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores_avail = os.cpu_count()
+    base = {"value": steps / sec, "unit": "implicit steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {steps} implicit step(s) of {w['name']} from X^0 (NumPy FP64, one "
+                      f"thread; {cores_avail} host cores available)",
+            "seconds": sec}
+    return base, {"first_step_max_abs_Rinv_dX": err}
+
+
+if __name__ == "__main__":
+    main()

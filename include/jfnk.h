@@ -127,7 +127,8 @@ int jfnk_jvp(jfnk_ctx* ctx, const double* X, const double* v, double* Jv, int32_
 /* J^T w at X (exact, frozen branches; deterministic gather form, no atomics).          */
 int jfnk_vjp(jfnk_ctx* ctx, const double* X, const double* w, double* JTw);
 
-/* (dF/dX^n)^T lam = -(dU/dX|_{X^n})^T lam / dt  (theta = 1 only).                     */
+/* (dF/dX^n)^T lam = -(dU/dX|_{X^n})^T lam / dt - (1-theta) (dR/dX|_{X^n})^T lam, the
+ * dependence of the step residual on the previous state (eq. crank_nicholson).         */
 int jfnk_vjp_prev(jfnk_ctx* ctx, const double* Xn, const double* lam, double* out);
 
 /* z ~ +J^-1 r by the physics-based preconditioner frozen at X (Sect. 4.3 with the
@@ -141,16 +142,30 @@ int jfnk_precond_apply(jfnk_ctx* ctx, const double* X, const double* r, double* 
  * JFNK_E_NEWTON_NOCONV otherwise (X then holds the last iterate).  stats may be NULL.   */
 int jfnk_implicit_step(jfnk_ctx* ctx, double* X, double dt, jfnk_step_stats* stats);
 
-/* Adjoint of one implicit step (theta = 1): given gbar_n1 = dL/dX^{n+1} at the converged
- * X^{n+1} = Xn1 of the step from Xn with dt, solve J^T lam = gbar_n1 (FGMRES on the scaled
- * transposed system with the transposed preconditioner, tolerance opts.gmres_eta) and
- * return gbar_n = dL/dX^n = (dU/dX|_{X^n})^T lam / dt.                                  */
+/* Adjoint of one implicit step: given gbar_n1 = dL/dX^{n+1} at the converged X^{n+1} = Xn1
+ * of the step from Xn with dt, solve J^T lam = gbar_n1 (FGMRES(m) on the scaled transposed
+ * system R J^T L^-1, right preconditioner L M^-T R^-1 with the transposed physics-based
+ * preconditioner, tolerance opts.gmres_eta) and return gbar_n = dL/dX^n =
+ * -(dF/dX^n)^T lam.  Returns JFNK_E_GMRES_NOCONV (gbar_n still written) when the linear
+ * solve stops at gmres_maxit.  dt is a constant of the step (not differentiated).       */
 int jfnk_adjoint_step(jfnk_ctx* ctx, const double* Xn1, const double* Xn, double dt,
                       const double* gbar_n1, double* gbar_n, jfnk_step_stats* stats);
 
 /* dt = cfl * min_d dx_d / max_c(|u_c| + c_s), u_c the cell-centred mean of the face
  * velocities (Introduction, CFL_hydro).  Synchronises; returns a negative value on error. */
 double jfnk_cfl_dt(jfnk_ctx* ctx, const double* X, double cfl);
+
+/* Measurement hooks (process-wide, not thread-safe).  jfnk_probe_enable(1) clears the
+ * counters and from then on brackets every launch of the instrumented kernels with HIP
+ * events on the stream it is launched on; jfnk_probe_enable(0) stops.  Kernel family k
+ * (0 <= k < jfnk_probe_count(), name jfnk_probe_name(k)) reports through jfnk_probe_read
+ * its summed event time in ms, its launch count, and the algorithmic bytes of those
+ * launches (every field the kernel must read or write, counted once).  jfnk_probe_read
+ * waits for the recorded events.                                                        */
+int jfnk_probe_enable(int32_t on);
+int jfnk_probe_count(void);
+const char* jfnk_probe_name(int32_t k);
+int jfnk_probe_read(int32_t k, double* ms, int64_t* launches, double* bytes);
 
 #ifdef __cplusplus
 }

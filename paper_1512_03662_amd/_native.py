@@ -97,7 +97,28 @@ SIGNATURES = {
     "jfnk_implicit_step": (C.c_int, [_P, _P, _D, C.POINTER(StepStats)]),
     "jfnk_adjoint_step": (C.c_int, [_P, _P, _P, _D, _P, _P, C.POINTER(StepStats)]),
     "jfnk_cfl_dt": (C.c_double, [_P, _P, _D]),
+    "jfnk_probe_enable": (C.c_int, [C.c_int32]),
+    "jfnk_probe_count": (C.c_int, []),
+    "jfnk_probe_name": (C.c_char_p, [C.c_int32]),
+    "jfnk_probe_read": (C.c_int, [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                  C.POINTER(C.c_double)]),
 }
+
+
+def probe_enable(on=True):
+    lib().jfnk_probe_enable(1 if on else 0)
+
+
+def probe_results():
+    """{kernel family: (ms, launches, algorithmic bytes)} of the instrumented kernels."""
+    L = lib()
+    out = {}
+    for k in range(L.jfnk_probe_count()):
+        ms, n, b = C.c_double(), C.c_int64(), C.c_double()
+        L.jfnk_probe_read(k, C.byref(ms), C.byref(n), C.byref(b))
+        if n.value:
+            out[L.jfnk_probe_name(k).decode()] = (ms.value, n.value, b.value)
+    return out
 
 
 def header_functions(path=HEADER):

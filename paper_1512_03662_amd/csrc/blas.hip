@@ -1,6 +1,6 @@
 // Vector kernels of the Krylov solvers: deterministic reductions (64-lane wavefront
 // shuffles, then LDS across the 4 waves of a block, then per-block partials summed in block
-// order by the last block to finish), the fused classical Gram-Schmidt passes of the Arnoldi
+// order by a one-block finalize kernel), the fused classical Gram-Schmidt passes of the Arnoldi
 // step (Sect. 4.1: GMRES), linear combinations and the scaled norms of eq. nr_terminate.
 //
 // Every reduction visits elements in a fixed order for a given grid, so results are
@@ -10,6 +10,7 @@
 
 #include "common.hpp"
 #include "kernels.hpp"
+#include "probe.hpp"
 
 namespace jfnk {
 
@@ -29,13 +30,12 @@ __device__ __forceinline__ double wave_reduce(double v) {
   return v;
 }
 
-// Reduce K per-thread values over the block, store the block partial, and let the last block
-// combine all partials into out[0..K-1].
+// Reduce K per-thread values over the block and store the block's partials; a one-block
+// finalize kernel launched next sums the partials in block order (no cross-block fences).
 template <class Op, int K>
 __device__ __forceinline__ void block_finish(const double (&vals)[K], double* out, const RedWS& ws) {
   constexpr int NW = kBlock / 64;
   __shared__ double sm[NW][K];
-  __shared__ bool is_last;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
@@ -49,30 +49,37 @@ __device__ __forceinline__ void block_finish(const double (&vals)[K], double* ou
     for (int w = 1; w < NW; ++w) acc = Op::f(acc, sm[w][threadIdx.x]);
     ws.part[(size_t)blockIdx.x * K + threadIdx.x] = acc;
   }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned int t = atomicAdd(ws.count, 1u);
-    is_last = (t == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  const int nb = gridDim.x;
+  (void)out;
+}
+
+// One block combines the nb partials of each of the K sums in block order.
+template <class Op>
+__global__ void __launch_bounds__(kBlock) k_finalize(const double* part, int nb, int K, double* out) {
+  constexpr int NW = kBlock / 64;
+  __shared__ double sm[NW];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int k = 0; k < K; ++k) {
     double acc = Op::id;
-    for (int b = threadIdx.x; b < nb; b += kBlock) acc = Op::f(acc, ws.part[(size_t)b * K + k]);
+    for (int b = threadIdx.x; b < nb; b += kBlock) acc = Op::f(acc, part[(size_t)b * K + k]);
     acc = wave_reduce<Op>(acc);
     __syncthreads();
-    if (lane == 0) sm[wid][0] = acc;
+    if (lane == 0) sm[wid] = acc;
     __syncthreads();
     if (threadIdx.x == 0) {
-      double s = sm[0][0];
-      for (int w = 1; w < NW; ++w) s = Op::f(s, sm[w][0]);
+      double s = sm[0];
+      for (int w = 1; w < NW; ++w) s = Op::f(s, sm[w]);
       out[k] = s;
     }
   }
-  if (threadIdx.x == 0) *ws.count = 0u;
+}
+
+template <class Op>
+static void finalize(const RedWS& ws, int nb, int K, double* out, hipStream_t s) {
+  k_finalize<Op><<<1, kBlock, 0, s>>>(ws.part, nb, K, out);
+}
+
+void launch_finalize_sum(const RedWS& ws, int nb, int K, double* out, hipStream_t s) {
+  finalize<OpSum>(ws, nb, K, out, s);
 }
 
 static inline int red_blocks(size_t n) {
@@ -94,7 +101,11 @@ __global__ void __launch_bounds__(kBlock) k_dot(size_t n, const T* a, const T* b
 
 template <class T>
 void launch_dot(size_t n, const T* a, const T* b, double* out, const RedWS& w, hipStream_t s) {
-  k_dot<T><<<red_blocks(n), kBlock, 0, s>>>(n, a, b, out, w);
+  {
+    launch_k(KF_DOT, 2.0 * sizeof(T) * n, k_dot<T>, dim3(red_blocks(n)), dim3(kBlock), 0, s, n, a, b,
+             out, w);
+  }
+  finalize<OpSum>(w, red_blocks(n), 1, out, s);
 }
 template void launch_dot<double>(size_t, const double*, const double*, double*, const RedWS&, hipStream_t);
 template void launch_dot<float>(size_t, const float*, const float*, double*, const RedWS&, hipStream_t);
@@ -182,18 +193,30 @@ static void md_launch(size_t n, const double* V, size_t ld, const double* h, con
                       double* w_mut, double* out, const RedWS& ws, hipStream_t s) {
   (void)h;
   (void)w_mut;
-  k_multidot<K><<<red_blocks(n), kBlock, 0, s>>>(n, V, ld, w, out, ws);
+  {
+    launch_k(KF_MULTIDOT, 8.0 * n * (K + 1), k_multidot<K>, dim3(red_blocks(n)), dim3(kBlock), 0, s,
+             n, V, ld, w, out, ws);
+  }
+  finalize<OpSum>(ws, red_blocks(n), K, out, s);
 }
 template <int K>
 static void ud_launch(size_t n, const double* V, size_t ld, const double* h, const double* w,
                       double* w_mut, double* out, const RedWS& ws, hipStream_t s) {
   (void)w;
-  k_cgs2_update_dot<K><<<red_blocks(n), kBlock, 0, s>>>(n, V, ld, h, w_mut, out, ws);
+  {
+    launch_k(KF_CGS2_UD, 8.0 * n * (K + 2), k_cgs2_update_dot<K>, dim3(red_blocks(n)), dim3(kBlock),
+             0, s, n, V, ld, h, w_mut, out, ws);
+  }
+  finalize<OpSum>(ws, red_blocks(n), K + 1, out, s);
 }
 template <int K>
 static void un_launch(size_t n, const double* V, size_t ld, const double* h, const double* w,
                       double* dst, double* out, const RedWS& ws, hipStream_t s) {
-  k_cgs2_update_norm<K><<<red_blocks(n), kBlock, 0, s>>>(n, V, ld, h, w, dst, out, ws);
+  {
+    launch_k(KF_CGS2_UN, 8.0 * n * (K + 2), k_cgs2_update_norm<K>, dim3(red_blocks(n)), dim3(kBlock),
+             0, s, n, V, ld, h, w, dst, out, ws);
+  }
+  finalize<OpSum>(ws, red_blocks(n), 1, out, s);
 }
 template <int K>
 static void lc_launch(size_t n, const double* Z, size_t ld, const double* y, const double* w,
@@ -203,7 +226,8 @@ static void lc_launch(size_t n, const double* Z, size_t ld, const double* y, con
   (void)ws;
   size_t b = (n + kBlock - 1) / kBlock;
   if (b > 4096) b = 4096;
-  k_lincomb<K><<<(unsigned)b, kBlock, 0, s>>>(n, Z, ld, y, dst);
+  launch_k(KF_LINCOMB, 8.0 * n * (K + 1), k_lincomb<K>, dim3((unsigned)b), dim3(kBlock), 0, s, n, Z,
+           ld, y, dst);
 }
 
 constexpr int kMaxBasis = kMaxK - 1;  // K ranges over 1..kMaxBasis
@@ -291,7 +315,7 @@ __device__ __forceinline__ void cell_R_scale(const Grid& G, const Pos& P, const 
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
     double s;
-    int im = gidx(G, P, 1, shift(off0(), d, -1), &s);
+    int im = gidx<ND>(G, P, 1, shift(off0(), d, -1), &s);
     double csf = 0.5 * (sqrt(k * X[G.N + im]) + cs0);
     Rs[2 + d] = fmax(fabs(X[(2 + d) * G.N + P.lin]), alpha2 * csf);
   }
@@ -302,7 +326,7 @@ __global__ void __launch_bounds__(kBlock) k_scaled_red(Grid G, const double* X, 
                                                        double alpha2, double* out, RedWS ws) {
   double acc = 0.0;
   for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < G.N; lin += gridDim.x * kBlock) {
-    Pos P = make_pos(G, lin);
+    Pos P = make_pos<ND>(G, lin);
     double Rs[2 + ND];
     cell_R_scale<ND>(G, P, X, alpha2, Rs);
 #pragma unroll
@@ -320,14 +344,21 @@ __global__ void __launch_bounds__(kBlock) k_scaled_red(Grid G, const double* X, 
 void launch_scaled_norm2(const Grid& G, const double* X, const double* V, double alpha2,
                          double* out, const RedWS& ws, hipStream_t s) {
   int b = red_blocks(G.N);
-  if (G.nd == 2) k_scaled_red<2, false><<<b, kBlock, 0, s>>>(G, X, V, alpha2, out, ws);
-  else k_scaled_red<3, false><<<b, kBlock, 0, s>>>(G, X, V, alpha2, out, ws);
+  {
+    const double by = 16.0 * (2 + G.nd) * G.N;
+    if (G.nd == 2)
+      launch_k(KF_SCALED, by, k_scaled_red<2, false>, dim3(b), dim3(kBlock), 0, s, G, X, V, alpha2, out, ws);
+    else
+      launch_k(KF_SCALED, by, k_scaled_red<3, false>, dim3(b), dim3(kBlock), 0, s, G, X, V, alpha2, out, ws);
+  }
+  finalize<OpSum>(ws, b, 1, out, s);
 }
 void launch_scaled_maxabs(const Grid& G, const double* X, const double* V, double alpha2,
                           double* out, const RedWS& ws, hipStream_t s) {
   int b = red_blocks(G.N);
   if (G.nd == 2) k_scaled_red<2, true><<<b, kBlock, 0, s>>>(G, X, V, alpha2, out, ws);
   else k_scaled_red<3, true><<<b, kBlock, 0, s>>>(G, X, V, alpha2, out, ws);
+  finalize<OpMax>(ws, b, 1, out, s);
 }
 
 // max_c (|u_c| + c_s), u_c the mean of the two faces of c along each axis (Introduction)
@@ -336,13 +367,13 @@ __global__ void __launch_bounds__(kBlock) k_cfl_speed(Grid G, const double* X, d
   double acc = 0.0;
   const double k = G.gamma * (G.gamma - 1.0);
   for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < G.N; lin += gridDim.x * kBlock) {
-    Pos P = make_pos(G, lin);
+    Pos P = make_pos<ND>(G, lin);
     double u2 = 0.0;
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
       double s0, s1;
-      int i0 = gidx(G, P, 2 + d, off0(), &s0);
-      int i1 = gidx(G, P, 2 + d, shift(off0(), d, 1), &s1);
+      int i0 = gidx<ND>(G, P, 2 + d, off0(), &s0);
+      int i1 = gidx<ND>(G, P, 2 + d, shift(off0(), d, 1), &s1);
       double uc = 0.5 * (s0 * X[(2 + d) * G.N + i0] + s1 * X[(2 + d) * G.N + i1]);
       u2 += uc * uc;
     }
@@ -355,6 +386,7 @@ void launch_cfl_speed(const Grid& G, const double* X, double* out, const RedWS& 
   int b = red_blocks(G.N);
   if (G.nd == 2) k_cfl_speed<2><<<b, kBlock, 0, s>>>(G, X, out, ws);
   else k_cfl_speed<3><<<b, kBlock, 0, s>>>(G, X, out, ws);
+  finalize<OpMax>(ws, b, 1, out, s);
 }
 
 }  // namespace jfnk

@@ -120,6 +120,7 @@ struct Pos {
   bool interior;
 };
 
+template <int ND>
 __device__ __forceinline__ Pos make_pos(const Grid& G, int lin) {
   Pos p;
   p.lin = lin;
@@ -129,7 +130,8 @@ __device__ __forceinline__ Pos make_pos(const Grid& G, int lin) {
   p.c[1] = r % G.n[1];
   p.c[2] = r / G.n[1];
   bool in = true;
-  for (int d = 0; d < G.nd; ++d) in = in && (p.c[d] >= 3) && (p.c[d] <= G.n[d] - 3);
+#pragma unroll
+  for (int d = 0; d < ND; ++d) in = in && (p.c[d] >= 3) && (p.c[d] <= G.n[d] - 3);
   p.interior = in;
   return p;
 }
@@ -144,15 +146,20 @@ __device__ __forceinline__ Off shift(Off a, int d, int k) {
   return a;
 }
 
-// index and sign of field var at offset; var >= 2 is velocity component var-2.
+// index and sign of field var at offset; var >= 2 is velocity component var-2.  The axis
+// loop is unrolled over the compile-time dimension so that positions stay in registers.
+template <int ND>
 __device__ __forceinline__ int gidx(const Grid& G, const Pos& p, int var, Off o, double* s) {
   if (p.interior) {
     *s = 1.0;
-    return p.lin + o.o[0] + o.o[1] * G.stride[1] + o.o[2] * G.stride[2];
+    int idx = p.lin + o.o[0] + o.o[1] * G.stride[1];
+    if (ND == 3) idx += o.o[2] * G.stride[2];
+    return idx;
   }
   double sign = 1.0;
   int idx = 0;
-  for (int d = 0; d < G.nd; ++d) {
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
     int i = p.c[d] + o.o[d];
     int src;
     if (var == 2 + d) {

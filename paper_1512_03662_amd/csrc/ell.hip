@@ -13,6 +13,7 @@
 // by Gershgorin); dense inverse at the coarsest level.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "probe.hpp"
 
 namespace jfnk {
 
@@ -77,7 +78,7 @@ __global__ void __launch_bounds__(kBlock) k_ell_coef(Grid G, const double* X, do
                                                      double* w0, double* w1, double* w2) {
   int lin = blockIdx.x * kBlock + threadIdx.x;
   if (lin >= G.N) return;
-  Pos P = make_pos(G, lin);
+  Pos P = make_pos<ND>(G, lin);
   const double gm1 = G.gamma - 1.0;
   const double rho = X[lin], e = X[G.N + lin];
   double* w[3] = {w0, w1, w2};
@@ -89,7 +90,7 @@ __global__ void __launch_bounds__(kBlock) k_ell_coef(Grid G, const double* X, do
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
     double s;
-    int im = gidx(G, P, 0, shift(off0(), d, -1), &s);
+    int im = gidx<ND>(G, P, 0, shift(off0(), d, -1), &s);
     double wf;
     if (G.bc[d] == 1 && P.c[d] == 0) {
       wf = 0.0;
@@ -286,31 +287,183 @@ __global__ void __launch_bounds__(kBlock) k_mg_smooth2(LV<T> L, const T* b, cons
 template <class T>
 void launch_mg_presmooth(const Grid& G, const Level& L, const T* b, T* x, hipStream_t s) {
   LV<T> v = view<T>(G, L);
-  if (G.nd == 2) k_mg_presmooth<T, 2><<<CELLS(L.N), 0, s>>>(v, b, x);
-  else k_mg_presmooth<T, 3><<<CELLS(L.N), 0, s>>>(v, b, x);
+  const double by = (4.0 + G.nd) * L.N * (double)sizeof(T);
+  if (G.nd == 2) launch_k(KF_MG_PRE, by, k_mg_presmooth<T, 2>, CELLS(L.N), 0, s, v, b, x);
+  else launch_k(KF_MG_PRE, by, k_mg_presmooth<T, 3>, CELLS(L.N), 0, s, v, b, x);
 }
 template <class T>
 void launch_mg_restrict_resid(const Grid& G, const Level& f, const T* b, const T* x, T* bc,
                               const Level& c, hipStream_t s) {
   LV<T> v = view<T>(G, f);
-  if (G.nd == 2) k_mg_restrict_resid<T, 2><<<CELLS(c.N), 0, s>>>(v, b, x, bc, c.N, c.n[0], c.n[1]);
-  else k_mg_restrict_resid<T, 3><<<CELLS(c.N), 0, s>>>(v, b, x, bc, c.N, c.n[0], c.n[1]);
+  const double by = ((3.0 + G.nd) * f.N + c.N) * (double)sizeof(T);
+  if (G.nd == 2)
+    launch_k(KF_MG_RESTRICT, by, k_mg_restrict_resid<T, 2>, CELLS(c.N), 0, s, v, b, x, bc, c.N, c.n[0], c.n[1]);
+  else
+    launch_k(KF_MG_RESTRICT, by, k_mg_restrict_resid<T, 3>, CELLS(c.N), 0, s, v, b, x, bc, c.N, c.n[0], c.n[1]);
 }
 template <class T>
 void launch_mg_prolong_smooth1(const Grid& G, const Level& f, const T* b, const T* x2, const T* xc,
                                const Level& c, T* x1, T* d0, hipStream_t s) {
   LV<T> v = view<T>(G, f);
+  const double by = ((6.0 + G.nd) * f.N + c.N) * (double)sizeof(T);
   if (G.nd == 2)
-    k_mg_prolong_smooth1<T, 2><<<CELLS(f.N), 0, s>>>(v, b, x2, xc, c.stride[0], c.stride[1], c.stride[2], x1, d0);
+    launch_k(KF_MG_PROLONG, by, k_mg_prolong_smooth1<T, 2>, CELLS(f.N), 0, s, v, b, x2, xc, c.stride[0],
+             c.stride[1], c.stride[2], x1, d0);
   else
-    k_mg_prolong_smooth1<T, 3><<<CELLS(f.N), 0, s>>>(v, b, x2, xc, c.stride[0], c.stride[1], c.stride[2], x1, d0);
+    launch_k(KF_MG_PROLONG, by, k_mg_prolong_smooth1<T, 3>, CELLS(f.N), 0, s, v, b, x2, xc, c.stride[0],
+             c.stride[1], c.stride[2], x1, d0);
 }
 template <class T>
 void launch_mg_smooth2(const Grid& G, const Level& L, const T* b, const T* x1, const T* d0, T* x,
                        hipStream_t s) {
   LV<T> v = view<T>(G, L);
-  if (G.nd == 2) k_mg_smooth2<T, 2><<<CELLS(L.N), 0, s>>>(v, b, x1, d0, x);
-  else k_mg_smooth2<T, 3><<<CELLS(L.N), 0, s>>>(v, b, x1, d0, x);
+  const double by = (6.0 + G.nd) * L.N * (double)sizeof(T);
+  if (G.nd == 2) launch_k(KF_MG_SMOOTH2, by, k_mg_smooth2<T, 2>, CELLS(L.N), 0, s, v, b, x1, d0, x);
+  else launch_k(KF_MG_SMOOTH2, by, k_mg_smooth2<T, 3>, CELLS(L.N), 0, s, v, b, x1, d0, x);
+}
+
+// ---- coarse part of the V-cycle in one workgroup -------------------------------------------
+// Levels with at most kCoarseMaxN cells: right-hand side, iterate and smoother vectors live
+// in LDS, coefficients are read from global memory; phases are separated by barriers.
+template <class T, int ND>
+__global__ void __launch_bounds__(kCoarseThreads) k_vcycle_coarse(CoarseArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sb = (T*)smem_raw;
+  T* sx = sb + a.tot;
+  T* s1 = sx + a.tot;
+  T* s2 = s1 + a.tot;
+  const int tid = threadIdx.x;
+  const int NT = blockDim.x;
+  const T th = T(1.0 / kChebTheta);
+  for (int i = tid; i < a.N[0]; i += NT) sb[a.off[0] + i] = ((const T*)a.b0)[i];
+  __syncthreads();
+  for (int j = 0; j + 1 < a.nl; ++j) {
+    LV<T> L;
+    for (int d = 0; d < 3; ++d) {
+      L.n[d] = a.n[j][d];
+      L.stride[d] = a.stride[j][d];
+      L.bc[d] = a.bc[d];
+      L.w[d] = (const T*)a.w[j][d];
+    }
+    L.N = a.N[j];
+    L.diag = (const T*)a.diag[j];
+    L.dinv = (const T*)a.dinv[j];
+    const T* b = sb + a.off[j];
+    T* x = sx + a.off[j];
+    for (int i = tid; i < L.N; i += NT) {
+      int c[3];
+      coords<ND>(L.n, i, c);
+      auto x1 = [&](int k) { return L.dinv[k] * b[k] * th; };
+      T x1c = x1(i);
+      T Ax = apply_at<T, ND>(L, c, i, x1, x1c);
+      x[i] = (T(1.0) + T(kChebC1)) * x1c + T(kChebC2) * L.dinv[i] * (b[i] - Ax);
+    }
+    __syncthreads();
+    T* bc = sb + a.off[j + 1];
+    const int Nc = a.N[j + 1];
+    for (int ic = tid; ic < Nc; ic += NT) {
+      int cc[3];
+      coords<ND>(a.n[j + 1], ic, cc);
+      auto xf = [&](int k) { return x[k]; };
+      T sum = T(0);
+#pragma unroll
+      for (int ch = 0; ch < (1 << ND); ++ch) {
+        int c[3] = {0, 0, 0};
+        int fl = 0;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+          c[d] = 2 * cc[d] + ((ch >> d) & 1);
+          fl += c[d] * L.stride[d];
+        }
+        sum += b[fl] - apply_at<T, ND>(L, c, fl, xf, x[fl]);
+      }
+      bc[ic] = sum * T(1.0 / (1 << ND));
+    }
+    __syncthreads();
+  }
+  {
+    const int j = a.nl - 1;
+    const T* b = sb + a.off[j];
+    T* x = sx + a.off[j];
+    const int n = a.N[j];
+    for (int i = tid; i < n; i += NT) {
+      double s = 0.0;
+      for (int k = 0; k < n; ++k) s += a.Ainv[(size_t)i * n + k] * (double)b[k];
+      x[i] = (T)s;
+    }
+    __syncthreads();
+  }
+  for (int j = a.nl - 2; j >= 0; --j) {
+    LV<T> L;
+    for (int d = 0; d < 3; ++d) {
+      L.n[d] = a.n[j][d];
+      L.stride[d] = a.stride[j][d];
+      L.bc[d] = a.bc[d];
+      L.w[d] = (const T*)a.w[j][d];
+    }
+    L.N = a.N[j];
+    L.diag = (const T*)a.diag[j];
+    L.dinv = (const T*)a.dinv[j];
+    const T* b = sb + a.off[j];
+    T* x = sx + a.off[j];
+    const T* xc = sx + a.off[j + 1];
+    T* t1 = s1 + a.off[j];
+    T* t2 = s2 + a.off[j];
+    const int cs[3] = {a.stride[j + 1][0], a.stride[j + 1][1], a.stride[j + 1][2]};
+    for (int i = tid; i < L.N; i += NT) {
+      int c[3];
+      coords<ND>(L.n, i, c);
+      auto xp = [&](int k) { return x[k] + xc[parent_of<T, ND>(L, k, cs)]; };
+      T xpc = xp(i);
+      T r0 = b[i] - apply_at<T, ND>(L, c, i, xp, xpc);
+      T dd = L.dinv[i] * r0 * th;
+      t1[i] = xpc + dd;
+      t2[i] = dd;
+    }
+    __syncthreads();
+    for (int i = tid; i < L.N; i += NT) {
+      int c[3];
+      coords<ND>(L.n, i, c);
+      auto xf = [&](int k) { return t1[k]; };
+      T x1c = t1[i];
+      T r1 = b[i] - apply_at<T, ND>(L, c, i, xf, x1c);
+      x[i] = x1c + T(kChebC1) * t2[i] + T(kChebC2) * L.dinv[i] * r1;
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < a.N[0]; i += NT) ((T*)a.x0)[i] = sx[a.off[0] + i];
+}
+
+template <class T>
+void launch_vcycle_coarse(const Grid& G, const Level* lv, int nl, const double* Ainv, const T* b0,
+                          T* x0, hipStream_t s) {
+  CoarseArgs a{};
+  a.nl = nl;
+  int tot = 0;
+  for (int j = 0; j < nl; ++j) {
+    for (int d = 0; d < 3; ++d) {
+      a.n[j][d] = lv[j].n[d];
+      a.stride[j][d] = lv[j].stride[d];
+      a.w[j][d] = lv[j].w[d];
+    }
+    a.N[j] = lv[j].N;
+    a.diag[j] = lv[j].diag;
+    a.dinv[j] = lv[j].dinv;
+    a.off[j] = tot;
+    tot += lv[j].N;
+  }
+  for (int d = 0; d < 3; ++d) a.bc[d] = G.bc[d];
+  a.tot = tot;
+  a.Ainv = Ainv;
+  a.b0 = b0;
+  a.x0 = x0;
+  size_t shm = 4 * (size_t)tot * sizeof(T);
+  double cbytes = 8.0 * (double)lv[nl - 1].N * lv[nl - 1].N + 2.0 * lv[0].N * (double)sizeof(T);
+  for (int j = 0; j < nl; ++j) cbytes += (3.0 + G.nd) * lv[j].N * (double)sizeof(T);
+  if (G.nd == 2)
+    launch_k(KF_MG_COARSE, cbytes, k_vcycle_coarse<T, 2>, dim3(1), dim3(kCoarseThreads), (unsigned)shm, s, a);
+  else
+    launch_k(KF_MG_COARSE, cbytes, k_vcycle_coarse<T, 3>, dim3(1), dim3(kCoarseThreads), (unsigned)shm, s, a);
 }
 
 template <class T>
@@ -334,11 +487,10 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// single-value deterministic block finish (same scheme as the Krylov reductions)
+// single-value block partial (the finalize kernel sums the partials in block order)
 __device__ __forceinline__ void finish_sum(double v, double* out, const RedWS& ws) {
   constexpr int NW = kBlock / 64;
   __shared__ double sm[NW];
-  __shared__ bool is_last;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   v = wave_sum<int>(v);
   if (lane == 0) sm[wid] = v;
@@ -348,24 +500,7 @@ __device__ __forceinline__ void finish_sum(double v, double* out, const RedWS& w
     for (int w = 1; w < NW; ++w) a += sm[w];
     ws.part[blockIdx.x] = a;
   }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) is_last = (atomicAdd(ws.count, 1u) == gridDim.x - 1);
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  double a = 0.0;
-  for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock) a += ws.part[b];
-  a = wave_sum<int>(a);
-  __syncthreads();
-  if (lane == 0) sm[wid] = a;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = sm[0];
-    for (int w = 1; w < NW; ++w) t += sm[w];
-    *out = t;
-    *ws.count = 0u;
-  }
+  (void)out;
 }
 
 static inline int red_grid(size_t n) {
@@ -392,8 +527,13 @@ template <class T>
 void launch_ell_apply_dot(const Grid& G, const Level& L, const T* p, T* q, double* out,
                           const RedWS& ws, hipStream_t s) {
   LV<T> v = view<T>(G, L);
-  if (G.nd == 2) k_ell_apply_dot<T, 2><<<red_grid(L.N), kBlock, 0, s>>>(v, p, q, out, ws);
-  else k_ell_apply_dot<T, 3><<<red_grid(L.N), kBlock, 0, s>>>(v, p, q, out, ws);
+  {
+    const double by = (3.0 + G.nd) * L.N * (double)sizeof(T);
+    dim3 gr(red_grid(L.N)), bl(kBlock);
+    if (G.nd == 2) launch_k(KF_CG_APPLY, by, k_ell_apply_dot<T, 2>, gr, bl, 0, s, v, p, q, out, ws);
+    else launch_k(KF_CG_APPLY, by, k_ell_apply_dot<T, 3>, gr, bl, 0, s, v, p, q, out, ws);
+  }
+  launch_finalize_sum(ws, red_grid(L.N), 1, out, s);
 }
 
 template <class T>
@@ -412,7 +552,11 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(size_t n, const double* sc
 template <class T>
 void launch_cg_update(size_t n, const double* sc, int i_num, int i_den, T* x, const T* p, T* r,
                       const T* q, double* rr, const RedWS& ws, hipStream_t s) {
-  k_cg_update<T><<<red_grid(n), kBlock, 0, s>>>(n, sc, i_num, i_den, x, p, r, q, rr, ws);
+  {
+    launch_k(KF_CG_UPDATE, 6.0 * n * (double)sizeof(T), k_cg_update<T>, dim3(red_grid(n)), dim3(kBlock),
+             0, s, n, sc, i_num, i_den, x, p, r, q, rr, ws);
+  }
+  launch_finalize_sum(ws, red_grid(n), 1, rr, s);
 }
 
 template <class T>
@@ -426,7 +570,8 @@ void launch_cg_pupdate(size_t n, const double* sc, int i_num, int i_den, const T
                        hipStream_t s) {
   size_t b = (n + kBlock - 1) / kBlock;
   if (b > 8192) b = 8192;
-  k_cg_pupdate<T><<<(unsigned)b, kBlock, 0, s>>>(n, sc, i_num, i_den, z, p);
+  launch_k(KF_CG_PUPDATE, 3.0 * n * (double)sizeof(T), k_cg_pupdate<T>, dim3((unsigned)b), dim3(kBlock), 0,
+           s, n, sc, i_num, i_den, z, p);
 }
 
 __global__ void k_cast_scale_f32(size_t n, const double* src, const double* nrm2, float* dst) {
@@ -498,7 +643,7 @@ __global__ void __launch_bounds__(kBlock) k_pbp_out(Grid G, const double* X, con
                                                     const double* dT, double* z) {
   int lin = blockIdx.x * kBlock + threadIdx.x;
   if (lin >= G.N) return;
-  Pos P = make_pos(G, lin);
+  Pos P = make_pos<ND>(G, lin);
   const double gm1 = G.gamma - 1.0;
   const double k = G.gamma * gm1;
   double rho = X[lin], e = X[G.N + lin];
@@ -516,7 +661,7 @@ __global__ void __launch_bounds__(kBlock) k_pbp_out(Grid G, const double* X, con
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
     double s;
-    int im = gidx(G, P, 0, shift(off0(), d, -1), &s);
+    int im = gidx<ND>(G, P, 0, shift(off0(), d, -1), &s);
     double rhom = X[im];
     double rf = 0.5 * (rhom + rho);
     double vm = v[(2 + d) * G.N + lin];
@@ -541,8 +686,8 @@ void launch_pbp_in(const Grid& G, const double* X, const double* v, int scaled, 
                    double dt, double* rhs_p, hipStream_t s) {
   (void)alpha1;
   (void)dt;
-  if (G.nd == 2) k_pbp_in<2><<<CELLS(G.N), 0, s>>>(G, X, v, scaled, rhs_p);
-  else k_pbp_in<3><<<CELLS(G.N), 0, s>>>(G, X, v, scaled, rhs_p);
+  if (G.nd == 2) launch_k(KF_PBP_IN, 40.0 * G.N, k_pbp_in<2>, CELLS(G.N), 0, s, G, X, v, scaled, rhs_p);
+  else launch_k(KF_PBP_IN, 40.0 * G.N, k_pbp_in<3>, CELLS(G.N), 0, s, G, X, v, scaled, rhs_p);
 }
 void launch_pbp_rhsT(const Grid& G, const double* X, const double* v, int scaled, double alpha1,
                      double dt, const double* dp, double* rhs_T, hipStream_t s) {
@@ -551,8 +696,9 @@ void launch_pbp_rhsT(const Grid& G, const double* X, const double* v, int scaled
 }
 void launch_pbp_out(const Grid& G, const double* X, const double* v, int scaled, double alpha1,
                     double dt, const double* dp, const double* dT, double* z, hipStream_t s) {
-  if (G.nd == 2) k_pbp_out<2><<<CELLS(G.N), 0, s>>>(G, X, v, scaled, alpha1, dt, dp, dT, z);
-  else k_pbp_out<3><<<CELLS(G.N), 0, s>>>(G, X, v, scaled, alpha1, dt, dp, dT, z);
+  const double by = 8.0 * G.N * (3.0 * (2 + G.nd) + 1 + (dT ? 1 : 0));
+  if (G.nd == 2) launch_k(KF_PBP_OUT, by, k_pbp_out<2>, CELLS(G.N), 0, s, G, X, v, scaled, alpha1, dt, dp, dT, z);
+  else launch_k(KF_PBP_OUT, by, k_pbp_out<3>, CELLS(G.N), 0, s, G, X, v, scaled, alpha1, dt, dp, dT, z);
 }
 
 // ---- explicit instantiations ---------------------------------------------------------------
@@ -567,6 +713,8 @@ void launch_pbp_out(const Grid& G, const double* X, const double* v, int scaled,
   template void launch_mg_smooth2<T>(const Grid&, const Level&, const T*, const T*, const T*, T*,   \
                                      hipStream_t);                                                   \
   template void launch_dense_matvec<T>(int, const double*, const T*, T*, hipStream_t);              \
+  template void launch_vcycle_coarse<T>(const Grid&, const Level*, int, const double*, const T*, T*, \
+                                        hipStream_t);                                                \
   template void launch_ell_apply_dot<T>(const Grid&, const Level&, const T*, T*, double*,           \
                                         const RedWS&, hipStream_t);                                  \
   template void launch_cg_update<T>(size_t, const double*, int, int, T*, const T*, T*, const T*,    \

@@ -33,8 +33,11 @@ constexpr int kMaxK = 72;          // maximum simultaneous sums (Krylov basis si
 
 struct RedWS {
   double* part = nullptr;          // kRedBlocks * kMaxK partials
-  unsigned int* count = nullptr;   // completion counter (returns to 0 after each use)
+  unsigned int* count = nullptr;   // unused (kept zero)
 };
+
+// out[k] = sum over b < nb of part[b*K + k], in block order (one block)
+void launch_finalize_sum(const RedWS& ws, int nb, int K, double* out, hipStream_t s);
 
 template <class T>
 void launch_dot(size_t n, const T* a, const T* b, double* out, const RedWS& w, hipStream_t s);
@@ -105,6 +108,25 @@ void launch_mg_smooth2(const Grid& G, const Level& L, const T* b, const T* x1, c
 template <class T>
 void launch_dense_matvec(int n, const double* A, const T* x, T* y, hipStream_t s);
 
+// coarse part of a V-cycle (levels of at most kCoarseMaxN cells) in one workgroup
+constexpr int kCoarseMaxN = 1024;
+constexpr int kCoarseThreads = 1024;
+constexpr int kMaxLevels = 12;
+struct CoarseArgs {
+  int nl, tot;
+  int n[kMaxLevels][3], stride[kMaxLevels][3], N[kMaxLevels], off[kMaxLevels];
+  int bc[3];
+  const void* diag[kMaxLevels];
+  const void* w[kMaxLevels][3];
+  const void* dinv[kMaxLevels];
+  const double* Ainv;   // dense inverse of the last level
+  const void* b0;       // right-hand side of the first fused level
+  void* x0;             // result on the first fused level
+};
+template <class T>
+void launch_vcycle_coarse(const Grid& G, const Level* lv, int nl, const double* Ainv, const T* b0,
+                          T* x0, hipStream_t s);
+
 // CG pieces: q = A p and out = p.q ; x += a p, r -= a q and out = r.r ; p = z + b p
 template <class T>
 void launch_ell_apply_dot(const Grid& G, const Level& L, const T* p, T* q, double* out,
@@ -127,5 +149,20 @@ void launch_pbp_rhsT(const Grid& G, const double* X, const double* v, int scaled
                      double dt, const double* dp, double* rhs_T, hipStream_t s);
 void launch_pbp_out(const Grid& G, const double* X, const double* v, int scaled, double alpha1,
                     double dt, const double* dp, const double* dT, double* z, hipStream_t s);
+
+// ---- transposed products (vjp.hip) -----------------------------------------------------
+// out = cU (dU/dX)^T w + cR (dR/dX)^T w at X (optionally each row multiplied by R(X));
+// scratch holds vjp_scratch_doubles(G) doubles
+size_t vjp_scratch_doubles(const Grid& G);
+void launch_vjp(const Grid& G, const double* X, const double* w, double cU, double cR, double* scratch,
+                int scaleR, double alpha2, double* out, hipStream_t s);
+// transposed preconditioner: rhs of the pressure solve (and of the thermal solve), the
+// completion of the pressure rhs after the thermal solve, and the output z = M^-T v
+// (scaled != 0: the input is v with w = v / R)
+void launch_pbpT_in(const Grid& G, const double* X, const double* v, int scaled, double alpha2,
+                    double dt, int thermal, double* rhs_p, double* rhs_T, hipStream_t s);
+void launch_pbpT_mid(const Grid& G, double dt, const double* t, double* rhs_p, hipStream_t s);
+void launch_pbpT_out(const Grid& G, const double* X, const double* v, int scaled, double alpha2,
+                     double dt, const double* sp, const double* t, double* z, hipStream_t s);
 
 }  // namespace jfnk

@@ -16,6 +16,7 @@
 // finite-difference product evaluates F at X + delta V with delta of eq. pert_old.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "probe.hpp"
 
 namespace jfnk {
 
@@ -54,7 +55,7 @@ struct Stencil {
 
   __device__ __forceinline__ T at(int var, Off o) const {
     double s;
-    int i = gidx(G, P, var, o, &s);
+    int i = gidx<ND>(G, P, var, o, &s);
     return ld(var, i, s);
   }
   __device__ __forceinline__ T rho(Off o) const { return at(0, o); }
@@ -217,7 +218,7 @@ template <int ND>
 __global__ void __launch_bounds__(kBlock) k_resid_value(Grid G, ResidArgs a) {
   int lin = blockIdx.x * blockDim.x + threadIdx.x;
   if (lin >= G.N) return;
-  Pos P = make_pos(G, lin);
+  Pos P = make_pos<ND>(G, lin);
   LoadVal<double> ld{a.X, G.N};
   double R[2 + ND], U[2 + ND], L[2 + ND];
   cell_R<ND>(G, P, ld, R);
@@ -238,7 +239,7 @@ template <int ND>
 __global__ void __launch_bounds__(kBlock) k_resid_tangent(Grid G, ResidArgs a) {
   int lin = blockIdx.x * blockDim.x + threadIdx.x;
   if (lin >= G.N) return;
-  Pos P = make_pos(G, lin);
+  Pos P = make_pos<ND>(G, lin);
   LoadDual ld{a.X, a.V, G.N};
   dual R[2 + ND], U[2 + ND];
   double L[2 + ND];
@@ -260,7 +261,7 @@ __global__ void __launch_bounds__(kBlock) k_resid_fd(Grid G, ResidArgs a) {
   const double xn2 = a.fd_norms[0], zn2 = a.fd_norms[1];
   double L[2 + ND];
   if (a.scaleL) {
-    Pos P0 = make_pos(G, lin);
+    Pos P0 = make_pos<ND>(G, lin);
     cell_L<ND>(G, P0, a.X, a.alpha1, L);
   }
   if (!(zn2 > 0.0)) {
@@ -270,7 +271,7 @@ __global__ void __launch_bounds__(kBlock) k_resid_fd(Grid G, ResidArgs a) {
   }
   const double lam = a.fd_lambda;
   const double delta = lam * (lam + sqrt(xn2) / sqrt(zn2));
-  Pos P = make_pos(G, lin);
+  Pos P = make_pos<ND>(G, lin);
   LoadShift ld{a.X, a.V, delta, G.N};
   double R[2 + ND], U[2 + ND];
   cell_R<ND>(G, P, ld, R);
@@ -289,7 +290,7 @@ __global__ void __launch_bounds__(kBlock) k_scale_LR(Grid G, const double* X, do
   // mode 0: out = in / S, mode 1: out = in * S, with S = L (which = 0) or R (which = 1)
   int lin = blockIdx.x * blockDim.x + threadIdx.x;
   if (lin >= G.N) return;
-  Pos P = make_pos(G, lin);
+  Pos P = make_pos<ND>(G, lin);
   double S[2 + ND];
   if (which == 0) cell_L<ND>(G, P, X, alpha, S);
   else cell_Rs<ND>(G, P, X, alpha, S);
@@ -305,14 +306,28 @@ static inline dim3 cells_grid(const Grid& G) { return dim3((G.N + kBlock - 1) / 
 
 void launch_resid(const Grid& G, const ResidArgs& a, int mode, hipStream_t s) {
   dim3 gr = cells_grid(G), bl(kBlock);
-  if (G.nd == 2) {
-    if (mode == 0) k_resid_value<2><<<gr, bl, 0, s>>>(G, a);
-    else if (mode == 1) k_resid_tangent<2><<<gr, bl, 0, s>>>(G, a);
-    else k_resid_fd<2><<<gr, bl, 0, s>>>(G, a);
+  // algorithmic bytes: every field read or written once (FP64)
+  const double nvN = 8.0 * (2 + G.nd) * G.N;
+  int fam;
+  double bytes;
+  if (mode == 0) {
+    fam = KF_RESID_VALUE;
+    bytes = nvN * (2 + (a.B ? 1 : 0) + (a.G0 ? 1 : 0));
+  } else if (mode == 1) {
+    fam = KF_RESID_TANGENT;
+    bytes = nvN * 3;
   } else {
-    if (mode == 0) k_resid_value<3><<<gr, bl, 0, s>>>(G, a);
-    else if (mode == 1) k_resid_tangent<3><<<gr, bl, 0, s>>>(G, a);
-    else k_resid_fd<3><<<gr, bl, 0, s>>>(G, a);
+    fam = KF_RESID_FD;
+    bytes = nvN * 4;
+  }
+  if (G.nd == 2) {
+    if (mode == 0) launch_k(fam, bytes, k_resid_value<2>, gr, bl, 0, s, G, a);
+    else if (mode == 1) launch_k(fam, bytes, k_resid_tangent<2>, gr, bl, 0, s, G, a);
+    else launch_k(fam, bytes, k_resid_fd<2>, gr, bl, 0, s, G, a);
+  } else {
+    if (mode == 0) launch_k(fam, bytes, k_resid_value<3>, gr, bl, 0, s, G, a);
+    else if (mode == 1) launch_k(fam, bytes, k_resid_tangent<3>, gr, bl, 0, s, G, a);
+    else launch_k(fam, bytes, k_resid_fd<3>, gr, bl, 0, s, G, a);
   }
 }
 

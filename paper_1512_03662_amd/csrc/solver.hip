@@ -16,6 +16,7 @@
 
 #include "../../include/jfnk.h"
 #include "kernels.hpp"
+#include "probe.hpp"
 
 using namespace jfnk;
 
@@ -76,6 +77,10 @@ struct jfnk_ctx {
   double *cg64[4] = {nullptr, nullptr, nullptr, nullptr};  // r, p, q, z
   float *cg32[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // r p q z b x
   int cg_its = 0;
+
+  // adjoint
+  double* vjps = nullptr;   // scratch of the transposed products
+  bool adj = false;         // FGMRES works on the transposed system
 };
 
 static std::string g_create_err;
@@ -322,12 +327,18 @@ void vcycle(jfnk_ctx* c, std::vector<Level>& lv, const double* Ainv, const T* r,
   int nl = (int)lv.size();
   auto B = [&](int l) -> const T* { return l == 0 ? r : (const T*)lv[l].b; };
   auto Xl = [&](int l) -> T* { return l == 0 ? z : (T*)lv[l].x; };
-  for (int l = 0; l + 1 < nl; ++l) {
+  // levels l0..nl-1 run in one single-workgroup kernel when they are small enough
+  int l0 = nl - 1;
+  const bool fused = lv[nl - 1].N <= kCoarseMaxN;
+  if (fused)
+    while (l0 > 0 && lv[l0 - 1].N <= kCoarseMaxN && nl - (l0 - 1) <= kMaxLevels) --l0;
+  for (int l = 0; l < l0; ++l) {
     launch_mg_presmooth<T>(G, lv[l], B(l), Xl(l), s);
     launch_mg_restrict_resid<T>(G, lv[l], B(l), Xl(l), (T*)lv[l + 1].b, lv[l + 1], s);
   }
-  launch_dense_matvec<T>(lv[nl - 1].N, Ainv, B(nl - 1), Xl(nl - 1), s);
-  for (int l = nl - 2; l >= 0; --l) {
+  if (fused) launch_vcycle_coarse<T>(G, &lv[l0], nl - l0, Ainv, B(l0), Xl(l0), s);
+  else launch_dense_matvec<T>(lv[nl - 1].N, Ainv, B(nl - 1), Xl(nl - 1), s);
+  for (int l = l0 - 1; l >= 0; --l) {
     launch_mg_prolong_smooth1<T>(G, lv[l], B(l), Xl(l), Xl(l + 1), lv[l + 1], (T*)lv[l].t1,
                                  (T*)lv[l].t2, s);
     launch_mg_smooth2<T>(G, lv[l], B(l), (const T*)lv[l].t1, (const T*)lv[l].t2, Xl(l), s);
@@ -413,9 +424,37 @@ void precond(jfnk_ctx* c, const double* X, const double* v, int scaled, double* 
   check_launch();
 }
 
+// Z = M^-T v (scaled = 1: v is a scaled basis vector of the transposed system, w = R^-1 v)
+void precond_T(jfnk_ctx* c, const double* X, const double* v, int scaled, double* z) {
+  const Grid& G = c->G;
+  hipStream_t s = c->stream;
+  const jfnk_opts& o = c->opts;
+  if (o.precond == JFNK_PC_NONE) {
+    if (scaled) launch_scale_LR(G, X, o.alpha1, 0, v, z, 0, s);
+    else copy_d2d(c, z, v, c->n * sizeof(double));
+    return;
+  }
+  const bool thermal = (o.precond == JFNK_PC_SOUND_THERMAL);
+  launch_pbpT_in(G, X, v, scaled, o.alpha2, c->dt, thermal ? 1 : 0, c->rhs_p, c->rhs_T, s);
+  const double* t = nullptr;
+  if (thermal) {
+    ell_solve(c, 1, c->rhs_T, c->dT);
+    launch_pbpT_mid(G, c->dt, c->dT, c->rhs_p, s);
+    t = c->dT;
+  }
+  ell_solve(c, 0, c->rhs_p, c->dp);
+  launch_pbpT_out(G, X, v, scaled, o.alpha2, c->dt, c->dp, t, z, s);
+  check_launch();
+}
+
 // out = L^-1 J z at X (scaled operator of eq. jacobian_system_norm applied to an unscaled z)
 void apply_J(jfnk_ctx* c, const double* X, const double* z, double* out) {
   const Grid& G = c->G;
+  if (c->adj) {
+    // transposed system: out = R J^T z
+    launch_vjp(G, X, z, 1.0 / c->dt, -c->prob.theta, c->vjps, 1, c->opts.alpha2, out, c->stream);
+    return;
+  }
   ResidArgs a;
   a.X = X;
   a.V = z;
@@ -440,9 +479,11 @@ struct GmresOut {
   bool converged = false;
 };
 
-// Flexible GMRES(m) on (L^-1 J R) y = rhs with rhs = -L^-1 F (in W), right-preconditioned;
-// the directions Z_j are unscaled state increments, so dX = sum_j y_j Z_j.
-GmresOut fgmres(jfnk_ctx* c, const double* X, double beta0) {
+// Flexible GMRES(m) on (L^-1 J R) y = rhs with rhs = sign * W (W = L^-1 F, sign = -1),
+// right-preconditioned; the directions Z_j are unscaled state increments, so
+// dX = sum_j y_j Z_j.  With c->adj the same loop solves the transposed system
+// (R J^T L^-1) y = W with the transposed preconditioner (sign = +1).
+GmresOut fgmres(jfnk_ctx* c, const double* X, double beta0, double sign) {
   const jfnk_opts& o = c->opts;
   hipStream_t s = c->stream;
   const size_t n = c->n;
@@ -457,14 +498,14 @@ GmresOut fgmres(jfnk_ctx* c, const double* X, double beta0) {
     double beta;
     if (first) {
       beta = beta0;
-      // V_0 = -W / beta
+      // V_0 = sign W / beta
       launch_fill(n, 0.0, c->V, s);
-      launch_axpy(n, -1.0 / beta, c->W, c->V, s);
+      launch_axpy(n, sign / beta, c->W, c->V, s);
     } else {
-      // r = -L^-1 F - L^-1 J dX
+      // r = sign W - A dX
       apply_J(c, X, c->dX, c->W2);
       launch_fill(n, 0.0, c->V, s);
-      launch_axpy(n, -1.0, c->W, c->V, s);
+      launch_axpy(n, sign, c->W, c->V, s);
       launch_axpy(n, -1.0, c->W2, c->V, s);
       launch_dot<double>(n, c->V, c->V, c->scal + S_TMP, c->red, s);
       pull(c, S_TMP, 1);
@@ -485,7 +526,8 @@ GmresOut fgmres(jfnk_ctx* c, const double* X, double beta0) {
       double* Vj = c->V + (size_t)j * n;
       double* Zj = c->Z + (size_t)j * n;
       double* w = c->V + (size_t)(j + 1) * n;
-      precond(c, X, Vj, 1, Zj);
+      if (c->adj) precond_T(c, X, Vj, 1, Zj);
+      else precond(c, X, Vj, 1, Zj);
       apply_J(c, X, Zj, w);
       const int K = j + 1;
       launch_multidot(n, c->V, n, K, w, c->scal + S_H1, c->red, s);
@@ -584,7 +626,7 @@ int implicit_step(jfnk_ctx* c, double* X, double dt, jfnk_step_stats* st) {
     double dxmax = 0.0;
     if (fn > 0.0) {
       if (o.precond != JFNK_PC_NONE) ell_setup(c, X, dt);
-      GmresOut go = fgmres(c, X, fn);
+      GmresOut go = fgmres(c, X, fn, -1.0);
       S.gmres_its += go.iters;
       launch_scaled_maxabs(G, X, c->dX, o.alpha2, c->scal + S_DXMAX, c->red, s);
       launch_axpy(c->n, 1.0, c->dX, X, s);
@@ -603,6 +645,55 @@ int implicit_step(jfnk_ctx* c, double* X, double dt, jfnk_step_stats* st) {
   S.cg_its = c->cg_its;
   if (st) *st = S;
   if (status != JFNK_OK) c->err = "Newton did not converge within newton_max iterations";
+  return status;
+}
+
+// Adjoint of one implicit step: lam solves J^T lam = gbar at X^{n+1}; returns
+// dL/dX^n = (dU/dX|_{X^n})^T lam / dt + (1 - theta) (dR/dX|_{X^n})^T lam.
+struct AdjGuard {
+  jfnk_ctx* c;
+  explicit AdjGuard(jfnk_ctx* cc) : c(cc) { c->adj = true; }
+  ~AdjGuard() { c->adj = false; }
+};
+
+int adjoint_step(jfnk_ctx* c, const double* Xn1, const double* Xn, double dt, const double* gbar,
+                 double* gbar_n, jfnk_step_stats* st) {
+  const jfnk_opts& o = c->opts;
+  const Grid& G = c->G;
+  hipStream_t s = c->stream;
+  if (!(dt > 0.0)) throw InvErr("dt must be positive");
+  jfnk_step_stats S{};
+  S.dt = dt;
+  c->dt = dt;
+  c->cg_its = 0;
+  int status = JFNK_OK;
+  // rhs of the scaled transposed system: R gbar (R at X^{n+1})
+  launch_scale_LR(G, Xn1, o.alpha2, 1, gbar, c->W, 1, s);
+  launch_dot<double>(c->n, c->W, c->W, c->scal + S_FN2, c->red, s);
+  pull(c, S_FN2, 1);
+  double bn = std::sqrt(c->hscal[S_FN2]);
+  if (!std::isfinite(bn)) throw FiniteErr("non-finite adjoint seed");
+  S.f0_norm = bn;
+  if (bn == 0.0) {
+    launch_fill(c->n, 0.0, c->dX, s);
+    S.converged = 1;
+  } else {
+    AdjGuard guard(c);
+    if (o.precond != JFNK_PC_NONE) ell_setup(c, Xn1, dt);
+    GmresOut go = fgmres(c, Xn1, bn, 1.0);
+    S.gmres_its = go.iters;
+    S.converged = go.converged ? 1 : 0;
+    if (!go.converged) {
+      status = JFNK_E_GMRES_NOCONV;
+      c->err = "adjoint GMRES did not reach gmres_eta within gmres_maxit iterations";
+    }
+  }
+  // dL/dX^n from lam (in dX)
+  launch_vjp(G, Xn, c->dX, 1.0 / dt, 1.0 - c->prob.theta, c->vjps, 0, o.alpha2, gbar_n, s);
+  check_launch();
+  S.newton_its = 0;
+  S.cg_its = c->cg_its;
+  if (st) *st = S;
   return status;
 }
 
@@ -646,6 +737,7 @@ void create(jfnk_ctx* c) {
   for (int i = 0; i < 6; ++i) c->cg32[i] = dalloc<float>(c, N);
   build_hierarchy(c, c->ops[0], want32);
   build_hierarchy(c, c->ops[1], want32);
+  c->vjps = dalloc<double>(c, vjp_scratch_doubles(G));
   sync(c);
 }
 
@@ -846,18 +938,55 @@ double jfnk_cfl_dt(jfnk_ctx* c, const double* X, double cfl) {
   }
 }
 
-int jfnk_vjp(jfnk_ctx* c, const double*, const double*, double*) {
-  if (c) c->err = "not built yet";
-  return JFNK_E_INVALID;
+int jfnk_vjp(jfnk_ctx* c, const double* X, const double* w, double* JTw) {
+  if (!c) return JFNK_E_INVALID;
+  ABI_BEGIN
+  if (!X || !w || !JTw) throw InvErr("null array");
+  if (!c->have_state) throw InvErr("jfnk_set_state_n must be called first");
+  launch_vjp(c->G, X, w, 1.0 / c->dt, -c->prob.theta, c->vjps, 0, c->opts.alpha2, JTw, c->stream);
+  check_launch();
+  return JFNK_OK;
+  ABI_END(c)
 }
-int jfnk_vjp_prev(jfnk_ctx* c, const double*, const double*, double*) {
-  if (c) c->err = "not built yet";
-  return JFNK_E_INVALID;
+
+int jfnk_vjp_prev(jfnk_ctx* c, const double* Xn, const double* lam, double* out) {
+  if (!c) return JFNK_E_INVALID;
+  ABI_BEGIN
+  if (!Xn || !lam || !out) throw InvErr("null array");
+  if (!c->have_state) throw InvErr("jfnk_set_state_n must be called first");
+  launch_vjp(c->G, Xn, lam, -1.0 / c->dt, -(1.0 - c->prob.theta), c->vjps, 0, c->opts.alpha2, out,
+             c->stream);
+  check_launch();
+  return JFNK_OK;
+  ABI_END(c)
 }
-int jfnk_adjoint_step(jfnk_ctx* c, const double*, const double*, double, const double*, double*,
-                      jfnk_step_stats*) {
-  if (c) c->err = "not built yet";
-  return JFNK_E_INVALID;
+
+int jfnk_probe_enable(int32_t on) {
+  probe_enable(on != 0);
+  return JFNK_OK;
+}
+
+int jfnk_probe_count(void) { return KF_COUNT; }
+
+const char* jfnk_probe_name(int32_t k) { return (k >= 0 && k < KF_COUNT) ? kFamNames[k] : ""; }
+
+int jfnk_probe_read(int32_t k, double* ms, int64_t* launches, double* bytes) {
+  if (!ms || !launches || !bytes) return JFNK_E_INVALID;
+  long long n = 0;
+  if (!probe_read(k, ms, &n, bytes)) return JFNK_E_INVALID;
+  *launches = n;
+  return JFNK_OK;
+}
+
+int jfnk_adjoint_step(jfnk_ctx* c, const double* Xn1, const double* Xn, double dt,
+                      const double* gbar_n1, double* gbar_n, jfnk_step_stats* st) {
+  if (!c) return JFNK_E_INVALID;
+  ABI_BEGIN
+  if (!Xn1 || !Xn || !gbar_n1 || !gbar_n) throw InvErr("null array");
+  int r = adjoint_step(c, Xn1, Xn, dt, gbar_n1, gbar_n, st);
+  sync(c);
+  return r;
+  ABI_END(c)
 }
 
 }  // extern "C"

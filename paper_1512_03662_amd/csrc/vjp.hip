@@ -1,0 +1,659 @@
+// Transposed Jacobian products of the residual, J^T w, in gather form (no atomics, so the
+// result is deterministic), and the transposed physics-based preconditioner used by the
+// adjoint of an implicit step.
+//
+// F = cU U(X) + cR R(X) - b with the staggered operator R of residual.hip.  The adjoint is
+// taken with respect to a ghost-padded copy of X (3 ghost layers per side, ghost values
+// treated as independent inputs), then folded back through the ghost rules (wrap, even
+// mirror, odd mirror with zero on wall faces):
+//   stage A: adjoint of the mass flux f_d on every padded face, from w (R_rho, the energy
+//            flux g = f e*, the momentum fluxes through their carrying mass flux);
+//   stage B: adjoint of every padded input (rho, e, u_d) gathered from the local terms that
+//            read it, re-evaluating their partial derivatives (upwind choices frozen);
+//   fold:    X_bar = cU (dU/dX)^T w + sum over the padded copies of each stored value.
+// Terms whose adjoint weight is exactly zero are skipped, so only terms that the forward
+// evaluates for some interior row are evaluated, with the same (in-range) ghost accesses.
+#include "common.hpp"
+#include "kernels.hpp"
+#include "probe.hpp"
+
+namespace jfnk {
+
+struct PadGrid {
+  int P[3];       // padded extents (n + 6 on used axes, 1 otherwise)
+  int pstride[3];
+  int PN;
+};
+
+static PadGrid make_pad(const Grid& G) {
+  PadGrid p;
+  for (int d = 0; d < 3; ++d) p.P[d] = (d < G.nd) ? G.n[d] + 6 : 1;
+  p.pstride[0] = 1;
+  p.pstride[1] = p.P[0];
+  p.pstride[2] = p.P[0] * p.P[1];
+  p.PN = p.P[0] * p.P[1] * p.P[2];
+  return p;
+}
+
+// derivative of the upwind van Leer value w.r.t. its four arguments (qm2, qm1, q0, qp1)
+__device__ __forceinline__ double upwind_grad(double qm2, double qm1, double q0, double qp1, double w,
+                                              double* g) {
+  if (w >= 0.0) {
+    double a = qm1 - qm2, b = q0 - qm1;
+    double v = 0.0, da = 0.0, db = 0.0;
+    if (a * b > 0.0) {
+      double s = a + b;
+      v = 2.0 * a * b / s;
+      da = 2.0 * b * b / (s * s);
+      db = 2.0 * a * a / (s * s);
+    }
+    g[0] = -0.5 * da;
+    g[1] = 1.0 + 0.5 * (da - db);
+    g[2] = 0.5 * db;
+    g[3] = 0.0;
+    return qm1 + 0.5 * v;
+  }
+  double a = q0 - qm1, b = qp1 - q0;
+  double v = 0.0, da = 0.0, db = 0.0;
+  if (a * b > 0.0) {
+    double s = a + b;
+    v = 2.0 * a * b / s;
+    da = 2.0 * b * b / (s * s);
+    db = 2.0 * a * a / (s * s);
+  }
+  g[0] = 0.0;
+  g[1] = 0.5 * da;
+  g[2] = 1.0 - 0.5 * (da - db);
+  g[3] = -0.5 * db;
+  return q0 - 0.5 * v;
+}
+
+// Accesses at logical (possibly ghost) positions; same ghost rules as the forward.
+template <int ND>
+struct Acc {
+  const Grid& G;
+  const double* X;
+  const double* w;   // adjoint seed (interior rows)
+  double cR;
+  __device__ Acc(const Grid& g, const double* x, const double* ww, double c) : G(g), X(x), w(ww), cR(c) {}
+
+  __device__ __forceinline__ double x(int var, const int* c) const {
+    double sign = 1.0;
+    int idx = 0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      int src;
+      if (var == 2 + d) {
+        double sd;
+        src = ghost_normal(c[d], G.n[d], G.bc[d], &sd);
+        sign *= sd;
+      } else {
+        src = ghost_even(c[d], G.n[d], G.bc[d]);
+      }
+      // the active terms only read logical positions in [-3, n+2], where the ghost rules
+      // already land inside the grid; the clamp keeps every read in bounds regardless
+      src = min(max(src, 0), G.n[d] - 1);
+      idx += src * G.stride[d];
+    }
+    return sign * X[var * G.N + idx];
+  }
+  // seed of row (var, c) of the R part: zero outside the grid and on wall-normal wall faces
+  __device__ __forceinline__ double W(int var, const int* c) const {
+    int idx = 0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      if (c[d] < 0 || c[d] >= G.n[d]) return 0.0;
+      idx += c[d] * G.stride[d];
+    }
+    if (var >= 2) {
+      int d = var - 2;
+      if (G.bc[d] == 1 && c[d] == 0) return 0.0;
+    }
+    return cR * w[var * G.N + idx];
+  }
+  __device__ __forceinline__ double rho(const int* c) const { return x(0, c); }
+  __device__ __forceinline__ double e(const int* c) const { return x(1, c); }
+  __device__ __forceinline__ double u(int d, const int* c) const { return x(2 + d, c); }
+  __device__ __forceinline__ double p(const int* c) const {
+    return (G.gamma - 1.0) * rho(c) * e(c);
+  }
+};
+
+#define SH(dst, src, d, k)           \
+  int dst[3] = {src[0], src[1], src[2]}; \
+  dst[d] += (k)
+
+// mass flux f_d at the low-d face of logical cell c
+template <int ND>
+__device__ __forceinline__ double mflux(const Acc<ND>& A, int d, const int* c) {
+  SH(m2, c, d, -2);
+  SH(m1, c, d, -1);
+  SH(p1, c, d, 1);
+  double w = A.u(d, c);
+  return w * upwind(A.rho(m2), A.rho(m1), A.rho(c), A.rho(p1), w);
+}
+
+// ---- stage A: adjoint of f_d on padded faces ---------------------------------------------
+template <int ND>
+__global__ void __launch_bounds__(kBlock) k_vjp_stageA(Grid G, PadGrid PG, const double* X, const double* w,
+                                                       double cR, double* fbar) {
+  int pl = blockIdx.x * kBlock + threadIdx.x;
+  if (pl >= PG.PN) return;
+  int c[3];
+  c[0] = pl % PG.P[0] - 3;
+  int r = pl / PG.P[0];
+  c[1] = (ND >= 2) ? r % PG.P[1] - 3 : 0;
+  c[2] = (ND == 3) ? r / PG.P[1] - 3 : 0;
+  Acc<ND> A(G, X, w, cR);
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    const double ih = G.idx[d];
+    SH(cm, c, d, -1);
+    double fb = (A.W(0, c) - A.W(0, cm)) * ih;  // from R_rho
+    double gb = (A.W(1, c) - A.W(1, cm)) * ih;  // energy flux g_d = f_d e*
+    if (gb != 0.0) {
+      SH(m2, c, d, -2);
+      SH(p1, c, d, 1);
+      double es = upwind(A.e(m2), A.e(cm), A.e(c), A.e(p1), A.u(d, c));
+      fb += gb * es;
+    }
+    // Phi_dd at the centres of c and c - e_d (u_d carried along d)
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      SH(cc, c, d, -k);  // centre cc lies between faces cc and cc + e_d
+      SH(cp, cc, d, 1);
+      double Pb = (A.W(2 + d, cp) - A.W(2 + d, cc)) * ih;
+      if (Pb != 0.0) {
+        double m = 0.5 * (mflux<ND>(A, d, cc) + mflux<ND>(A, d, cp));
+        SH(um1, cc, d, -1);
+        SH(up2, cc, d, 2);
+        double us = upwind(A.u(d, um1), A.u(d, cc), A.u(d, cp), A.u(d, up2), m);
+        fb += 0.5 * Pb * us;
+      }
+    }
+    // Phi_ed (u_e carried along d, mass flux mean of f_d[c' - e_e] and f_d[c']) at c' = c, c + e_e
+#pragma unroll
+    for (int e = 0; e < ND; ++e) {
+      if (e == d) continue;
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        SH(ce, c, e, k);
+        SH(ced, ce, d, -1);
+        double Pb = (A.W(2 + e, ce) - A.W(2 + e, ced)) * ih;
+        if (Pb != 0.0) {
+          SH(cee, ce, e, -1);
+          double m = 0.5 * (mflux<ND>(A, d, cee) + mflux<ND>(A, d, ce));
+          SH(d2, ce, d, -2);
+          SH(dp, ce, d, 1);
+          double us = upwind(A.u(e, d2), A.u(e, ced), A.u(e, ce), A.u(e, dp), m);
+          fb += 0.5 * Pb * us;
+        }
+      }
+    }
+    fbar[(size_t)d * PG.PN + pl] = fb;
+  }
+}
+
+// ---- stage B: adjoint of every padded input ----------------------------------------------
+template <int ND>
+__global__ void __launch_bounds__(kBlock) k_vjp_stageB(Grid G, PadGrid PG, const double* X, const double* w,
+                                                       double cR, const double* fbar, double* xbar) {
+  int pl = blockIdx.x * kBlock + threadIdx.x;
+  if (pl >= PG.PN) return;
+  int c[3];
+  c[0] = pl % PG.P[0] - 3;
+  int r = pl / PG.P[0];
+  c[1] = (ND >= 2) ? r % PG.P[1] - 3 : 0;
+  c[2] = (ND == 3) ? r / PG.P[1] - 3 : 0;
+  Acc<ND> A(G, X, w, cR);
+  const double gm1 = G.gamma - 1.0;
+  double rb = 0.0, eb = 0.0, ub[3] = {0.0, 0.0, 0.0};
+  auto padded = [&](const int* q) -> int {  // padded index or -1 outside the padded grid
+    int idx = 0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      int pq = q[d] + 3;
+      if (pq < 0 || pq >= PG.P[d]) return -1;
+      idx += pq * PG.pstride[d];
+    }
+    return idx;
+  };
+  double pbar = 0.0;
+  // pressure: p in -p div u (row E at c) and in the momentum pressure gradients
+  {
+    double WE = A.W(1, c);
+    if (WE != 0.0) {
+      double D = 0.0;
+#pragma unroll
+      for (int d = 0; d < ND; ++d) {
+        SH(cp, c, d, 1);
+        D += (A.u(d, cp) - A.u(d, c)) * G.idx[d];
+      }
+      pbar -= WE * D;
+    }
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      SH(cp, c, d, 1);
+      pbar += (A.W(2 + d, cp) - A.W(2 + d, c)) * G.idx[d];
+      // gravity: rho_f g_d on the faces c and c + e_d
+      rb += 0.5 * G.g[d] * (A.W(2 + d, c) + A.W(2 + d, cp));
+    }
+  }
+  if (pbar != 0.0) {
+    rb += pbar * gm1 * A.e(c);
+    eb += pbar * gm1 * A.rho(c);
+  }
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    const double ih = G.idx[d];
+    // mass flux faces f = p + k e_d (k = -1..2) read rho at c through the reconstruction
+#pragma unroll
+    for (int k = -1; k <= 2; ++k) {
+      SH(f, c, d, k);
+      int pf = padded(f);
+      if (pf < 0) continue;
+      double fb = fbar[(size_t)d * PG.PN + pf];
+      if (fb == 0.0) continue;
+      SH(m2, f, d, -2);
+      SH(m1, f, d, -1);
+      SH(p1, f, d, 1);
+      double wv = A.u(d, f);
+      double g[4];
+      upwind_grad(A.rho(m2), A.rho(m1), A.rho(f), A.rho(p1), wv, g);
+      rb += fb * wv * g[2 - k];  // c = f - k is argument (c - (f - 2)) = 2 - k
+    }
+    // energy flux g = f e*: e* reads e at c from faces f = c + k e_d
+#pragma unroll
+    for (int k = -1; k <= 2; ++k) {
+      SH(f, c, d, k);
+      SH(fm, f, d, -1);
+      double gb = (A.W(1, f) - A.W(1, fm)) * ih;
+      if (gb == 0.0) continue;
+      SH(m2, f, d, -2);
+      SH(p1, f, d, 1);
+      double wv = A.u(d, f);
+      double fl = wv * upwind(A.rho(m2), A.rho(fm), A.rho(f), A.rho(p1), wv);
+      double g[4];
+      upwind_grad(A.e(m2), A.e(fm), A.e(f), A.e(p1), wv, g);
+      eb += gb * fl * g[2 - k];
+    }
+    // conduction q_d on faces c and c + e_d (not on wall faces)
+    if (G.chi_model != 0) {
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        SH(f, c, d, k);
+        if (G.bc[d] == 1 && (f[d] == 0 || f[d] == G.n[d])) continue;
+        SH(fm, f, d, -1);
+        double qb = (A.W(1, fm) - A.W(1, f)) * ih;
+        if (qb == 0.0) continue;
+        double Tm = gm1 * A.e(fm), T0 = gm1 * A.e(f);
+        double chm, ch0, dchm, dch0;
+        if (G.chi_model == 1) {
+          chm = ch0 = G.chi0;
+          dchm = dch0 = 0.0;
+        } else {
+          double p = G.chi_exp;
+          chm = G.chi0 * powr(Tm * G.chi_tref_inv, p);
+          ch0 = G.chi0 * powr(T0 * G.chi_tref_inv, p);
+          dchm = p * chm / Tm;
+          dch0 = p * ch0 / T0;
+        }
+        double chif = 0.5 * (chm + ch0);
+        double dT = T0 - Tm;
+        // q = chif (T0 - Tm) ih; c is the face's cell (k = 0: T0) or its lower cell (k = 1: Tm)
+        double dq_dT = (k == 0) ? (0.5 * dch0 * dT + chif) * ih : (0.5 * dchm * dT - chif) * ih;
+        eb += qb * dq_dT * gm1;
+      }
+    }
+    // u_d at face c: its own mass flux f_d[c] = u_d rho*
+    {
+      int pc = padded(c);
+      double fb = fbar[(size_t)d * PG.PN + pc];
+      if (fb != 0.0) {
+        SH(m2, c, d, -2);
+        SH(m1, c, d, -1);
+        SH(p1, c, d, 1);
+        ub[d] += fb * upwind(A.rho(m2), A.rho(m1), A.rho(c), A.rho(p1), A.u(d, c));
+      }
+    }
+    // u_d in div u of rows E at c and c - e_d
+    {
+      SH(cm, c, d, -1);
+      double a0 = A.W(1, c), a1 = A.W(1, cm);
+      if (a0 != 0.0) ub[d] += a0 * A.p(c) * ih;
+      if (a1 != 0.0) ub[d] -= a1 * A.p(cm) * ih;
+    }
+    // Phi_dd at centres cc = c - k e_d (k = -1..2): u* reads u_d[cc-1..cc+2]
+#pragma unroll
+    for (int k = -1; k <= 2; ++k) {
+      SH(cc, c, d, -k);
+      SH(cp, cc, d, 1);
+      double Pb = (A.W(2 + d, cp) - A.W(2 + d, cc)) * ih;
+      if (Pb == 0.0) continue;
+      double m = 0.5 * (mflux<ND>(A, d, cc) + mflux<ND>(A, d, cp));
+      SH(um1, cc, d, -1);
+      SH(up2, cc, d, 2);
+      double g[4];
+      upwind_grad(A.u(d, um1), A.u(d, cc), A.u(d, cp), A.u(d, up2), m, g);
+      ub[d] += Pb * m * g[k + 1];  // c = cc + k: argument index k + 1
+    }
+    // Phi_de (u_d carried along e) at edges ce = c - k e_e (k = -2..1): u* reads
+    // u_d[ce - 2e_e .. ce + e_e]
+#pragma unroll
+    for (int e = 0; e < ND; ++e) {
+      if (e == d) continue;
+      const double ihe = G.idx[e];
+#pragma unroll
+      for (int k = -2; k <= 1; ++k) {
+        SH(ce, c, e, -k);
+        SH(cem, ce, e, -1);
+        double Pb = (A.W(2 + d, ce) - A.W(2 + d, cem)) * ihe;
+        if (Pb == 0.0) continue;
+        SH(ced, ce, d, -1);
+        double m = 0.5 * (mflux<ND>(A, e, ced) + mflux<ND>(A, e, ce));
+        SH(em2, ce, e, -2);
+        SH(ep1, ce, e, 1);
+        double g[4];
+        upwind_grad(A.u(d, em2), A.u(d, cem), A.u(d, ce), A.u(d, ep1), m, g);
+        ub[d] += Pb * m * g[k + 2];  // c = ce + k: argument index k + 2
+      }
+    }
+  }
+  xbar[pl] = rb;
+  xbar[(size_t)PG.PN + pl] = eb;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) xbar[(size_t)(2 + d) * PG.PN + pl] = ub[d];
+}
+
+// ---- fold: interior adjoint = U part + sum of padded copies ------------------------------
+// padded logical positions that hold a copy of stored index i on an axis, with signs
+__device__ __forceinline__ int preimages(int i, int n, int bc, bool normal, int* pos, double* sg) {
+  int k = 0;
+  if (bc == 0) {
+    pos[k] = i; sg[k++] = 1.0;
+    if (i - n >= -3) { pos[k] = i - n; sg[k++] = 1.0; }
+    if (i + n <= n + 2) { pos[k] = i + n; sg[k++] = 1.0; }
+    return k;
+  }
+  if (!normal) {
+    pos[k] = i; sg[k++] = 1.0;
+    if (-1 - i >= -3) { pos[k] = -1 - i; sg[k++] = 1.0; }
+    if (2 * n - 1 - i <= n + 2) { pos[k] = 2 * n - 1 - i; sg[k++] = 1.0; }
+    return k;
+  }
+  if (i >= 1) { pos[k] = i; sg[k++] = 1.0; }
+  if (i >= 1 && -i >= -3) { pos[k] = -i; sg[k++] = -1.0; }
+  if (i >= 1 && 2 * n - i <= n + 2) { pos[k] = 2 * n - i; sg[k++] = -1.0; }
+  return k;
+}
+
+template <int ND>
+__global__ void __launch_bounds__(kBlock) k_vjp_fold(Grid G, PadGrid PG, const double* X, const double* w,
+                                                     double cU, const double* xbar, int scaleR, double alpha2,
+                                                     double* out) {
+  int lin = blockIdx.x * kBlock + threadIdx.x;
+  if (lin >= G.N) return;
+  Pos P = make_pos<ND>(G, lin);
+  const int N = G.N;
+  double res[2 + ND];
+  // U part: (dU/dX)^T (cU w) with U = (rho, rho e, rho_f u_d), rho_f the face mean
+  {
+    const double rho = X[lin], e = X[N + lin];
+    double r0 = w[lin] + e * w[N + lin];
+    double r1 = rho * w[N + lin];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      double s;
+      int im = gidx<ND>(G, P, 0, shift(off0(), d, -1), &s);
+      double rf = 0.5 * (X[im] + rho);
+      double wd = w[(2 + d) * N + lin];
+      double ud = X[(2 + d) * N + lin];
+      res[2 + d] = cU * rf * wd;
+      r0 += 0.5 * ud * wd;
+      if (G.bc[d] == 1 && P.c[d] == 0) r0 += 0.5 * ud * wd;  // mirror ghost rho[-1] = rho[0]
+      // face c + e_d reads rho[c] as its lower cell
+      bool has_up = !(G.bc[d] == 1 && P.c[d] == G.n[d] - 1);
+      if (has_up) {
+        int ip = (P.c[d] == G.n[d] - 1) ? lin - (G.n[d] - 1) * G.stride[d] : lin + G.stride[d];
+        r0 += 0.5 * X[(2 + d) * N + ip] * w[(2 + d) * N + ip];
+      }
+    }
+    res[0] = cU * r0;
+    res[1] = cU * r1;
+  }
+  // R part: sum over padded copies
+#pragma unroll
+  for (int var = 0; var < 2 + ND; ++var) {
+    int pos[3][3];
+    double sg[3][3];
+    int cnt[3] = {1, 1, 1};
+    pos[1][0] = pos[2][0] = 0;
+    sg[1][0] = sg[2][0] = 1.0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) cnt[d] = preimages(P.c[d], G.n[d], G.bc[d], var == 2 + d, pos[d], sg[d]);
+    double acc = 0.0;
+    for (int a = 0; a < cnt[0]; ++a)
+      for (int b = 0; b < cnt[1]; ++b)
+        for (int cc = 0; cc < cnt[2]; ++cc) {
+          int pl = (pos[0][a] + 3) + (pos[1][b] + (ND >= 2 ? 3 : 0)) * PG.pstride[1];
+          if (ND == 3) pl += (pos[2][cc] + 3) * PG.pstride[2];
+          double s = sg[0][a] * sg[1][b] * sg[2][cc];
+          acc += s * xbar[(size_t)var * PG.PN + pl];
+        }
+    res[var] += acc;
+  }
+  if (scaleR) {
+    const double k = G.gamma * (G.gamma - 1.0);
+    const double e0 = X[N + lin];
+    const double cs0 = sqrt(k * e0);
+    res[0] *= X[lin];
+    res[1] *= e0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      double s;
+      int im = gidx<ND>(G, P, 1, shift(off0(), d, -1), &s);
+      double csf = 0.5 * (sqrt(k * X[N + im]) + cs0);
+      res[2 + d] *= fmax(fabs(X[(2 + d) * N + lin]), alpha2 * csf);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 2 + ND; ++v) out[v * N + lin] = res[v];
+}
+
+// ---- transposed physics-based preconditioner ---------------------------------------------
+// The forward map r -> z is: F_V = dV/dU r; dp = A_p^-1 (F_p/(Gamma1 p)); de from the
+// identity (sound) or dT = A_T^-1 (rho F_e + (dp/dt - F_p)/Gamma1), de = c_v dT (thermal);
+// du = dt (F_u - grad dp / rho_f); drho from the linearised EOS.  Its transpose applies the
+// transposed pointwise maps in reverse order around the same (symmetric) solves.
+
+// adjoint input w of one cell (w = v / R(X) when scaled) and the EOS factors
+template <int ND>
+struct CellT {
+  double rho, e, dpdr, dpde, wr, we;
+};
+
+template <int ND>
+__device__ __forceinline__ double rscale_u(const Grid& G, const Pos& P, const double* X, int d,
+                                           double alpha2) {
+  const double k = G.gamma * (G.gamma - 1.0);
+  double s;
+  int im = gidx<ND>(G, P, 1, shift(off0(), d, -1), &s);
+  double csf = 0.5 * (sqrt(k * X[G.N + im]) + sqrt(k * X[G.N + P.lin]));
+  return fmax(fabs(X[(2 + d) * G.N + P.lin]), alpha2 * csf);
+}
+
+// w_d at face lin of axis d (divided by R_u there when scaled)
+template <int ND>
+__device__ __forceinline__ double w_face(const Grid& G, const double* X, const double* v, int scaled,
+                                         double alpha2, int d, int lin) {
+  double wv = v[(2 + d) * G.N + lin];
+  if (scaled) {
+    Pos Q = make_pos<ND>(G, lin);
+    wv /= rscale_u<ND>(G, Q, X, d, alpha2);
+  }
+  return wv;
+}
+
+// transposed face gradient: sum over the faces of c of a_d[f] d(grad dp)[f]/d dp[c] with
+// grad dp[f] = (dp[f] - dp[f-1])/(rho_f dx_d), zero on wall faces
+template <int ND>
+__device__ __forceinline__ double gradT(const Grid& G, const Pos& P, const double* X, const double* v,
+                                        int scaled, double alpha2) {
+  double acc = 0.0;
+  const int N = G.N;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    double s;
+    // own face c: + a[c]/(rho_f[c] dx)
+    if (!(G.bc[d] == 1 && P.c[d] == 0)) {
+      int im = gidx<ND>(G, P, 0, shift(off0(), d, -1), &s);
+      double rf = 0.5 * (X[im] + X[P.lin]);
+      acc += w_face<ND>(G, X, v, scaled, alpha2, d, P.lin) / (rf * G.dx[d]);
+    }
+    // upper face c + e_d: - a[c+e]/(rho_f[c+e] dx)
+    bool top = (P.c[d] == G.n[d] - 1);
+    if (!(G.bc[d] == 1 && top)) {
+      int ip = top ? P.lin - (G.n[d] - 1) * G.stride[d] : P.lin + G.stride[d];
+      double rf = 0.5 * (X[P.lin] + X[ip]);
+      if (!(G.bc[d] == 1 && top)) acc -= w_face<ND>(G, X, v, scaled, alpha2, d, ip) / (rf * G.dx[d]);
+    }
+    (void)N;
+  }
+  return acc;
+}
+
+template <int ND>
+__global__ void __launch_bounds__(kBlock) k_pbpT_in(Grid G, const double* X, const double* v, int scaled,
+                                                    double alpha2, double dt, int thermal, double* rhs_p,
+                                                    double* rhs_T) {
+  int lin = blockIdx.x * kBlock + threadIdx.x;
+  if (lin >= G.N) return;
+  Pos P = make_pos<ND>(G, lin);
+  const double gm1 = G.gamma - 1.0;
+  double rho = X[lin], e = X[G.N + lin];
+  double wr = v[lin], we = v[G.N + lin];
+  if (scaled) {
+    wr /= rho;
+    we /= e;
+  }
+  double dpdr = gm1 * e, dpde = gm1 * rho;
+  double dp_b = wr / dpdr;
+  double de_b = we - dpde / dpdr * wr;
+  dp_b -= dt * gradT<ND>(G, P, X, v, scaled, alpha2);
+  if (!thermal) {
+    rhs_p[lin] = dp_b + de_b / (G.gamma * rho);
+  } else {
+    rhs_p[lin] = dp_b;  // completed by k_pbpT_mid after the thermal solve
+    rhs_T[lin] = de_b / gm1;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_pbpT_mid(Grid G, double dt, const double* t, double* rhs_p) {
+  int lin = blockIdx.x * kBlock + threadIdx.x;
+  if (lin >= G.N) return;
+  rhs_p[lin] += t[lin] / (G.gamma * dt);
+}
+
+template <int ND>
+__global__ void __launch_bounds__(kBlock) k_pbpT_out(Grid G, const double* X, const double* v, int scaled,
+                                                     double alpha2, double dt, const double* sp,
+                                                     const double* t, double* z) {
+  int lin = blockIdx.x * kBlock + threadIdx.x;
+  if (lin >= G.N) return;
+  Pos P = make_pos<ND>(G, lin);
+  const double gm1 = G.gamma - 1.0;
+  const int N = G.N;
+  double rho = X[lin], e = X[N + lin];
+  double wr = v[lin], we = v[N + lin];
+  if (scaled) {
+    wr /= rho;
+    we /= e;
+  }
+  double dpdr = gm1 * e, dpde = gm1 * rho;
+  double de_b = we - dpde / dpdr * wr;
+  double p = gm1 * rho * e;
+  double Fe_b, Fp_b;
+  if (t) {
+    Fe_b = rho * t[lin];
+    Fp_b = -t[lin] / G.gamma;
+  } else {
+    Fe_b = dt * de_b;
+    Fp_b = -dt * de_b / (G.gamma * rho);
+  }
+  Fp_b += sp[lin] / (G.gamma * p);
+  double r0 = (dpdr - (e / rho) * dpde) * Fp_b - (e / rho) * Fe_b;
+  double r1 = (dpde / rho) * Fp_b + Fe_b / rho;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    double s;
+    int im = gidx<ND>(G, P, 0, shift(off0(), d, -1), &s);
+    double rf = 0.5 * (X[im] + rho);
+    double Fu_b = dt * w_face<ND>(G, X, v, scaled, alpha2, d, lin);
+    z[(2 + d) * N + lin] = Fu_b / rf;
+    // the F_u row of face f reads rbar = (r_rho[f-1] + r_rho[f])/2 with coefficient -u/rho_f
+    double a0 = -X[(2 + d) * N + lin] * Fu_b / rf;
+    r0 += 0.5 * a0;
+    if (G.bc[d] == 1 && P.c[d] == 0) r0 += 0.5 * a0;  // mirror ghost r_rho[-1] = r_rho[0]
+    bool top = (P.c[d] == G.n[d] - 1);
+    if (!(G.bc[d] == 1 && top)) {
+      int ip = top ? lin - (G.n[d] - 1) * G.stride[d] : lin + G.stride[d];
+      double rfp = 0.5 * (rho + X[ip]);
+      double Fu_bp = dt * w_face<ND>(G, X, v, scaled, alpha2, d, ip);
+      r0 += 0.5 * (-X[(2 + d) * N + ip] * Fu_bp / rfp);
+    }
+  }
+  z[lin] = r0;
+  z[N + lin] = r1;
+}
+
+void launch_pbpT_in(const Grid& G, const double* X, const double* v, int scaled, double alpha2,
+                    double dt, int thermal, double* rhs_p, double* rhs_T, hipStream_t s) {
+  dim3 gr((G.N + kBlock - 1) / kBlock);
+  if (G.nd == 2) k_pbpT_in<2><<<gr, kBlock, 0, s>>>(G, X, v, scaled, alpha2, dt, thermal, rhs_p, rhs_T);
+  else k_pbpT_in<3><<<gr, kBlock, 0, s>>>(G, X, v, scaled, alpha2, dt, thermal, rhs_p, rhs_T);
+}
+void launch_pbpT_mid(const Grid& G, double dt, const double* t, double* rhs_p, hipStream_t s) {
+  dim3 gr((G.N + kBlock - 1) / kBlock);
+  k_pbpT_mid<<<gr, kBlock, 0, s>>>(G, dt, t, rhs_p);
+}
+void launch_pbpT_out(const Grid& G, const double* X, const double* v, int scaled, double alpha2,
+                     double dt, const double* sp, const double* t, double* z, hipStream_t s) {
+  dim3 gr((G.N + kBlock - 1) / kBlock);
+  if (G.nd == 2) k_pbpT_out<2><<<gr, kBlock, 0, s>>>(G, X, v, scaled, alpha2, dt, sp, t, z);
+  else k_pbpT_out<3><<<gr, kBlock, 0, s>>>(G, X, v, scaled, alpha2, dt, sp, t, z);
+}
+
+size_t vjp_scratch_doubles(const Grid& G) {
+  PadGrid PG = make_pad(G);
+  return (size_t)PG.PN * (G.nd + 2 + G.nd);
+}
+
+void launch_vjp(const Grid& G, const double* X, const double* w, double cU, double cR, double* scratch,
+                int scaleR, double alpha2, double* out, hipStream_t s) {
+  PadGrid PG = make_pad(G);
+  double* fbar = scratch;
+  double* xbar = scratch + (size_t)G.nd * PG.PN;
+  dim3 gp((PG.PN + kBlock - 1) / kBlock), gc((G.N + kBlock - 1) / kBlock), bl(kBlock);
+  const double nv = 2 + G.nd;
+  {
+    const double by = 8.0 * (2 * nv * G.N + G.nd * (double)PG.PN);
+    if (G.nd == 2) launch_k(KF_VJP_A, by, k_vjp_stageA<2>, gp, bl, 0, s, G, PG, X, w, cR, fbar);
+    else launch_k(KF_VJP_A, by, k_vjp_stageA<3>, gp, bl, 0, s, G, PG, X, w, cR, fbar);
+  }
+  {
+    const double by = 8.0 * (2 * nv * G.N + (G.nd + nv) * (double)PG.PN);
+    const double* fb = fbar;
+    if (G.nd == 2) launch_k(KF_VJP_B, by, k_vjp_stageB<2>, gp, bl, 0, s, G, PG, X, w, cR, fb, xbar);
+    else launch_k(KF_VJP_B, by, k_vjp_stageB<3>, gp, bl, 0, s, G, PG, X, w, cR, fb, xbar);
+  }
+  {
+    const double by = 8.0 * (3 * nv * G.N + nv * (double)PG.PN);
+    const double* xb = xbar;
+    if (G.nd == 2)
+      launch_k(KF_VJP_FOLD, by, k_vjp_fold<2>, gc, bl, 0, s, G, PG, X, w, cU, xb, scaleR, alpha2, out);
+    else
+      launch_k(KF_VJP_FOLD, by, k_vjp_fold<3>, gc, bl, 0, s, G, PG, X, w, cU, xb, scaleR, alpha2, out);
+  }
+}
+
+}  // namespace jfnk

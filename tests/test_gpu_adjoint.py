@@ -1,0 +1,214 @@
+"""GPU parity of the transposed products and of the adjoint of implicit steps.
+
+* J^T w against the oracle's coloured complex-step sparse Jacobian, element by element,
+  with each element's error bounded by 1e-12 times the sum of the absolute contributions to
+  it (|J|^T |w|), the natural scale of a cancelling sum;
+* the dot-product identity <w, J v> = <J^T w, v> with both products from the GPU, at full
+  workload sizes (a property that holds at any size);
+* (dF/dX^n)^T lam against the oracle's (dU/dX)^T lam / dt;
+* the adjoint step against the oracle's LU solve of J^T lam = g (<= 1e-8);
+* gradients of a kinetic-energy loss through two implicit steps (autograd.Function with
+  per-step checkpoints) against central differences of the GPU's own forward steps.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle.residual import Problem, rhs_b, cfl_dt, conserved_U
+from oracle.jacobian import jacobian_sparse
+from oracle.adjoint import dU_dX_T, adjoint_step_exact
+from oracle.newton import exact_step
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+from test_gpu_parity import TINY, _tiny, T, H  # noqa: E402
+
+
+def _lib():
+    import paper_1512_03662_amd as J
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return J
+
+
+@pytest.mark.parametrize("case", TINY, ids=[c[0] for c in TINY])
+def test_vjp_parity_small(case):
+    J = _lib()
+    pd, X = _tiny(case, seed=21)
+    P = Problem.from_dict(pd)
+    dt = 0.03
+    b = rhs_b(P, X, dt)
+    w = W.random_vector(X, 22)
+    Jm = jacobian_sparse(P, X, b, dt)
+    ref = (Jm.T @ w.ravel()).reshape(X.shape)
+    scale = (abs(Jm).T @ np.abs(w.ravel())).reshape(X.shape)
+    ctx = J.Context(pd)
+    ctx.set_state_n(T(X), dt)
+    got = H(ctx.vjp(T(X), T(w)))
+    assert np.all(np.abs(got - ref) <= 1e-12 * scale + 1e-300)
+
+
+@pytest.mark.parametrize("name", ["c2", "c3_64", "c5_64"])
+def test_vjp_dot_product_large(name):
+    J = _lib()
+    if name == "c2":
+        w_ = W.stratified_2d(n=256)
+    elif name == "c3_64":
+        w_ = W.taylor_green_3d(n=64, mach=1e-2)
+    else:
+        w_ = W.polytrope((64, 64, 64), 20.0, mach=1e-4, seed=1005, chi_model="power", cfl=500.0)
+    pd, X = w_["problem"], w_["X0"]
+    P = Problem.from_dict(pd)
+    dt = cfl_dt(P, X, w_["cfl"])
+    ctx = J.Context(pd)
+    Xg = T(X)
+    ctx.set_state_n(Xg, dt)
+    g = torch.Generator(device=DEV)
+    g.manual_seed(5)
+    v = torch.rand(Xg.shape, dtype=torch.float64, device=DEV, generator=g) - 0.5
+    wv = torch.rand(Xg.shape, dtype=torch.float64, device=DEV, generator=g) - 0.5
+    Jv = ctx.jvp(Xg, v, "exact")
+    JTw = ctx.vjp(Xg, wv)
+    a = float(torch.sum(wv * Jv))
+    b = float(torch.sum(JTw * v))
+    mag = float(torch.sum(torch.abs(wv * Jv)))
+    assert abs(a - b) <= 1e-12 * mag, (a, b, mag)
+
+
+def test_vjp_prev_parity():
+    J = _lib()
+    pd, X = _tiny(TINY[3], seed=23)
+    P = Problem.from_dict(pd)
+    dt = 0.07
+    lam = W.random_vector(X, 24)
+    ref = -dU_dX_T(P, X, lam) / dt
+    ctx = J.Context(pd)
+    ctx.set_state_n(T(X), dt)
+    got = H(ctx.vjp_prev(T(X), T(lam)))
+    assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+ADJ_CASES = [
+    ("bump_16", lambda: W.acoustic_bump_2d(n=16), "sound"),
+    ("strat_16x24_thermal", lambda: W.polytrope((16, 24), 10.0, mach=1e-3, seed=5, chi_model="power",
+                                                steps=1, cfl=50.0), "sound_thermal"),
+    ("tg_3d_8", lambda: W.taylor_green_3d(n=8, mach=1e-2), "sound"),
+]
+
+
+@pytest.mark.parametrize("name,mk,prec", ADJ_CASES, ids=[c[0] for c in ADJ_CASES])
+def test_adjoint_step_parity(name, mk, prec):
+    J = _lib()
+    w_ = mk()
+    pd, X0 = w_["problem"], w_["X0"]
+    P = Problem.from_dict(pd)
+    dt = cfl_dt(P, X0, 10.0)
+    Xs, _ = exact_step(P, X0, dt)
+    gbar = W.random_vector(X0, 31)
+    ref, _ = adjoint_step_exact(P, Xs, X0, dt, gbar)
+    ctx = J.Context(pd, precond=prec, gmres_eta=1e-12, cg_eta=1e-6)
+    got, st = ctx.adjoint_step(T(Xs), T(X0), dt, T(gbar))
+    got = H(got)
+    assert st["converged"] == 1
+    assert np.max(np.abs(got - ref)) <= 1e-8 * np.max(np.abs(ref)), (np.max(np.abs(got - ref)), st)
+
+
+def _ke_torch(pd):
+    def ke(Xt):
+        tot = 0.0
+        for d in range(2):
+            ax = 1 - d
+            rho = Xt[0]
+            lower = torch.roll(rho, 1, dims=ax)
+            if pd["bc"][d] == "wall":
+                idx = [slice(None)] * 2
+                idx[ax] = 0
+                lower[tuple(idx)] = rho[tuple(idx)]
+            rf = 0.5 * (lower + rho)
+            tot = tot + 0.5 * torch.sum(rf * Xt[2 + d] ** 2)
+        return tot
+    return ke
+
+
+def test_implicit_steps_gradient_vs_oracle_chain():
+    """Gradient through 2 steps (ImplicitSteps.backward) against the oracle's chain of
+    exact-Newton steps and LU adjoints."""
+    J = _lib()
+    w_ = W.polytrope((24, 24), 10.0, mach=1e-3, seed=1004, chi_model="power", steps=2, cfl=50.0)
+    pd, X0 = w_["problem"], w_["X0"]
+    P = Problem.from_dict(pd)
+    dt = cfl_dt(P, X0, 50.0)
+    ctx = J.Context(pd, precond="sound_thermal", jv_mode="exact", newton_tol=1e-13, newton_max=30,
+                    gmres_eta=1e-11, gmres_maxit=600, cg_eta=1e-8)
+    ke = _ke_torch(pd)
+    Xg = T(X0).requires_grad_(True)
+    Xn = J.ImplicitSteps.apply(Xg, ctx, [dt, dt])
+    ke(Xn).backward()
+    got = H(Xg.grad)
+    # oracle chain
+    X1, _ = exact_step(P, X0, dt)
+    X2, _ = exact_step(P, X1, dt)
+    X2t = torch.tensor(X2, requires_grad=True)
+    ke(X2t).backward()
+    g2 = X2t.grad.numpy()
+    g1, _ = adjoint_step_exact(P, X2, X1, dt, g2)
+    g0, _ = adjoint_step_exact(P, X1, X0, dt, g1)
+    for k in range(P.nvar):
+        assert np.max(np.abs(got[k] - g0[k])) <= 1e-6 * np.max(np.abs(g0[k])), k
+
+
+def test_implicit_steps_gradient_fd():
+    """Gradient of total kinetic energy after 2 steps w.r.t. the initial temperature, through
+    ImplicitSteps, against central differences along 8 seeded directions (1e-4: the
+    difference straddles rare upwind switches)."""
+    J = _lib()
+    w_ = W.polytrope((24, 24), 10.0, mach=1e-3, seed=1004, chi_model="power", steps=2, cfl=50.0)
+    pd, X0 = w_["problem"], w_["X0"]
+    P = Problem.from_dict(pd)
+    dt = cfl_dt(P, X0, 50.0)
+    dts = [dt, dt]
+    ctx = J.Context(pd, precond="sound_thermal", jv_mode="exact", newton_tol=1e-13, newton_max=30,
+                    gmres_eta=1e-11, gmres_maxit=600, cg_eta=1e-8)
+    gamma = pd["gamma"]
+
+    def ke(Xt):
+        # sum of rho_f u^2 / 2 over faces (rho_f the face mean, mirror at walls)
+        tot = 0.0
+        for d in range(2):
+            ax = 1 - d
+            rho = Xt[0]
+            lower = torch.roll(rho, 1, dims=ax)
+            if pd["bc"][d] == "wall":
+                idx = [slice(None)] * 2
+                idx[ax] = 0
+                lower[tuple(idx)] = rho[tuple(idx)]
+            rf = 0.5 * (lower + rho)
+            tot = tot + 0.5 * torch.sum(rf * Xt[2 + d] ** 2)
+        return tot
+
+    Xg = T(X0).requires_grad_(True)
+    Xn = J.ImplicitSteps.apply(Xg, ctx, dts)
+    loss = ke(Xn)
+    loss.backward()
+    grad_e = H(Xg.grad)[1]
+    T0 = (gamma - 1.0) * X0[1]
+    # eps = 1e-7: at Mach 1e-3 a relative change of 1e-5 in e moves face velocities by
+    # ~2e-5 and flips the upwind choice on ~1% of the faces, which a central difference
+    # straddles; 1e-7 keeps switches unlikely while the 1e-13 Newton error stays negligible
+    for k in range(8):
+        d = W.random_vector(X0[1:2], 2001 + k)[0]
+        an = float(np.sum(grad_e * X0[1] * d))  # dL/deps for e -> e (1 + eps d)
+        eps = 1e-7
+        vals = []
+        for sgn in (1.0, -1.0):
+            Xp = X0.copy()
+            Xp[1] = X0[1] * (1.0 + sgn * eps * d)
+            Xt = T(Xp)
+            for dtk in dts:
+                ctx.implicit_step(Xt, dtk)
+            vals.append(float(ke(Xt)))
+        fd = (vals[0] - vals[1]) / (2 * eps)
+        assert abs(fd - an) <= 1e-4 * abs(an), (k, fd, an)
+    del T0
