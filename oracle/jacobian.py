@@ -6,7 +6,8 @@ TEST INFRASTRUCTURE ONLY.
   of eq. pert_old, delta = lam (lam + ||x||/||v||).  The norms are 2-norms of the vectors in
   the scaled space of eq. jacobian_system_norm (x = R^-1 X, v = R^-1 dX), so delta is
   unit-free.  lam = 1e-7 is the value the Results section finds necessary at low Mach.
-* ``jvp_cs``: exact product by the complex step Im F(X + i h v)/h, h = 1e-30 (frozen branches).
+* ``jvp_cs``: exact product by the complex step Im F(X + i h v)/h, h = 1e-200 (frozen
+  branches; see H_CS).
 * ``jacobian_sparse``: the full sparse Jacobian, columns from complex steps on coloured
   groups of unknowns.  The stencil reaches cells at offsets -3..+3 per axis, so cells whose
   indices agree modulo a period P >= 8 (P divides n on periodic axes) never share a row.
@@ -24,7 +25,12 @@ import scipy.sparse as sp
 from .residual import Problem, residual_F, WALL
 from .scaling import scaling_LR
 
-H_CS = 1e-30
+# Complex-step size.  Products of two imaginary parts (h^2 ~ 1e-400) underflow to exactly
+# zero, so the real part of every intermediate equals the real evaluation and every upwind /
+# limiter branch is taken exactly as in the real computation (frozen branches).  With a
+# larger h (e.g. 1e-30) the O(h^2) real corrections decide exact ties such as a zero mass
+# flux on a plane where u = 0, making the "derivative" depend on the direction.
+H_CS = 1e-200
 
 
 def fd_delta(prob: Problem, X, v, lam=1e-7, alpha1=1e-5, alpha2=1.0):

@@ -65,6 +65,25 @@ def test_sparse_coloured_product_large(shape, bc):
     assert np.max(np.abs(Js @ v.ravel() - Jv.ravel())) <= 1e-13 * np.max(np.abs(Jv))
 
 
+def test_complex_step_is_linear_at_exact_ties():
+    """The frozen-branch product must be linear in the direction, also on states with exact
+    ties (Taylor-Green at Mach 1e-6 has u = 0 on whole planes, so mass fluxes vanish
+    exactly): J(v1 + v2) = J v1 + J v2 for directions mixing density and velocity."""
+    w = W.taylor_green_3d(n=8, mach=1e-6)
+    P = Problem.from_dict(w["problem"])
+    X = w["X0"]
+    dt = 10.0
+    b = rhs_b(P, X, dt)
+    rng = np.random.default_rng(3)
+    v1 = np.zeros_like(X)
+    v2 = np.zeros_like(X)
+    v1[0] = rng.uniform(-1, 1, X[0].shape)
+    v2[2:] = rng.uniform(-1, 1, X[2:].shape)
+    J1, J2, J12 = jvp_cs(P, X, b, dt, v1), jvp_cs(P, X, b, dt, v2), jvp_cs(P, X, b, dt, v1 + v2)
+    scale = np.abs(J1).max() + np.abs(J2).max()
+    assert np.max(np.abs(J12 - J1 - J2)) <= 1e-14 * scale
+
+
 def test_fd_product_first_order():
     P, X = _case(1)
     dt = 0.02
