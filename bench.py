@@ -41,6 +41,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernels-3d", dest="kernels_3d", action="store_false",
                     help="skip the kernel rates at the 256^3 production size")
+    ap.add_argument("--only-kernels-3d", action="store_true",
+                    help="only time the single-launch kernels at 256^3 (for profiling them)")
+    ap.add_argument("--compare", action="store_true",
+                    help="also time the exact-J.v + FP32-elliptic form on the same steps")
     ap.add_argument("--cpu-budget-s", type=float, default=30.0)
     return ap.parse_args()
 
@@ -64,6 +68,15 @@ def main():
     import paper_1512_03662_amd as J
 
     dev = torch.device("cuda:0")
+    if args.only_kernels_3d:
+        import workloads as Wl
+        w5 = Wl.convective_box_3d(n=256)
+        X5 = torch.tensor(w5["X0"], dtype=torch.float64, device=dev)
+        ctx5 = J.Context(w5["problem"], gmres_m=1, precond="none")
+        r = kernel_rates(J, ctx5, X5, w5["cfl"], int(np.prod(w5["problem"]["shape"])), 5,
+                         args.kernel_reps, prefix="3d256_")
+        print(json.dumps({"workload": w5["name"], "kernels": r}), flush=True)
+        return
     w = workload(args.workload)
     pd = w["problem"]
     jv = args.jv or w["jv_mode"]
@@ -123,6 +136,36 @@ def main():
         ctx5.close()
         del X5
 
+    compare = None
+    if args.compare:
+        print("# compare: exact J.v + FP32 elliptic solves", file=sys.stderr, flush=True)
+        ctx_ai = J.Context(pd, precond=precond, jv_mode="exact", ell_precision="fp32")
+        ctx_save = ctx
+        ctx = ctx_ai
+        run_steps(args.warmup)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        Xa, stats_a = run_steps(args.steps)
+        torch.cuda.synchronize()
+        sec_a = time.perf_counter() - ta
+        ctx = ctx_save
+        Xk_np, Xa_np = Xk.cpu().numpy(), Xa.cpu().numpy()
+        from oracle.residual import Problem as _P
+        from oracle.scaling import scaling_LR as _LR
+        _, Rsc = _LR(_P.from_dict(pd), Xk_np)
+        compare = {
+            "form": "exact J.v + FP32 elliptic (MG-CG) solves",
+            "value": args.steps / sec_a, "unit": "implicit steps/s",
+            "ms_per_step": 1e3 * sec_a / args.steps,
+            "speedup_vs_plain": sec / sec_a,
+            "solver": {"newton_its": sum(s["newton_its"] for s in stats_a),
+                       "gmres_its": sum(s["gmres_its"] for s in stats_a),
+                       "cg_its": sum(s["cg_its"] for s in stats_a),
+                       "converged_steps": sum(s["converged"] for s in stats_a)},
+            "max_abs_Rinv_diff_vs_plain": float(np.max(np.abs((Xa_np - Xk_np) / Rsc))),
+        }
+        ctx_ai.close()
+
     rec = {
         "metric": METRIC,
         "value": steps_per_s,
@@ -145,6 +188,7 @@ def main():
                    "converged_steps": sum(s["converged"] for s in stats)},
         "roofline": roofline,
         "kernels": kernels,
+        "compare": compare,
         "probe_ms": {k: round(v[0], 3) for k, v in sorted(probes.items(), key=lambda kv: -kv[1][0])},
     }
     if not args.no_cpu_baseline:

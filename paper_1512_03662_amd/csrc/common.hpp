@@ -69,19 +69,53 @@ __device__ __forceinline__ dual powr(dual x, double p) {
   return dual(y, p * y / x.v * x.d);
 }
 
+// Reciprocal by the hardware estimate refined with two Newton steps (relative error within
+// a few ulp; operands here are far from the overflow and denormal ranges).
+__device__ __forceinline__ double rcp_nr(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
+}
+
 // van Leer (1974) harmonic slope: 2ab/(a+b) if ab > 0, else 0 (branch frozen for tangents).
-template <class T>
-__device__ __forceinline__ T vl(T a, T b) {
-  if (val(a) * val(b) > 0.0) return (2.0 * a * b) / (a + b);
-  return T(0.0);
+// Evaluated without branches: the quotient is always formed and discarded by the select.
+__device__ __forceinline__ double vl(double a, double b) {
+  const double s = a + b;
+  const double q = 2.0 * a * b * rcp_nr(s);
+  return (a * b > 0.0) ? q : 0.0;
+}
+__device__ __forceinline__ dual vl(dual a, dual b) {
+  const double s = a.v + b.v;
+  const double r = rcp_nr(s);
+  const double num = 2.0 * a.v * b.v;
+  const double q = num * r;
+  // d(2ab/(a+b)) = (2(a' b + a b') - q (a' + b')) / (a + b)
+  const double dq = (2.0 * (a.d * b.v + a.v * b.d) - q * (a.d + b.d)) * r;
+  const bool on = a.v * b.v > 0.0;
+  return dual(on ? q : 0.0, on ? dq : 0.0);
 }
 
 // Upwind van Leer value at the face between q[c-1] (qm1) and q[c] (q0): w >= 0 takes the
-// left-biased reconstruction.
+// left-biased reconstruction qm1 + vl(qm1-qm2, q0-qm1)/2, else q0 - vl(q0-qm1, qp1-q0)/2.
+// The operands are selected first so that one slope is evaluated without divergence.
+template <class T>
+__device__ __forceinline__ T sel(bool c, T a, T b) {
+  return c ? a : b;
+}
+__device__ __forceinline__ dual sel(bool c, dual a, dual b) {
+  return dual(c ? a.v : b.v, c ? a.d : b.d);
+}
 template <class T>
 __device__ __forceinline__ T upwind(T qm2, T qm1, T q0, T qp1, double w) {
-  if (w >= 0.0) return qm1 + 0.5 * vl(qm1 - qm2, q0 - qm1);
-  return q0 - 0.5 * vl(q0 - qm1, qp1 - q0);
+  const bool left = (w >= 0.0);
+  const T d0 = q0 - qm1;
+  const T base = sel(left, qm1, q0);
+  const T a = sel(left, qm1 - qm2, d0);
+  const T b = sel(left, d0, qp1 - q0);
+  const double h = left ? 0.5 : -0.5;
+  return base + h * vl(a, b);
 }
 
 // ------------------------------------------------------------------------------------
@@ -110,6 +144,16 @@ __device__ __forceinline__ int ghost_normal(int i, int n, int bc, double* s) {
   if (i == 0 || i == n) { *s = 0.0; return 0; }
   *s = 1.0;
   return i;
+}
+
+// MI355X deals consecutive workgroups round-robin to its 8 XCDs, each with its own L2.
+// Renumber them so that XCD k works on one contiguous range of blocks: neighbouring grid
+// rows (the stencil's y and z neighbours) then share an L2.
+constexpr int kNumXcd = 8;
+__device__ __forceinline__ int xcd_block(int i, int nb) {
+  const int q = nb / kNumXcd, r = nb % kNumXcd;
+  const int x = i % kNumXcd, j = i / kNumXcd;
+  return (x < r) ? x * (q + 1) + j : r * (q + 1) + (x - r) * q + j;
 }
 
 // Position of one thread's cell; loads of field var at an offset apply the ghost rules

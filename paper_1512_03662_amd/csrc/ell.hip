@@ -76,7 +76,7 @@ __device__ __forceinline__ T apply_at(const LV<T>& L, const int* c, int lin, con
 template <int ND>
 __global__ void __launch_bounds__(kBlock) k_ell_coef(Grid G, const double* X, double dt, int op, double* diag,
                                                      double* w0, double* w1, double* w2) {
-  int lin = blockIdx.x * kBlock + threadIdx.x;
+  int lin = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (lin >= G.N) return;
   Pos P = make_pos<ND>(G, lin);
   const double gm1 = G.gamma - 1.0;
@@ -125,7 +125,7 @@ void launch_ell_coef(const Grid& G, const double* X, double dt, int op, double* 
 
 template <class T, int ND>
 __global__ void __launch_bounds__(kBlock) k_ell_coarsen(Level f, Level c) {
-  int lin = blockIdx.x * kBlock + threadIdx.x;
+  int lin = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (lin >= c.N) return;
   int cc[3];
   coords<ND>(c.n, lin, cc);
@@ -169,7 +169,7 @@ void launch_ell_coarsen(const Grid& G, const Level& f, const Level& c, hipStream
 
 template <class T, int ND>
 __global__ void __launch_bounds__(kBlock) k_ell_dinv(LV<T> L, T* dinv) {
-  int lin = blockIdx.x * kBlock + threadIdx.x;
+  int lin = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (lin >= L.N) return;
   int c[3];
   coords<ND>(L.n, lin, c);
@@ -207,7 +207,7 @@ void launch_level_to_f32(const Level& src, const Level& dst, int nd, hipStream_t
 // ---- V-cycle pieces ------------------------------------------------------------------------
 template <class T, int ND>
 __global__ void __launch_bounds__(kBlock) k_mg_presmooth(LV<T> L, const T* b, T* x) {
-  int lin = blockIdx.x * kBlock + threadIdx.x;
+  int lin = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (lin >= L.N) return;
   int c[3];
   coords<ND>(L.n, lin, c);
@@ -221,7 +221,7 @@ __global__ void __launch_bounds__(kBlock) k_mg_presmooth(LV<T> L, const T* b, T*
 template <class T, int ND>
 __global__ void __launch_bounds__(kBlock) k_mg_restrict_resid(LV<T> L, const T* b, const T* x, T* bc,
                                                               int Nc, int nc0, int nc1) {
-  int lin = blockIdx.x * kBlock + threadIdx.x;
+  int lin = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (lin >= Nc) return;
   int cc[3];
   cc[0] = lin % nc0;
@@ -257,7 +257,7 @@ __device__ __forceinline__ int parent_of(const LV<T>& L, int lin, const int* cst
 template <class T, int ND>
 __global__ void __launch_bounds__(kBlock) k_mg_prolong_smooth1(LV<T> L, const T* b, const T* x2, const T* xc,
                                                                int cs0, int cs1, int cs2, T* x1, T* d0) {
-  int lin = blockIdx.x * kBlock + threadIdx.x;
+  int lin = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (lin >= L.N) return;
   int c[3];
   coords<ND>(L.n, lin, c);
@@ -272,7 +272,7 @@ __global__ void __launch_bounds__(kBlock) k_mg_prolong_smooth1(LV<T> L, const T*
 
 template <class T, int ND>
 __global__ void __launch_bounds__(kBlock) k_mg_smooth2(LV<T> L, const T* b, const T* x1, const T* d0, T* x) {
-  int lin = blockIdx.x * kBlock + threadIdx.x;
+  int lin = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (lin >= L.N) return;
   int c[3];
   coords<ND>(L.n, lin, c);
@@ -612,7 +612,7 @@ __device__ __forceinline__ void r_cell(const Grid& G, const double* X, const dou
 template <int ND>
 __global__ void __launch_bounds__(kBlock) k_pbp_in(Grid G, const double* X, const double* v, int scaled,
                                                    double* rhs_p) {
-  int lin = blockIdx.x * kBlock + threadIdx.x;
+  int lin = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (lin >= G.N) return;
   const double gm1 = G.gamma - 1.0;
   double rho = X[lin], e = X[G.N + lin];
@@ -625,7 +625,7 @@ __global__ void __launch_bounds__(kBlock) k_pbp_in(Grid G, const double* X, cons
 
 __global__ void __launch_bounds__(kBlock) k_pbp_rhsT(Grid G, const double* X, const double* v, int scaled,
                                                      double dt, const double* dp, double* rhs_T) {
-  int lin = blockIdx.x * kBlock + threadIdx.x;
+  int lin = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (lin >= G.N) return;
   const double gm1 = G.gamma - 1.0;
   double rho = X[lin], e = X[G.N + lin];
@@ -641,7 +641,7 @@ template <int ND>
 __global__ void __launch_bounds__(kBlock) k_pbp_out(Grid G, const double* X, const double* v, int scaled,
                                                     double alpha1, double dt, const double* dp,
                                                     const double* dT, double* z) {
-  int lin = blockIdx.x * kBlock + threadIdx.x;
+  int lin = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (lin >= G.N) return;
   Pos P = make_pos<ND>(G, lin);
   const double gm1 = G.gamma - 1.0;

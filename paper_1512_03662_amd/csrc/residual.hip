@@ -216,7 +216,7 @@ __device__ __forceinline__ void cell_Rs(const Grid& G, const Pos& P, const doubl
 // ---- kernels --------------------------------------------------------------------------
 template <int ND>
 __global__ void __launch_bounds__(kBlock) k_resid_value(Grid G, ResidArgs a) {
-  int lin = blockIdx.x * blockDim.x + threadIdx.x;
+  int lin = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (lin >= G.N) return;
   Pos P = make_pos<ND>(G, lin);
   LoadVal<double> ld{a.X, G.N};
@@ -237,7 +237,7 @@ __global__ void __launch_bounds__(kBlock) k_resid_value(Grid G, ResidArgs a) {
 
 template <int ND>
 __global__ void __launch_bounds__(kBlock) k_resid_tangent(Grid G, ResidArgs a) {
-  int lin = blockIdx.x * blockDim.x + threadIdx.x;
+  int lin = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (lin >= G.N) return;
   Pos P = make_pos<ND>(G, lin);
   LoadDual ld{a.X, a.V, G.N};
@@ -256,7 +256,7 @@ __global__ void __launch_bounds__(kBlock) k_resid_tangent(Grid G, ResidArgs a) {
 
 template <int ND>
 __global__ void __launch_bounds__(kBlock) k_resid_fd(Grid G, ResidArgs a) {
-  int lin = blockIdx.x * blockDim.x + threadIdx.x;
+  int lin = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (lin >= G.N) return;
   const double xn2 = a.fd_norms[0], zn2 = a.fd_norms[1];
   double L[2 + ND];
@@ -288,7 +288,7 @@ template <int ND>
 __global__ void __launch_bounds__(kBlock) k_scale_LR(Grid G, const double* X, double alpha, int which,
                                                      const double* in, double* out, int mode) {
   // mode 0: out = in / S, mode 1: out = in * S, with S = L (which = 0) or R (which = 1)
-  int lin = blockIdx.x * blockDim.x + threadIdx.x;
+  int lin = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (lin >= G.N) return;
   Pos P = make_pos<ND>(G, lin);
   double S[2 + ND];

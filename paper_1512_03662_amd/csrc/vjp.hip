@@ -137,7 +137,7 @@ __device__ __forceinline__ double mflux(const Acc<ND>& A, int d, const int* c) {
 template <int ND>
 __global__ void __launch_bounds__(kBlock) k_vjp_stageA(Grid G, PadGrid PG, const double* X, const double* w,
                                                        double cR, double* fbar) {
-  int pl = blockIdx.x * kBlock + threadIdx.x;
+  int pl = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (pl >= PG.PN) return;
   int c[3];
   c[0] = pl % PG.P[0] - 3;
@@ -198,7 +198,7 @@ __global__ void __launch_bounds__(kBlock) k_vjp_stageA(Grid G, PadGrid PG, const
 template <int ND>
 __global__ void __launch_bounds__(kBlock) k_vjp_stageB(Grid G, PadGrid PG, const double* X, const double* w,
                                                        double cR, const double* fbar, double* xbar) {
-  int pl = blockIdx.x * kBlock + threadIdx.x;
+  int pl = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (pl >= PG.PN) return;
   int c[3];
   c[0] = pl % PG.P[0] - 3;
@@ -391,7 +391,7 @@ template <int ND>
 __global__ void __launch_bounds__(kBlock) k_vjp_fold(Grid G, PadGrid PG, const double* X, const double* w,
                                                      double cU, const double* xbar, int scaleR, double alpha2,
                                                      double* out) {
-  int lin = blockIdx.x * kBlock + threadIdx.x;
+  int lin = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (lin >= G.N) return;
   Pos P = make_pos<ND>(G, lin);
   const int N = G.N;
@@ -526,7 +526,7 @@ template <int ND>
 __global__ void __launch_bounds__(kBlock) k_pbpT_in(Grid G, const double* X, const double* v, int scaled,
                                                     double alpha2, double dt, int thermal, double* rhs_p,
                                                     double* rhs_T) {
-  int lin = blockIdx.x * kBlock + threadIdx.x;
+  int lin = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (lin >= G.N) return;
   Pos P = make_pos<ND>(G, lin);
   const double gm1 = G.gamma - 1.0;
@@ -549,7 +549,7 @@ __global__ void __launch_bounds__(kBlock) k_pbpT_in(Grid G, const double* X, con
 }
 
 __global__ void __launch_bounds__(kBlock) k_pbpT_mid(Grid G, double dt, const double* t, double* rhs_p) {
-  int lin = blockIdx.x * kBlock + threadIdx.x;
+  int lin = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (lin >= G.N) return;
   rhs_p[lin] += t[lin] / (G.gamma * dt);
 }
@@ -558,7 +558,7 @@ template <int ND>
 __global__ void __launch_bounds__(kBlock) k_pbpT_out(Grid G, const double* X, const double* v, int scaled,
                                                      double alpha2, double dt, const double* sp,
                                                      const double* t, double* z) {
-  int lin = blockIdx.x * kBlock + threadIdx.x;
+  int lin = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (lin >= G.N) return;
   Pos P = make_pos<ND>(G, lin);
   const double gm1 = G.gamma - 1.0;

@@ -1,0 +1,134 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py times, on sampled
+outputs the oracle computes one by one.
+
+* F and exact J.v at sampled cells of the 256^3 convective box and the 128^3 Taylor-Green
+  box (oracle evaluated only at the sampled cells);
+* J^T w at sampled unknowns: the oracle perturbs one unknown by a complex step and reads its
+  Jacobian column on the rows that can depend on it (a box of radius 3), then dots it with w;
+* the finite-difference J.v at sampled cells, with the perturbation size from full-grid norms.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle.residual import Problem, residual_F, residual_R, conserved_U, cfl_dt, WALL
+from oracle.jacobian import H_CS, fd_delta
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _lib():
+    import paper_1512_03662_amd as J
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return J
+
+
+def _rhs_b_cells(P, Xn, dt, cells):
+    # b = U(X^n)/dt (theta = 1) at the sampled cells
+    return conserved_U(P, Xn, cells) / dt
+
+
+def _sample(P, k, seed):
+    rng = np.random.default_rng(seed)
+    cells = [rng.integers(0, P.shape[d], size=k) for d in range(P.nd)]
+    # include boundary-adjacent cells on every axis
+    for d in range(P.nd):
+        cells[d][:2] = [0, P.shape[d] - 1]
+    return tuple(cells)
+
+
+def _at(A, P, cells):
+    idx = tuple(np.asarray(cells[d]) for d in reversed(range(P.nd)))
+    return np.stack([A[v][idx] for v in range(A.shape[0])])
+
+
+def _workload(name):
+    if name == "c5_256":
+        return W.convective_box_3d(n=256)
+    return W.taylor_green_3d(n=128)
+
+
+@pytest.mark.parametrize("name", ["c5_256", "c3_128"])
+def test_fullsize_residual_and_jv_sampled(name):
+    J = _lib()
+    w = _workload(name)
+    pd, X = w["problem"], w["X0"]
+    P = Problem.from_dict(pd)
+    dt = cfl_dt(P, X, w["cfl"])
+    # X^n: the same state slightly changed so that F(X) != 0
+    Xn = X.copy()
+    Xn[0] *= 1.0 + 1e-3 * np.sin(np.arange(Xn[0].size).reshape(Xn[0].shape) * 0.37)
+    ctx = J.Context(pd, gmres_m=1, precond="none")
+    Xg = torch.tensor(X, device=DEV)
+    ctx.set_state_n(torch.tensor(Xn, device=DEV), dt)
+    Fg = ctx.residual(Xg).cpu().numpy()
+    rng = np.random.default_rng(77)
+    v = rng.uniform(-1, 1, X.shape)
+    Jvg = ctx.jvp(Xg, torch.tensor(v, device=DEV), "exact").cpu().numpy()
+    cells = _sample(P, 48, 5)
+    b = _rhs_b_cells(P, Xn, dt, cells)
+    # residual at the sampled cells: F = U/dt - R - b
+    F = conserved_U(P, X, cells) / dt - residual_R(P, X, cells) - b
+    _, A = residual_R(P, X, cells, with_abs=True)
+    U = conserved_U(P, X, cells)
+    S = np.max(np.abs(U) / dt + np.abs(b), axis=1) + np.max(A, axis=1)
+    err = np.max(np.abs(_at(Fg, P, cells) - F), axis=1) / S
+    assert np.all(err <= 1e-12), err
+    # exact J v at the sampled cells by the complex step
+    Xc = X.astype(np.complex128) + 1j * H_CS * v
+    Jv = np.imag(conserved_U(P, Xc, cells) / dt - residual_R(P, Xc, cells)) / H_CS
+    errj = np.max(np.abs(_at(Jvg, P, cells) - Jv), axis=1) / S
+    assert np.all(errj <= 1e-12), errj
+    # finite-difference J v (pert_old with scaled norms) at the sampled cells
+    Jfd = ctx.jvp(Xg, torch.tensor(v, device=DEV), "fd").cpu().numpy()
+    delta = fd_delta(P, X, v)
+    Xp = X + delta * v
+    Jf = ((conserved_U(P, Xp, cells) / dt - residual_R(P, Xp, cells))
+          - (conserved_U(P, X, cells) / dt - residual_R(P, X, cells))) / delta
+    errf = np.max(np.abs(_at(Jfd, P, cells) - Jf), axis=1) / S
+    assert np.all(errf <= 1e-7), errf
+
+
+def _box_cells(P, c, r=3):
+    """All cells within distance r of cell c (wrapped on periodic axes, clipped at walls)."""
+    axes = []
+    for d in range(P.nd):
+        idx = np.arange(c[d] - r, c[d] + r + 1)
+        if P.bc[d] == WALL:
+            idx = idx[(idx >= 0) & (idx < P.shape[d])]
+        else:
+            idx = np.mod(idx, P.shape[d])
+        axes.append(idx)
+    grids = np.meshgrid(*axes, indexing="ij")
+    return tuple(g.ravel() for g in grids)
+
+
+@pytest.mark.parametrize("name", ["c5_256"])
+def test_fullsize_vjp_sampled(name):
+    J = _lib()
+    w = _workload(name)
+    pd, X = w["problem"], w["X0"]
+    P = Problem.from_dict(pd)
+    dt = cfl_dt(P, X, w["cfl"])
+    ctx = J.Context(pd, gmres_m=1, precond="none")
+    Xg = torch.tensor(X, device=DEV)
+    ctx.set_state_n(Xg, dt)
+    rng = np.random.default_rng(78)
+    wv = rng.uniform(-1, 1, X.shape)
+    JTw = ctx.vjp(Xg, torch.tensor(wv, device=DEV)).cpu().numpy()
+    Xc = X.astype(np.complex128)
+    cells = _sample(P, 6, 9)
+    for s in range(len(cells[0])):
+        c = [int(cells[d][s]) for d in range(P.nd)]
+        box = _box_cells(P, c)
+        for var in range(P.nvar):
+            idx = (var,) + tuple(c[d] for d in reversed(range(P.nd)))
+            Xc[idx] += 1j * H_CS
+            col = np.imag(conserved_U(P, Xc, box) / dt - residual_R(P, Xc, box)) / H_CS
+            Xc[idx] -= 1j * H_CS
+            wb = _at(wv, P, box)
+            ref = float(np.sum(col * wb))
+            scale = float(np.sum(np.abs(col * wb)))
+            assert abs(JTw[idx] - ref) <= 1e-12 * scale + 1e-300, (c, var, JTw[idx], ref)
