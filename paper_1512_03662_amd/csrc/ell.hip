@@ -56,9 +56,11 @@ __device__ __forceinline__ void coords(const int* n, int lin, int* c) {
   c[2] = r / n[1];
 }
 
-// (A phi)[c] with phi given by a functor of the linear index; phic = phi(lin)
+// (A phi)[c]; nb(d, s, k) is phi at the neighbour k (linear index, wrapped) on side s = -1/+1
+// of axis d, phic = phi at c.  Neighbours across a wall are wrapped too: their face weight
+// is 0.
 template <class T, int ND, class F>
-__device__ __forceinline__ T apply_at(const LV<T>& L, const int* c, int lin, const F& phi, T phic) {
+__device__ __forceinline__ T apply_nb(const LV<T>& L, const int* c, int lin, const F& nb, T phic) {
   T out = L.diag[lin] * phic;
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
@@ -67,9 +69,34 @@ __device__ __forceinline__ T apply_at(const LV<T>& L, const int* c, int lin, con
     const int cp = (c[d] == n - 1) ? lin - (n - 1) * st : lin + st;
     const T wl = L.w[d][lin];
     const T wu = (L.bc[d] == 1 && c[d] == n - 1) ? T(0) : L.w[d][cp];
-    out -= wu * (phi(cp) - phic) - wl * (phic - phi(cm));
+    out -= wu * (nb(d, 1, cp) - phic) - wl * (phic - nb(d, -1, cm));
   }
   return out;
+}
+
+// (A phi)[c] with phi given by a functor of the linear index; phic = phi(lin)
+template <class T, int ND, class F>
+__device__ __forceinline__ T apply_at(const LV<T>& L, const int* c, int lin, const F& phi, T phic) {
+  return apply_nb<T, ND>(L, c, lin, [&](int, int, int k) { return phi(k); }, phic);
+}
+
+// restricted residual (mean over the 2^ND children of b - A x) of coarse cell cc
+template <class T, int ND>
+__device__ __forceinline__ T restrict_at(const LV<T>& F, const T* b, const T* x, const int* cc) {
+  auto xf = [&](int i) { return x[i]; };
+  T sum = T(0);
+#pragma unroll
+  for (int ch = 0; ch < (1 << ND); ++ch) {
+    int c[3] = {0, 0, 0};
+    int fl = 0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      c[d] = 2 * cc[d] + ((ch >> d) & 1);
+      fl += c[d] * F.stride[d];
+    }
+    sum += b[fl] - apply_at<T, ND>(F, c, fl, xf, x[fl]);
+  }
+  return sum * T(1.0 / (1 << ND));
 }
 
 // ---- coefficients ------------------------------------------------------------------------
@@ -204,44 +231,128 @@ void launch_level_to_f32(const Level& src, const Level& dst, int nd, hipStream_t
     k_to_f32<<<gr, kBlock, 0, s>>>(src.N, (const double*)src.w[d], (float*)dst.w[d]);
 }
 
-// ---- V-cycle pieces ------------------------------------------------------------------------
-template <class T, int ND>
-__global__ void __launch_bounds__(kBlock) k_mg_presmooth(LV<T> L, const T* b, T* x) {
-  int lin = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-  if (lin >= L.N) return;
-  int c[3];
-  coords<ND>(L.n, lin, c);
-  const T th = T(1.0 / kChebTheta);
-  auto x1 = [&](int i) { return L.dinv[i] * b[i] * th; };
-  T x1c = x1(lin);
-  T Ax = apply_at<T, ND>(L, c, lin, x1, x1c);
-  x[lin] = (T(1.0) + T(kChebC1)) * x1c + T(kChebC2) * L.dinv[lin] * (b[lin] - Ax);
+// ---- CG control and partial sums --------------------------------------------------------
+// A CG solve is driven from the device: every kernel of an iteration returns at once when
+// the control block's flag is set, so the host enqueues iterations ahead of the test.
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
 }
 
-template <class T, int ND>
-__global__ void __launch_bounds__(kBlock) k_mg_restrict_resid(LV<T> L, const T* b, const T* x, T* bc,
-                                                              int Nc, int nc0, int nc1) {
-  int lin = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-  if (lin >= Nc) return;
-  int cc[3];
-  cc[0] = lin % nc0;
-  int r = lin / nc0;
-  cc[1] = r % nc1;
-  cc[2] = r / nc1;
-  auto xf = [&](int i) { return x[i]; };
-  T sum = T(0);
-#pragma unroll
-  for (int ch = 0; ch < (1 << ND); ++ch) {
-    int c[3] = {0, 0, 0};
-    int fl = 0;
-#pragma unroll
-    for (int d = 0; d < ND; ++d) {
-      c[d] = 2 * cc[d] + ((ch >> d) & 1);
-      fl += c[d] * L.stride[d];
-    }
-    sum += b[fl] - apply_at<T, ND>(L, c, fl, xf, x[fl]);
+// Sum of n partials in a fixed order; every block of a launch obtains the same value.
+__device__ double block_sum_parts(const double* P, int n) {
+  __shared__ double sm[kCoarseThreads / 64];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) v += P[i];
+  v = wave_sum_d(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (lane == 0) sm[wid] = v;
+  __syncthreads();
+  double a = sm[0];
+  for (int w = 1; w < nw; ++w) a += sm[w];
+  __syncthreads();
+  return a;
+}
+
+// P[blockIdx.x] = sum of v over the block
+__device__ void block_partial(double v, double* P) {
+  __shared__ double sm[kCoarseThreads / 64];
+  v = wave_sum_d(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (lane == 0) sm[wid] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = sm[0];
+    for (int w = 1; w < nw; ++w) a += sm[w];
+    P[blockIdx.x] = a;
   }
-  bc[lin] = sum * T(1.0 / (1 << ND));
+}
+
+// convergence test of iteration it: ||r|| < eta ||b||, or the iteration limit
+__device__ void cg_decide(const CGArgs& g, double rr, int it) {
+  CGCtl* S = g.ctl;
+  S->rr = rr;
+  const double rn = sqrt(rr), bn = sqrt(S->bb);
+  if (!isfinite(rn)) {
+    S->its = it;
+    S->flag = -1;
+  } else if (rn < g.eta * bn || it >= g.maxit) {
+    S->its = it;
+    S->flag = 1;
+  }
+}
+
+static inline int red_grid(size_t n) {
+  size_t b = (n + kBlock - 1) / kBlock;
+  if (b > (size_t)kRedBlocks) b = kRedBlocks;
+  return (int)(b < 1 ? 1 : b);
+}
+
+int cg_partials(size_t n) { return red_grid(n); }
+
+// cells of a launch: one per thread when the grid covers N, grid-stride otherwise
+#define FOR_CELLS(lin, N) \
+  for (int lin = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x; lin < (N); lin += gridDim.x * kBlock)
+
+// ---- V-cycle pieces ------------------------------------------------------------------------
+// INIT: first smoothing of a solve; also resets the control block and writes the (b, b)
+// partials
+template <class T, int ND, bool INIT>
+__global__ void __launch_bounds__(kBlock) k_mg_presmooth(LV<T> L, const T* b, T* x, CGArgs g) {
+  if (INIT) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      g.ctl->flag = 0;
+      g.ctl->its = 0;
+    }
+  } else if (g.ctl->flag) {
+    return;
+  }
+  const T th = T(1.0 / kChebTheta);
+  T acc = T(0);
+  FOR_CELLS(lin, L.N) {
+    int c[3];
+    coords<ND>(L.n, lin, c);
+    auto x1 = [&](int i) { return L.dinv[i] * b[i] * th; };
+    T x1c = x1(lin);
+    T Ax = apply_at<T, ND>(L, c, lin, x1, x1c);
+    x[lin] = (T(1.0) + T(kChebC1)) * x1c + T(kChebC2) * L.dinv[lin] * (b[lin] - Ax);
+    if (INIT) acc += b[lin] * b[lin];
+  }
+  if (INIT) block_partial((double)acc, g.part + kPartBB * kRedBlocks);
+}
+
+// CONV: block 0 also takes the convergence decision of iteration it from the (r, r) partials
+// (the other blocks of this launch may or may not see it; their output is then unused)
+template <class T, int ND, bool CONV>
+__global__ void __launch_bounds__(kBlock) k_mg_restrict_resid(LV<T> L, const T* b, const T* x, T* bc,
+                                                              int Nc, int nc0, int nc1, CGArgs g, int it) {
+  if (g.ctl->flag) return;
+  if (CONV && blockIdx.x == 0) {
+    const double rr = block_sum_parts(g.part + kPartRR * kRedBlocks, g.np);
+    if (threadIdx.x == 0) cg_decide(g, rr, it);
+  }
+  auto xf = [&](int i) { return x[i]; };
+  FOR_CELLS(lin, Nc) {
+    int cc[3];
+    cc[0] = lin % nc0;
+    int r = lin / nc0;
+    cc[1] = r % nc1;
+    cc[2] = r / nc1;
+    T sum = T(0);
+#pragma unroll
+    for (int ch = 0; ch < (1 << ND); ++ch) {
+      int c[3] = {0, 0, 0};
+      int fl = 0;
+#pragma unroll
+      for (int d = 0; d < ND; ++d) {
+        c[d] = 2 * cc[d] + ((ch >> d) & 1);
+        fl += c[d] * L.stride[d];
+      }
+      sum += b[fl] - apply_at<T, ND>(L, c, fl, xf, x[fl]);
+    }
+    bc[lin] = sum * T(1.0 / (1 << ND));
+  }
 }
 
 template <class T, int ND>
@@ -256,128 +367,372 @@ __device__ __forceinline__ int parent_of(const LV<T>& L, int lin, const int* cst
 
 template <class T, int ND>
 __global__ void __launch_bounds__(kBlock) k_mg_prolong_smooth1(LV<T> L, const T* b, const T* x2, const T* xc,
-                                                               int cs0, int cs1, int cs2, T* x1, T* d0) {
-  int lin = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-  if (lin >= L.N) return;
-  int c[3];
-  coords<ND>(L.n, lin, c);
+                                                               int cs0, int cs1, int cs2, T* x1, T* d0,
+                                                               CGArgs g) {
+  if (g.ctl->flag) return;
   const int cst[3] = {cs0, cs1, cs2};
   auto xp = [&](int i) { return x2[i] + xc[parent_of<T, ND>(L, i, cst)]; };
-  T xpc = xp(lin);
-  T r0 = b[lin] - apply_at<T, ND>(L, c, lin, xp, xpc);
-  T dd = L.dinv[lin] * r0 * T(1.0 / kChebTheta);
-  x1[lin] = xpc + dd;
-  d0[lin] = dd;
+  FOR_CELLS(lin, L.N) {
+    int c[3];
+    coords<ND>(L.n, lin, c);
+    T xpc = xp(lin);
+    T r0 = b[lin] - apply_at<T, ND>(L, c, lin, xp, xpc);
+    T dd = L.dinv[lin] * r0 * T(1.0 / kChebTheta);
+    x1[lin] = xpc + dd;
+    d0[lin] = dd;
+  }
 }
 
-template <class T, int ND>
-__global__ void __launch_bounds__(kBlock) k_mg_smooth2(LV<T> L, const T* b, const T* x1, const T* d0, T* x) {
-  int lin = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-  if (lin >= L.N) return;
-  int c[3];
-  coords<ND>(L.n, lin, c);
+// RZ: also the (b, x) partials (b the level's right-hand side, x the result)
+template <class T, int ND, bool RZ>
+__global__ void __launch_bounds__(kBlock) k_mg_smooth2(LV<T> L, const T* b, const T* x1, const T* d0, T* x,
+                                                       CGArgs g) {
+  if (g.ctl->flag) return;
   auto xf = [&](int i) { return x1[i]; };
-  T x1c = x1[lin];
-  T r1 = b[lin] - apply_at<T, ND>(L, c, lin, xf, x1c);
-  x[lin] = x1c + T(kChebC1) * d0[lin] + T(kChebC2) * L.dinv[lin] * r1;
+  T acc = T(0);
+  FOR_CELLS(lin, L.N) {
+    int c[3];
+    coords<ND>(L.n, lin, c);
+    T x1c = x1[lin];
+    T r1 = b[lin] - apply_at<T, ND>(L, c, lin, xf, x1c);
+    T xn = x1c + T(kChebC1) * d0[lin] + T(kChebC2) * L.dinv[lin] * r1;
+    x[lin] = xn;
+    if (RZ) acc += b[lin] * xn;
+  }
+  if (RZ) block_partial((double)acc, g.part + kPartRZ * kRedBlocks);
+}
+
+// ---- fused level pairs on LDS tiles ----------------------------------------------------
+// One workgroup owns a tile of kBlock cells (16 x 16 in 2D, 8 x 8 x 4 in 3D) of the level it
+// writes; the intermediate coarse vector lives in LDS with a halo of one cell, recomputed by
+// every tile that needs it.
+template <int ND>
+struct TileDims;
+template <>
+struct TileDims<2> {
+  static constexpr int X = 16, Y = 16, Z = 1;
+};
+template <>
+struct TileDims<3> {
+  static constexpr int X = 8, Y = 8, Z = 4;
+};
+
+__device__ __forceinline__ int wrapc(int c, int n) {
+  c %= n;
+  return c < 0 ? c + n : c;
+}
+
+template <int ND>
+__device__ __forceinline__ void tile_origin(const int* n, int* o) {
+  using TD = TileDims<ND>;
+  const int nbx = (n[0] + TD::X - 1) / TD::X, nby = (n[1] + TD::Y - 1) / TD::Y;
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  o[0] = (b % nbx) * TD::X;
+  const int r = b / nbx;
+  o[1] = (r % nby) * TD::Y;
+  o[2] = (ND == 3) ? (r / nby) * TD::Z : 0;
+}
+
+template <int ND>
+static int tile_blocks(const int* n) {
+  using TD = TileDims<ND>;
+  int b = ((n[0] + TD::X - 1) / TD::X) * ((n[1] + TD::Y - 1) / TD::Y);
+  if (ND == 3) b *= (n[2] + TD::Z - 1) / TD::Z;
+  return b;
+}
+
+// restriction of level F into level C (on C's tile and its halo, in LDS), then the first
+// smoothing of level C on the tile.  CONV: block 0 also takes the convergence decision of
+// iteration it (as k_mg_restrict_resid).
+template <class T, int ND, bool CONV>
+__global__ void __launch_bounds__(kBlock) k_mg_down(LV<T> F, const T* bf, const T* xf, LV<T> C, T* bc, T* xc,
+                                                    CGArgs g, int it) {
+  using TD = TileDims<ND>;
+  constexpr int HX = TD::X + 2, HY = TD::Y + 2, HZ = (ND == 3) ? TD::Z + 2 : 1;
+  constexpr int HN = HX * HY * HZ;
+  __shared__ T sb[HN];
+  if (g.ctl->flag) return;
+  if (CONV && blockIdx.x == 0) {
+    const double rr = block_sum_parts(g.part + kPartRR * kRedBlocks, g.np);
+    if (threadIdx.x == 0) cg_decide(g, rr, it);
+  }
+  int o[3];
+  tile_origin<ND>(C.n, o);
+  for (int h = threadIdx.x; h < HN; h += kBlock) {
+    const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
+    int cc[3] = {wrapc(o[0] + hx - 1, C.n[0]), wrapc(o[1] + hy - 1, C.n[1]),
+                 (ND == 3) ? wrapc(o[2] + hz - 1, C.n[2]) : 0};
+    sb[h] = restrict_at<T, ND>(F, bf, xf, cc);
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  const int l[3] = {t % TD::X, (t / TD::X) % TD::Y, t / (TD::X * TD::Y)};
+  int c[3] = {o[0] + l[0], o[1] + l[1], (ND == 3) ? o[2] + l[2] : 0};
+  if (c[0] >= C.n[0] || c[1] >= C.n[1] || (ND == 3 && c[2] >= C.n[2])) return;
+  const int lin = c[0] * C.stride[0] + c[1] * C.stride[1] + c[2] * C.stride[2];
+  const int hs[3] = {1, HX, HX * HY};
+  const int hc = (l[0] + 1) + (l[1] + 1) * HX + ((ND == 3) ? (l[2] + 1) * HX * HY : 0);
+  const T bcen = sb[hc];
+  bc[lin] = bcen;
+  const T th = T(1.0 / kChebTheta);
+  auto x1 = [&](int d, int s, int k) { return C.dinv[k] * sb[hc + s * hs[d]] * th; };
+  const T x1c = C.dinv[lin] * bcen * th;
+  const T Ax = apply_nb<T, ND>(C, c, lin, x1, x1c);
+  xc[lin] = (T(1.0) + T(kChebC1)) * x1c + T(kChebC2) * C.dinv[lin] * (bcen - Ax);
+}
+
+// second smoothing step of level C on the parents of F's tile and their halo (in LDS), then
+// the prolongation to level F and its first post-smoothing step (as k_mg_prolong_smooth1).
+template <class T, int ND>
+__global__ void __launch_bounds__(kBlock) k_mg_up(LV<T> C, const T* bc, const T* t1c, const T* t2c, LV<T> F,
+                                                  const T* bf, const T* x2f, T* t1f, T* t2f, CGArgs g) {
+  using TD = TileDims<ND>;
+  constexpr int PX = TD::X / 2 + 2, PY = TD::Y / 2 + 2, PZ = (ND == 3) ? TD::Z / 2 + 2 : 1;
+  constexpr int PN = PX * PY * PZ;
+  __shared__ T sx[PN];
+  if (g.ctl->flag) return;
+  int o[3];
+  tile_origin<ND>(F.n, o);
+  const int p0[3] = {o[0] / 2, o[1] / 2, o[2] / 2};
+  auto t1 = [&](int k) { return t1c[k]; };
+  for (int h = threadIdx.x; h < PN; h += kBlock) {
+    const int hx = h % PX, hy = (h / PX) % PY, hz = h / (PX * PY);
+    int cc[3] = {wrapc(p0[0] + hx - 1, C.n[0]), wrapc(p0[1] + hy - 1, C.n[1]),
+                 (ND == 3) ? wrapc(p0[2] + hz - 1, C.n[2]) : 0};
+    const int k = cc[0] * C.stride[0] + cc[1] * C.stride[1] + cc[2] * C.stride[2];
+    const T x1c = t1c[k];
+    const T r1 = bc[k] - apply_at<T, ND>(C, cc, k, t1, x1c);
+    sx[h] = x1c + T(kChebC1) * t2c[k] + T(kChebC2) * C.dinv[k] * r1;
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  const int l[3] = {t % TD::X, (t / TD::X) % TD::Y, t / (TD::X * TD::Y)};
+  int c[3] = {o[0] + l[0], o[1] + l[1], (ND == 3) ? o[2] + l[2] : 0};
+  if (c[0] >= F.n[0] || c[1] >= F.n[1] || (ND == 3 && c[2] >= F.n[2])) return;
+  const int lin = c[0] * F.stride[0] + c[1] * F.stride[1] + c[2] * F.stride[2];
+  // LDS position of the parent of the fine cell f (unwrapped, at most one step from the tile)
+  auto ppos = [&](const int* f) {
+    int p = ((f[0] >> 1) - p0[0] + 1) + ((f[1] >> 1) - p0[1] + 1) * PX;
+    if (ND == 3) p += ((f[2] >> 1) - p0[2] + 1) * PX * PY;
+    return p;
+  };
+  const T xpc = x2f[lin] + sx[ppos(c)];
+  auto xp = [&](int d, int s, int k) {
+    int f[3] = {c[0], c[1], c[2]};
+    f[d] += s;
+    return x2f[k] + sx[ppos(f)];
+  };
+  const T r0 = bf[lin] - apply_nb<T, ND>(F, c, lin, xp, xpc);
+  const T dd = F.dinv[lin] * r0 * T(1.0 / kChebTheta);
+  t1f[lin] = xpc + dd;
+  t2f[lin] = dd;
 }
 
 #define CELLS(n) dim3(((n) + kBlock - 1) / kBlock), dim3(kBlock)
 
 template <class T>
-void launch_mg_presmooth(const Grid& G, const Level& L, const T* b, T* x, hipStream_t s) {
+void launch_mg_down(const Grid& G, const Level& f, const T* bf, const T* xf, const Level& c, T* bc, T* xc,
+                    const CGArgs& g, int conv_it, hipStream_t s) {
+  LV<T> vf = view<T>(G, f), vc = view<T>(G, c);
+  const double by = ((3.0 + G.nd) * f.N + (5.0 + G.nd) * c.N) * (double)sizeof(T);
+  const int nb2 = tile_blocks<2>(c.n), nb3 = tile_blocks<3>(c.n);
+  if (G.nd == 2) {
+    if (conv_it > 0)
+      launch_k(KF_MG_DOWN, by, k_mg_down<T, 2, true>, dim3(nb2), dim3(kBlock), 0, s, vf, bf, xf, vc, bc, xc, g,
+               conv_it);
+    else
+      launch_k(KF_MG_DOWN, by, k_mg_down<T, 2, false>, dim3(nb2), dim3(kBlock), 0, s, vf, bf, xf, vc, bc, xc, g,
+               0);
+  } else {
+    if (conv_it > 0)
+      launch_k(KF_MG_DOWN, by, k_mg_down<T, 3, true>, dim3(nb3), dim3(kBlock), 0, s, vf, bf, xf, vc, bc, xc, g,
+               conv_it);
+    else
+      launch_k(KF_MG_DOWN, by, k_mg_down<T, 3, false>, dim3(nb3), dim3(kBlock), 0, s, vf, bf, xf, vc, bc, xc, g,
+               0);
+  }
+}
+template <class T>
+void launch_mg_up(const Grid& G, const Level& c, const T* bc, const T* t1c, const T* t2c, const Level& f,
+                  const T* bf, const T* x2f, T* t1f, T* t2f, const CGArgs& g, hipStream_t s) {
+  LV<T> vc = view<T>(G, c), vf = view<T>(G, f);
+  const double by = ((5.0 + G.nd) * c.N + (6.0 + G.nd) * f.N) * (double)sizeof(T);
+  if (G.nd == 2)
+    launch_k(KF_MG_UP, by, k_mg_up<T, 2>, dim3(tile_blocks<2>(f.n)), dim3(kBlock), 0, s, vc, bc, t1c, t2c, vf, bf,
+             x2f, t1f, t2f, g);
+  else
+    launch_k(KF_MG_UP, by, k_mg_up<T, 3>, dim3(tile_blocks<3>(f.n)), dim3(kBlock), 0, s, vc, bc, t1c, t2c, vf, bf,
+             x2f, t1f, t2f, g);
+}
+
+
+template <class T>
+void launch_mg_presmooth(const Grid& G, const Level& L, const T* b, T* x, const CGArgs& g, bool init,
+                         hipStream_t s) {
   LV<T> v = view<T>(G, L);
   const double by = (4.0 + G.nd) * L.N * (double)sizeof(T);
-  if (G.nd == 2) launch_k(KF_MG_PRE, by, k_mg_presmooth<T, 2>, CELLS(L.N), 0, s, v, b, x);
-  else launch_k(KF_MG_PRE, by, k_mg_presmooth<T, 3>, CELLS(L.N), 0, s, v, b, x);
+  if (init) {
+    dim3 gr(red_grid(L.N)), bl(kBlock);
+    if (G.nd == 2) launch_k(KF_MG_PRE, by, k_mg_presmooth<T, 2, true>, gr, bl, 0, s, v, b, x, g);
+    else launch_k(KF_MG_PRE, by, k_mg_presmooth<T, 3, true>, gr, bl, 0, s, v, b, x, g);
+  } else {
+    if (G.nd == 2) launch_k(KF_MG_PRE, by, k_mg_presmooth<T, 2, false>, CELLS(L.N), 0, s, v, b, x, g);
+    else launch_k(KF_MG_PRE, by, k_mg_presmooth<T, 3, false>, CELLS(L.N), 0, s, v, b, x, g);
+  }
 }
 template <class T>
 void launch_mg_restrict_resid(const Grid& G, const Level& f, const T* b, const T* x, T* bc,
-                              const Level& c, hipStream_t s) {
+                              const Level& c, const CGArgs& g, int conv_it, hipStream_t s) {
   LV<T> v = view<T>(G, f);
   const double by = ((3.0 + G.nd) * f.N + c.N) * (double)sizeof(T);
-  if (G.nd == 2)
-    launch_k(KF_MG_RESTRICT, by, k_mg_restrict_resid<T, 2>, CELLS(c.N), 0, s, v, b, x, bc, c.N, c.n[0], c.n[1]);
-  else
-    launch_k(KF_MG_RESTRICT, by, k_mg_restrict_resid<T, 3>, CELLS(c.N), 0, s, v, b, x, bc, c.N, c.n[0], c.n[1]);
+  if (conv_it > 0) {
+    if (G.nd == 2)
+      launch_k(KF_MG_RESTRICT, by, k_mg_restrict_resid<T, 2, true>, CELLS(c.N), 0, s, v, b, x, bc, c.N, c.n[0],
+               c.n[1], g, conv_it);
+    else
+      launch_k(KF_MG_RESTRICT, by, k_mg_restrict_resid<T, 3, true>, CELLS(c.N), 0, s, v, b, x, bc, c.N, c.n[0],
+               c.n[1], g, conv_it);
+  } else {
+    if (G.nd == 2)
+      launch_k(KF_MG_RESTRICT, by, k_mg_restrict_resid<T, 2, false>, CELLS(c.N), 0, s, v, b, x, bc, c.N,
+               c.n[0], c.n[1], g, 0);
+    else
+      launch_k(KF_MG_RESTRICT, by, k_mg_restrict_resid<T, 3, false>, CELLS(c.N), 0, s, v, b, x, bc, c.N,
+               c.n[0], c.n[1], g, 0);
+  }
 }
 template <class T>
 void launch_mg_prolong_smooth1(const Grid& G, const Level& f, const T* b, const T* x2, const T* xc,
-                               const Level& c, T* x1, T* d0, hipStream_t s) {
+                               const Level& c, T* x1, T* d0, const CGArgs& g, hipStream_t s) {
   LV<T> v = view<T>(G, f);
   const double by = ((6.0 + G.nd) * f.N + c.N) * (double)sizeof(T);
   if (G.nd == 2)
     launch_k(KF_MG_PROLONG, by, k_mg_prolong_smooth1<T, 2>, CELLS(f.N), 0, s, v, b, x2, xc, c.stride[0],
-             c.stride[1], c.stride[2], x1, d0);
+             c.stride[1], c.stride[2], x1, d0, g);
   else
     launch_k(KF_MG_PROLONG, by, k_mg_prolong_smooth1<T, 3>, CELLS(f.N), 0, s, v, b, x2, xc, c.stride[0],
-             c.stride[1], c.stride[2], x1, d0);
+             c.stride[1], c.stride[2], x1, d0, g);
 }
 template <class T>
 void launch_mg_smooth2(const Grid& G, const Level& L, const T* b, const T* x1, const T* d0, T* x,
-                       hipStream_t s) {
+                       const CGArgs& g, bool rz, hipStream_t s) {
   LV<T> v = view<T>(G, L);
   const double by = (6.0 + G.nd) * L.N * (double)sizeof(T);
-  if (G.nd == 2) launch_k(KF_MG_SMOOTH2, by, k_mg_smooth2<T, 2>, CELLS(L.N), 0, s, v, b, x1, d0, x);
-  else launch_k(KF_MG_SMOOTH2, by, k_mg_smooth2<T, 3>, CELLS(L.N), 0, s, v, b, x1, d0, x);
+  if (rz) {
+    dim3 gr(red_grid(L.N)), bl(kBlock);
+    if (G.nd == 2) launch_k(KF_MG_SMOOTH2, by, k_mg_smooth2<T, 2, true>, gr, bl, 0, s, v, b, x1, d0, x, g);
+    else launch_k(KF_MG_SMOOTH2, by, k_mg_smooth2<T, 3, true>, gr, bl, 0, s, v, b, x1, d0, x, g);
+  } else {
+    if (G.nd == 2)
+      launch_k(KF_MG_SMOOTH2, by, k_mg_smooth2<T, 2, false>, CELLS(L.N), 0, s, v, b, x1, d0, x, g);
+    else
+      launch_k(KF_MG_SMOOTH2, by, k_mg_smooth2<T, 3, false>, CELLS(L.N), 0, s, v, b, x1, d0, x, g);
+  }
 }
 
 // ---- coarse part of the V-cycle in one workgroup -------------------------------------------
-// Levels with at most kCoarseMaxN cells: right-hand side, iterate and smoother vectors live
-// in LDS, coefficients are read from global memory; phases are separated by barriers.
-template <class T, int ND>
-__global__ void __launch_bounds__(kCoarseThreads) k_vcycle_coarse(CoarseArgs a) {
+// Levels with at most kCoarseMaxN cells.  Right-hand sides, iterates and smoother vectors
+// live in LDS, and so do the coefficients of every level for which the launch reserved room
+// (coff >= 0; ALL_LDS: every level); phases are separated by barriers.  mode bits:
+//   kCoarseInit     reset the control block, write the (b, b) partials of the first level;
+//   kCoarseConv     take the convergence decision of iteration it first;
+//   kCoarseRZ       write the (b, x) partials of the first level;
+//   kCoarseFromPre  x0 already holds the first smoothing of the first level (skipped here);
+//   kCoarseToUp     stop after the first post-smoothing step of the first level and write
+//                   its (t1, t2) to t1_0, t2_0 instead of x0.
+template <class T, int ND, bool ALL_LDS>
+__global__ void __launch_bounds__(kCoarseThreads) k_vcycle_coarse(CoarseArgs a, CGArgs g, int mode, int it) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int s_stop;
+  const int tid = threadIdx.x;
+  const int NT = blockDim.x;
+  if (mode & kCoarseInit) {
+    if (tid == 0) {
+      g.ctl->flag = 0;
+      g.ctl->its = 0;
+    }
+  } else if (g.ctl->flag) {
+    return;
+  }
+  if (mode & kCoarseConv) {
+    const double rr = block_sum_parts(g.part + kPartRR * kRedBlocks, g.np);
+    if (tid == 0) {
+      cg_decide(g, rr, it);
+      s_stop = g.ctl->flag;
+    }
+    __syncthreads();
+    if (s_stop) return;
+  }
   T* sb = (T*)smem_raw;
   T* sx = sb + a.tot;
   T* s1 = sx + a.tot;
   T* s2 = s1 + a.tot;
-  const int tid = threadIdx.x;
-  const int NT = blockDim.x;
+  T* sc = s2 + a.tot;
   const T th = T(1.0 / kChebTheta);
-  for (int i = tid; i < a.N[0]; i += NT) sb[a.off[0] + i] = ((const T*)a.b0)[i];
+  for (int j = 0; j < a.nl; ++j) {
+    if (!ALL_LDS && a.coff[j] < 0) continue;
+    T* base = sc + a.coff[j];
+    const int n = a.N[j];
+    for (int i = tid; i < n; i += NT) {
+      base[i] = ((const T*)a.diag[j])[i];
+      base[n + i] = ((const T*)a.dinv[j])[i];
+#pragma unroll
+      for (int d = 0; d < ND; ++d) base[(2 + d) * n + i] = ((const T*)a.w[j][d])[i];
+    }
+  }
+  T bbacc = T(0);
+  for (int i = tid; i < a.N[0]; i += NT) {
+    const T bi = ((const T*)a.b0)[i];
+    sb[a.off[0] + i] = bi;
+    bbacc += bi * bi;
+    if (mode & kCoarseFromPre) sx[a.off[0] + i] = ((const T*)a.x0)[i];
+  }
+  if (mode & kCoarseInit) {
+    block_partial((double)bbacc, g.part + kPartBB * kRedBlocks);
+    for (int i = tid + 1; i < g.np; i += NT) g.part[kPartBB * kRedBlocks + i] = 0.0;
+  }
   __syncthreads();
-  for (int j = 0; j + 1 < a.nl; ++j) {
+  auto level = [&](int j) {
     LV<T> L;
     for (int d = 0; d < 3; ++d) {
       L.n[d] = a.n[j][d];
       L.stride[d] = a.stride[j][d];
       L.bc[d] = a.bc[d];
-      L.w[d] = (const T*)a.w[j][d];
     }
     L.N = a.N[j];
-    L.diag = (const T*)a.diag[j];
-    L.dinv = (const T*)a.dinv[j];
+    if (ALL_LDS || a.coff[j] >= 0) {
+      const T* base = sc + a.coff[j];
+      L.diag = base;
+      L.dinv = base + L.N;
+      for (int d = 0; d < 3; ++d) L.w[d] = base + (2 + (d < ND ? d : 0)) * L.N;
+    } else {
+      L.diag = (const T*)a.diag[j];
+      L.dinv = (const T*)a.dinv[j];
+      for (int d = 0; d < 3; ++d) L.w[d] = (const T*)a.w[j][d];
+    }
+    return L;
+  };
+  for (int j = 0; j + 1 < a.nl; ++j) {
+    const LV<T> L = level(j);
     const T* b = sb + a.off[j];
     T* x = sx + a.off[j];
-    for (int i = tid; i < L.N; i += NT) {
-      int c[3];
-      coords<ND>(L.n, i, c);
-      auto x1 = [&](int k) { return L.dinv[k] * b[k] * th; };
-      T x1c = x1(i);
-      T Ax = apply_at<T, ND>(L, c, i, x1, x1c);
-      x[i] = (T(1.0) + T(kChebC1)) * x1c + T(kChebC2) * L.dinv[i] * (b[i] - Ax);
+    if (!(j == 0 && (mode & kCoarseFromPre))) {
+      for (int i = tid; i < L.N; i += NT) {
+        int c[3];
+        coords<ND>(L.n, i, c);
+        auto x1 = [&](int k) { return L.dinv[k] * b[k] * th; };
+        T x1c = x1(i);
+        T Ax = apply_at<T, ND>(L, c, i, x1, x1c);
+        x[i] = (T(1.0) + T(kChebC1)) * x1c + T(kChebC2) * L.dinv[i] * (b[i] - Ax);
+      }
+      __syncthreads();
     }
-    __syncthreads();
     T* bc = sb + a.off[j + 1];
     const int Nc = a.N[j + 1];
     for (int ic = tid; ic < Nc; ic += NT) {
       int cc[3];
       coords<ND>(a.n[j + 1], ic, cc);
-      auto xf = [&](int k) { return x[k]; };
-      T sum = T(0);
-#pragma unroll
-      for (int ch = 0; ch < (1 << ND); ++ch) {
-        int c[3] = {0, 0, 0};
-        int fl = 0;
-#pragma unroll
-        for (int d = 0; d < ND; ++d) {
-          c[d] = 2 * cc[d] + ((ch >> d) & 1);
-          fl += c[d] * L.stride[d];
-        }
-        sum += b[fl] - apply_at<T, ND>(L, c, fl, xf, x[fl]);
-      }
-      bc[ic] = sum * T(1.0 / (1 << ND));
+      bc[ic] = restrict_at<T, ND>(L, b, x, cc);
     }
     __syncthreads();
   }
@@ -394,19 +749,11 @@ __global__ void __launch_bounds__(kCoarseThreads) k_vcycle_coarse(CoarseArgs a) 
     __syncthreads();
   }
   for (int j = a.nl - 2; j >= 0; --j) {
-    LV<T> L;
-    for (int d = 0; d < 3; ++d) {
-      L.n[d] = a.n[j][d];
-      L.stride[d] = a.stride[j][d];
-      L.bc[d] = a.bc[d];
-      L.w[d] = (const T*)a.w[j][d];
-    }
-    L.N = a.N[j];
-    L.diag = (const T*)a.diag[j];
-    L.dinv = (const T*)a.dinv[j];
+    const LV<T> L = level(j);
     const T* b = sb + a.off[j];
     T* x = sx + a.off[j];
     const T* xc = sx + a.off[j + 1];
+    const bool to_up = (j == 0) && (mode & kCoarseToUp);
     T* t1 = s1 + a.off[j];
     T* t2 = s2 + a.off[j];
     const int cs[3] = {a.stride[j + 1][0], a.stride[j + 1][1], a.stride[j + 1][2]};
@@ -419,7 +766,12 @@ __global__ void __launch_bounds__(kCoarseThreads) k_vcycle_coarse(CoarseArgs a) 
       T dd = L.dinv[i] * r0 * th;
       t1[i] = xpc + dd;
       t2[i] = dd;
+      if (to_up) {
+        ((T*)a.t1_0)[i] = xpc + dd;
+        ((T*)a.t2_0)[i] = dd;
+      }
     }
+    if (to_up) return;
     __syncthreads();
     for (int i = tid; i < L.N; i += NT) {
       int c[3];
@@ -431,12 +783,52 @@ __global__ void __launch_bounds__(kCoarseThreads) k_vcycle_coarse(CoarseArgs a) 
     }
     __syncthreads();
   }
-  for (int i = tid; i < a.N[0]; i += NT) ((T*)a.x0)[i] = sx[a.off[0] + i];
+  T rzacc = T(0);
+  for (int i = tid; i < a.N[0]; i += NT) {
+    const T xi = sx[a.off[0] + i];
+    ((T*)a.x0)[i] = xi;
+    rzacc += sb[a.off[0] + i] * xi;
+  }
+  if (mode & kCoarseRZ) {
+    block_partial((double)rzacc, g.part + kPartRZ * kRedBlocks);
+    for (int i = tid + 1; i < g.np; i += NT) g.part[kPartRZ * kRedBlocks + i] = 0.0;
+  }
+}
+
+static int max_lds_bytes() {
+  static int v = -1;
+  if (v < 0) {
+    int dev = 0;
+    int val = 65536;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&val, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      val = 65536;
+    v = val;
+  }
+  return v;
+}
+
+template <class T, int ND, bool ALL_LDS>
+static void coarse_lds_attr(size_t shm) {
+  static size_t set = 0;
+  if (shm > 65536 && shm > set) {
+    (void)hipFuncSetAttribute((const void*)k_vcycle_coarse<T, ND, ALL_LDS>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    set = shm;
+  }
+}
+
+template <class T, int ND, bool ALL_LDS>
+static void launch_coarse_k(const CoarseArgs& a, const CGArgs& g, int mode, int it, size_t shm, double bytes,
+                            hipStream_t s) {
+  coarse_lds_attr<T, ND, ALL_LDS>(shm);
+  launch_k(KF_MG_COARSE, bytes, k_vcycle_coarse<T, ND, ALL_LDS>, dim3(1), dim3(kCoarseThreads), (unsigned)shm, s,
+           a, g, mode, it);
 }
 
 template <class T>
 void launch_vcycle_coarse(const Grid& G, const Level* lv, int nl, const double* Ainv, const T* b0,
-                          T* x0, hipStream_t s) {
+                          T* x0, const CGArgs& g, int mode, int it, hipStream_t s) {
   CoarseArgs a{};
   a.nl = nl;
   int tot = 0;
@@ -457,17 +849,38 @@ void launch_vcycle_coarse(const Grid& G, const Level* lv, int nl, const double* 
   a.Ainv = Ainv;
   a.b0 = b0;
   a.x0 = x0;
+  a.t1_0 = lv[0].t1;
+  a.t2_0 = lv[0].t2;
+  // coefficients in LDS, coarsest levels first, while they fit
   size_t shm = 4 * (size_t)tot * sizeof(T);
+  const size_t cap = (size_t)max_lds_bytes() - 1024;  // static LDS of the kernel
+  int coef = 0;
+  bool all = true;
+  for (int j = nl - 1; j >= 0; --j) {
+    const size_t need = (size_t)(2 + G.nd) * lv[j].N;
+    if (shm + (coef + need) * sizeof(T) <= cap) {
+      a.coff[j] = coef;
+      coef += (int)need;
+    } else {
+      a.coff[j] = -1;
+      all = false;
+    }
+  }
+  shm += (size_t)coef * sizeof(T);
   double cbytes = 8.0 * (double)lv[nl - 1].N * lv[nl - 1].N + 2.0 * lv[0].N * (double)sizeof(T);
   for (int j = 0; j < nl; ++j) cbytes += (3.0 + G.nd) * lv[j].N * (double)sizeof(T);
-  if (G.nd == 2)
-    launch_k(KF_MG_COARSE, cbytes, k_vcycle_coarse<T, 2>, dim3(1), dim3(kCoarseThreads), (unsigned)shm, s, a);
-  else
-    launch_k(KF_MG_COARSE, cbytes, k_vcycle_coarse<T, 3>, dim3(1), dim3(kCoarseThreads), (unsigned)shm, s, a);
+  if (G.nd == 2) {
+    if (all) launch_coarse_k<T, 2, true>(a, g, mode, it, shm, cbytes, s);
+    else launch_coarse_k<T, 2, false>(a, g, mode, it, shm, cbytes, s);
+  } else {
+    if (all) launch_coarse_k<T, 3, true>(a, g, mode, it, shm, cbytes, s);
+    else launch_coarse_k<T, 3, false>(a, g, mode, it, shm, cbytes, s);
+  }
 }
 
 template <class T>
-__global__ void k_dense_matvec(int n, const double* A, const T* x, T* y) {
+__global__ void k_dense_matvec(int n, const double* A, const T* x, T* y, CGArgs g) {
+  if (g.ctl->flag) return;
   int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   double s = 0.0;
@@ -475,107 +888,155 @@ __global__ void k_dense_matvec(int n, const double* A, const T* x, T* y) {
   y[i] = (T)s;
 }
 template <class T>
-void launch_dense_matvec(int n, const double* A, const T* x, T* y, hipStream_t s) {
-  k_dense_matvec<T><<<CELLS(n), 0, s>>>(n, A, x, y);
+void launch_dense_matvec(int n, const double* A, const T* x, T* y, const CGArgs& g, hipStream_t s) {
+  k_dense_matvec<T><<<CELLS(n), 0, s>>>(n, A, x, y, g);
 }
 
-// ---- CG vector kernels --------------------------------------------------------------------
-template <class Op>
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-// single-value block partial (the finalize kernel sums the partials in block order)
-__device__ __forceinline__ void finish_sum(double v, double* out, const RedWS& ws) {
-  constexpr int NW = kBlock / 64;
-  __shared__ double sm[NW];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  v = wave_sum<int>(v);
-  if (lane == 0) sm[wid] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double a = sm[0];
-    for (int w = 1; w < NW; ++w) a += sm[w];
-    ws.part[blockIdx.x] = a;
-  }
-  (void)out;
-}
-
-static inline int red_grid(size_t n) {
-  size_t b = (n + kBlock - 1) / kBlock;
-  if (b > (size_t)kRedBlocks) b = kRedBlocks;
-  return (int)(b < 1 ? 1 : b);
-}
-
+// ---- CG kernels ------------------------------------------------------------------------
+// iteration it (1-based).  apply: p = z + beta p_old with beta = (r,z)_{it-1}/(r,z)_{it-2}
+// (p = z when it = 1), q = A p, partials of (p, q).  It also stores (r,z)_{it-1}, and at
+// it = 1 stores ||b||^2 and writes x = 0 when b = 0 (the solve then ends with no iteration).
+// The flag is only ever set by a kernel whose own blocks need no other output of it: blocks
+// of that launch may read it before or after the write.
 template <class T, int ND>
-__global__ void __launch_bounds__(kBlock) k_ell_apply_dot(LV<T> L, const T* p, T* q, double* out, RedWS ws) {
+__global__ void __launch_bounds__(kBlock) k_cg_apply(LV<T> L, const T* z, const T* pold, T* pnew, T* q, T* x,
+                                                     CGArgs g, int it) {
+  CGCtl* S = g.ctl;
+  if (S->flag) return;
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  const double rz = block_sum_parts(g.part + kPartRZ * kRedBlocks, g.np);
+  double beta = 0.0;
+  if (it == 1) {
+    const double bb = block_sum_parts(g.part + kPartBB * kRedBlocks, g.np);
+    if (lead) S->bb = bb;
+    if (bb == 0.0) {  // the update kernel of this iteration ends the solve
+      FOR_CELLS(lin, L.N) x[lin] = T(0);
+      return;
+    }
+  } else {
+    beta = rz / S->rz[it & 1];
+  }
+  if (lead) S->rz[(it - 1) & 1] = rz;
+  const T bt = (T)beta;
+  const T* po = (it == 1) ? z : pold;
+  auto pf = [&](int i) { return z[i] + bt * po[i]; };
   T acc = T(0);
-  auto pf = [&](int i) { return p[i]; };
-  for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < L.N; lin += gridDim.x * kBlock) {
+  FOR_CELLS(lin, L.N) {
     int c[3];
     coords<ND>(L.n, lin, c);
-    T pc = p[lin];
-    T qv = apply_at<T, ND>(L, c, lin, pf, pc);
+    const T pc = pf(lin);
+    const T qv = apply_at<T, ND>(L, c, lin, pf, pc);
+    pnew[lin] = pc;
     q[lin] = qv;
     acc += pc * qv;
   }
-  finish_sum((double)acc, out, ws);
-}
-template <class T>
-void launch_ell_apply_dot(const Grid& G, const Level& L, const T* p, T* q, double* out,
-                          const RedWS& ws, hipStream_t s) {
-  LV<T> v = view<T>(G, L);
-  {
-    const double by = (3.0 + G.nd) * L.N * (double)sizeof(T);
-    dim3 gr(red_grid(L.N)), bl(kBlock);
-    if (G.nd == 2) launch_k(KF_CG_APPLY, by, k_ell_apply_dot<T, 2>, gr, bl, 0, s, v, p, q, out, ws);
-    else launch_k(KF_CG_APPLY, by, k_ell_apply_dot<T, 3>, gr, bl, 0, s, v, p, q, out, ws);
-  }
-  launch_finalize_sum(ws, red_grid(L.N), 1, out, s);
+  block_partial((double)acc, g.part + kPartPQ * kRedBlocks);
 }
 
-template <class T>
-__global__ void __launch_bounds__(kBlock) k_cg_update(size_t n, const double* sc, int inum, int iden, T* x,
-                                                      const T* p, T* r, const T* q, double* rr, RedWS ws) {
-  const T a = (T)(sc[inum] / sc[iden]);
+// update: alpha = (r,z)_{it-1} / (p,q); x += alpha p; r_new = r_old - alpha q, partials of
+// (r_new, r_new); PRE: also the first smoothing of the next V-cycle on level 0, xm.
+template <class T, int ND, bool PRE>
+__global__ void __launch_bounds__(kBlock) k_cg_update(LV<T> L, const T* rold, const T* q, const T* p, T* x,
+                                                      T* rnew, T* xm, CGArgs g, int it) {
+  CGCtl* S = g.ctl;
+  if (S->flag) return;
+  if (it == 1 && S->bb == 0.0) {  // b = 0: x = 0 was written by the apply kernel
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      S->its = 0;
+      S->flag = 1;
+    }
+    return;
+  }
+  const double pq = block_sum_parts(g.part + kPartPQ * kRedBlocks, g.np);
+  const T al = (T)(S->rz[(it - 1) & 1] / pq);
+  const T th = T(1.0 / kChebTheta);
+  auto rf = [&](int i) { return rold[i] - al * q[i]; };
   T acc = T(0);
-  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
-    x[i] += a * p[i];
-    T ri = r[i] - a * q[i];
-    r[i] = ri;
-    acc += ri * ri;
+  FOR_CELLS(lin, L.N) {
+    const T xo = (it == 1) ? T(0) : x[lin];
+    x[lin] = xo + al * p[lin];
+    const T rc = rf(lin);
+    rnew[lin] = rc;
+    acc += rc * rc;
+    if (PRE) {
+      int c[3];
+      coords<ND>(L.n, lin, c);
+      auto x1 = [&](int i) { return L.dinv[i] * rf(i) * th; };
+      const T x1c = L.dinv[lin] * rc * th;
+      const T Ax = apply_at<T, ND>(L, c, lin, x1, x1c);
+      xm[lin] = (T(1.0) + T(kChebC1)) * x1c + T(kChebC2) * L.dinv[lin] * (rc - Ax);
+    }
   }
-  finish_sum((double)acc, rr, ws);
+  block_partial((double)acc, g.part + kPartRR * kRedBlocks);
+}
+
+// control reset and (b, b) partials; convergence decision alone; (r, z) partials alone
+// (used when level 0 is the dense coarsest level)
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_cg_init(int n, const T* b, CGArgs g) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    g.ctl->flag = 0;
+    g.ctl->its = 0;
+  }
+  T acc = T(0);
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) acc += b[i] * b[i];
+  block_partial((double)acc, g.part + kPartBB * kRedBlocks);
+}
+__global__ void __launch_bounds__(kBlock) k_cg_decide(CGArgs g, int it) {
+  if (g.ctl->flag) return;
+  const double rr = block_sum_parts(g.part + kPartRR * kRedBlocks, g.np);
+  if (threadIdx.x == 0) cg_decide(g, rr, it);
 }
 template <class T>
-void launch_cg_update(size_t n, const double* sc, int i_num, int i_den, T* x, const T* p, T* r,
-                      const T* q, double* rr, const RedWS& ws, hipStream_t s) {
-  {
-    launch_k(KF_CG_UPDATE, 6.0 * n * (double)sizeof(T), k_cg_update<T>, dim3(red_grid(n)), dim3(kBlock),
-             0, s, n, sc, i_num, i_den, x, p, r, q, rr, ws);
-  }
-  launch_finalize_sum(ws, red_grid(n), 1, rr, s);
+__global__ void __launch_bounds__(kBlock) k_cg_dot_rz(int n, const T* r, const T* z, CGArgs g) {
+  if (g.ctl->flag) return;
+  T acc = T(0);
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) acc += r[i] * z[i];
+  block_partial((double)acc, g.part + kPartRZ * kRedBlocks);
 }
 
 template <class T>
-__global__ void k_cg_pupdate(size_t n, const double* sc, int inum, int iden, const T* z, T* p) {
-  const T bta = (T)(sc[inum] / sc[iden]);
-  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
-    p[i] = z[i] + bta * p[i];
+void launch_cg_apply(const Grid& G, const Level& L, const T* z, const T* pold, T* pnew, T* q, T* x,
+                     const CGArgs& g, int it, hipStream_t s) {
+  LV<T> v = view<T>(G, L);
+  const double by = (5.0 + G.nd) * L.N * (double)sizeof(T);
+  dim3 gr(red_grid(L.N)), bl(kBlock);
+  if (G.nd == 2) launch_k(KF_CG_APPLY, by, k_cg_apply<T, 2>, gr, bl, 0, s, v, z, pold, pnew, q, x, g, it);
+  else launch_k(KF_CG_APPLY, by, k_cg_apply<T, 3>, gr, bl, 0, s, v, z, pold, pnew, q, x, g, it);
 }
 template <class T>
-void launch_cg_pupdate(size_t n, const double* sc, int i_num, int i_den, const T* z, T* p,
-                       hipStream_t s) {
-  size_t b = (n + kBlock - 1) / kBlock;
-  if (b > 8192) b = 8192;
-  launch_k(KF_CG_PUPDATE, 3.0 * n * (double)sizeof(T), k_cg_pupdate<T>, dim3((unsigned)b), dim3(kBlock), 0,
-           s, n, sc, i_num, i_den, z, p);
+void launch_cg_update(const Grid& G, const Level& L, const T* rold, const T* q, const T* p, T* x, T* rnew,
+                      T* xm, const CGArgs& g, int it, hipStream_t s) {
+  LV<T> v = view<T>(G, L);
+  dim3 gr(red_grid(L.N)), bl(kBlock);
+  if (xm) {
+    const double by = (9.0 + G.nd) * L.N * (double)sizeof(T);
+    if (G.nd == 2)
+      launch_k(KF_CG_UPDATE, by, k_cg_update<T, 2, true>, gr, bl, 0, s, v, rold, q, p, x, rnew, xm, g, it);
+    else
+      launch_k(KF_CG_UPDATE, by, k_cg_update<T, 3, true>, gr, bl, 0, s, v, rold, q, p, x, rnew, xm, g, it);
+  } else {
+    const double by = 6.0 * L.N * (double)sizeof(T);
+    if (G.nd == 2)
+      launch_k(KF_CG_UPDATE, by, k_cg_update<T, 2, false>, gr, bl, 0, s, v, rold, q, p, x, rnew, xm, g, it);
+    else
+      launch_k(KF_CG_UPDATE, by, k_cg_update<T, 3, false>, gr, bl, 0, s, v, rold, q, p, x, rnew, xm, g, it);
+  }
+}
+template <class T>
+void launch_cg_init(int n, const T* b, const CGArgs& g, hipStream_t s) {
+  k_cg_init<T><<<red_grid(n), kBlock, 0, s>>>(n, b, g);
+}
+void launch_cg_decide(const CGArgs& g, int it, hipStream_t s) { k_cg_decide<<<1, kBlock, 0, s>>>(g, it); }
+template <class T>
+void launch_cg_dot_rz(int n, const T* r, const T* z, const CGArgs& g, hipStream_t s) {
+  k_cg_dot_rz<T><<<red_grid(n), kBlock, 0, s>>>(n, r, z, g);
 }
 
+// double <-> float with scaling by 1/sqrt(*nrm2) (to float) or sqrt(*nrm2) (back); a zero
+// right-hand side stays zero, a non-finite one stays non-finite
 __global__ void k_cast_scale_f32(size_t n, const double* src, const double* nrm2, float* dst) {
-  const double sc = 1.0 / sqrt(*nrm2);
+  const double sc = (*nrm2 == 0.0) ? 0.0 : 1.0 / sqrt(*nrm2);
   for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
     dst[i] = (float)(src[i] * sc);
 }
@@ -702,24 +1163,30 @@ void launch_pbp_out(const Grid& G, const double* X, const double* v, int scaled,
 }
 
 // ---- explicit instantiations ---------------------------------------------------------------
-#define INST(T)                                                                                      \
-  template void launch_ell_coarsen<T>(const Grid&, const Level&, const Level&, hipStream_t);        \
-  template void launch_ell_dinv<T>(const Grid&, const Level&, hipStream_t);                          \
-  template void launch_mg_presmooth<T>(const Grid&, const Level&, const T*, T*, hipStream_t);       \
-  template void launch_mg_restrict_resid<T>(const Grid&, const Level&, const T*, const T*, T*,     \
-                                            const Level&, hipStream_t);                              \
-  template void launch_mg_prolong_smooth1<T>(const Grid&, const Level&, const T*, const T*,         \
-                                             const T*, const Level&, T*, T*, hipStream_t);           \
-  template void launch_mg_smooth2<T>(const Grid&, const Level&, const T*, const T*, const T*, T*,   \
-                                     hipStream_t);                                                   \
-  template void launch_dense_matvec<T>(int, const double*, const T*, T*, hipStream_t);              \
-  template void launch_vcycle_coarse<T>(const Grid&, const Level*, int, const double*, const T*, T*, \
-                                        hipStream_t);                                                \
-  template void launch_ell_apply_dot<T>(const Grid&, const Level&, const T*, T*, double*,           \
-                                        const RedWS&, hipStream_t);                                  \
-  template void launch_cg_update<T>(size_t, const double*, int, int, T*, const T*, T*, const T*,    \
-                                    double*, const RedWS&, hipStream_t);                             \
-  template void launch_cg_pupdate<T>(size_t, const double*, int, int, const T*, T*, hipStream_t);
+#define INST(T)                                                                                          \
+  template void launch_ell_coarsen<T>(const Grid&, const Level&, const Level&, hipStream_t);            \
+  template void launch_ell_dinv<T>(const Grid&, const Level&, hipStream_t);                              \
+  template void launch_mg_presmooth<T>(const Grid&, const Level&, const T*, T*, const CGArgs&, bool,     \
+                                       hipStream_t);                                                     \
+  template void launch_mg_restrict_resid<T>(const Grid&, const Level&, const T*, const T*, T*,         \
+                                            const Level&, const CGArgs&, int, hipStream_t);              \
+  template void launch_mg_prolong_smooth1<T>(const Grid&, const Level&, const T*, const T*,             \
+                                             const T*, const Level&, T*, T*, const CGArgs&, hipStream_t);\
+  template void launch_mg_smooth2<T>(const Grid&, const Level&, const T*, const T*, const T*, T*,       \
+                                     const CGArgs&, bool, hipStream_t);                                  \
+  template void launch_dense_matvec<T>(int, const double*, const T*, T*, const CGArgs&, hipStream_t);   \
+  template void launch_vcycle_coarse<T>(const Grid&, const Level*, int, const double*, const T*, T*,     \
+                                        const CGArgs&, int, int, hipStream_t);                           \
+  template void launch_mg_down<T>(const Grid&, const Level&, const T*, const T*, const Level&, T*, T*,  \
+                                  const CGArgs&, int, hipStream_t);                                      \
+  template void launch_mg_up<T>(const Grid&, const Level&, const T*, const T*, const T*, const Level&, \
+                                const T*, const T*, T*, T*, const CGArgs&, hipStream_t);                 \
+  template void launch_cg_apply<T>(const Grid&, const Level&, const T*, const T*, T*, T*, T*,           \
+                                   const CGArgs&, int, hipStream_t);                                     \
+  template void launch_cg_update<T>(const Grid&, const Level&, const T*, const T*, const T*, T*, T*, T*,\
+                                    const CGArgs&, int, hipStream_t);                                    \
+  template void launch_cg_init<T>(int, const T*, const CGArgs&, hipStream_t);                           \
+  template void launch_cg_dot_rz<T>(int, const T*, const T*, const CGArgs&, hipStream_t);
 INST(float)
 INST(double)
 

@@ -94,49 +94,93 @@ template <class T>
 void launch_ell_dinv(const Grid& G, const Level& L, hipStream_t s);
 void launch_level_to_f32(const Level& src, const Level& dst, int nd, hipStream_t s);
 
+// ---- multigrid-preconditioned CG driven from the device --------------------------------
+// Control block of one CG solve (device memory).  Every kernel of an iteration returns at
+// once when flag != 0, so the host may enqueue iterations ahead of the convergence test.
+struct CGCtl {
+  double rz[2];   // (r, z) of the last two iterations, slot = iteration & 1
+  double bb;      // ||b||^2
+  double rr;      // ||r||^2 after the last update
+  int flag;       // 0 running, 1 stopped (converged or iteration limit), -1 non-finite
+  int its;        // iterations of the stopped solve
+};
+// partial sums, kRedBlocks doubles each: (b,b), (r,z), (p,q), (r,r)
+enum { kPartBB = 0, kPartRZ = 1, kPartPQ = 2, kPartRR = 3, kPartCount = 4 };
+struct CGArgs {
+  CGCtl* ctl = nullptr;
+  double* part = nullptr;   // kPartCount * kRedBlocks
+  int np = 0;               // partials per sum (cg_partials(N) of level 0)
+  double eta = 1e-4;        // stop when ||r|| < eta ||b||
+  int maxit = 50;
+};
+int cg_partials(size_t n);
+
+// V-cycle pieces.  presmooth with init: first smoothing of a solve (resets the control block,
+// writes the (b, b) partials); restrict with conv_it > 0: also the convergence decision of
+// that iteration; smooth2 with rz: also the (b, x) partials.
 template <class T>
-void launch_mg_presmooth(const Grid& G, const Level& L, const T* b, T* x, hipStream_t s);
+void launch_mg_presmooth(const Grid& G, const Level& L, const T* b, T* x, const CGArgs& g, bool init,
+                         hipStream_t s);
 template <class T>
 void launch_mg_restrict_resid(const Grid& G, const Level& f, const T* b, const T* x, T* bc,
-                              const Level& c, hipStream_t s);
+                              const Level& c, const CGArgs& g, int conv_it, hipStream_t s);
 template <class T>
 void launch_mg_prolong_smooth1(const Grid& G, const Level& f, const T* b, const T* x2, const T* xc,
-                               const Level& c, T* x1, T* d0, hipStream_t s);
+                               const Level& c, T* x1, T* d0, const CGArgs& g, hipStream_t s);
 template <class T>
 void launch_mg_smooth2(const Grid& G, const Level& L, const T* b, const T* x1, const T* d0, T* x,
-                       hipStream_t s);
+                       const CGArgs& g, bool rz, hipStream_t s);
 template <class T>
-void launch_dense_matvec(int n, const double* A, const T* x, T* y, hipStream_t s);
+void launch_dense_matvec(int n, const double* A, const T* x, T* y, const CGArgs& g, hipStream_t s);
 
 // coarse part of a V-cycle (levels of at most kCoarseMaxN cells) in one workgroup
 constexpr int kCoarseMaxN = 1024;
 constexpr int kCoarseThreads = 1024;
 constexpr int kMaxLevels = 12;
+enum { kCoarseInit = 1, kCoarseConv = 2, kCoarseRZ = 4, kCoarseFromPre = 8, kCoarseToUp = 16 };
 struct CoarseArgs {
   int nl, tot;
   int n[kMaxLevels][3], stride[kMaxLevels][3], N[kMaxLevels], off[kMaxLevels];
+  int coff[kMaxLevels];  // offset of the level's coefficients in LDS, -1: read from memory
   int bc[3];
   const void* diag[kMaxLevels];
   const void* w[kMaxLevels][3];
   const void* dinv[kMaxLevels];
   const double* Ainv;   // dense inverse of the last level
   const void* b0;       // right-hand side of the first fused level
-  void* x0;             // result on the first fused level
+  void* x0;             // its iterate: in with kCoarseFromPre, out unless kCoarseToUp
+  void* t1_0;           // out with kCoarseToUp: first post-smoothing step of the first level
+  void* t2_0;
 };
 template <class T>
 void launch_vcycle_coarse(const Grid& G, const Level* lv, int nl, const double* Ainv, const T* b0,
-                          T* x0, hipStream_t s);
+                          T* x0, const CGArgs& g, int mode, int it, hipStream_t s);
+// fused level pairs: restriction f -> c with the first smoothing of c (conv_it > 0: also the
+// convergence decision); second smoothing of c with the prolongation to f and f's first
+// post-smoothing step
+template <class T>
+void launch_mg_down(const Grid& G, const Level& f, const T* bf, const T* xf, const Level& c, T* bc, T* xc,
+                    const CGArgs& g, int conv_it, hipStream_t s);
+template <class T>
+void launch_mg_up(const Grid& G, const Level& c, const T* bc, const T* t1c, const T* t2c, const Level& f,
+                  const T* bf, const T* x2f, T* t1f, T* t2f, const CGArgs& g, hipStream_t s);
 
-// CG pieces: q = A p and out = p.q ; x += a p, r -= a q and out = r.r ; p = z + b p
+// CG iteration it (1-based): apply (p = z + beta p_old, q = A p, (p,q) partials) and update
+// (x += alpha p, r_new = r_old - alpha q, (r,r) partials; with xm != nullptr also the first
+// smoothing of the next V-cycle on level 0)
 template <class T>
-void launch_ell_apply_dot(const Grid& G, const Level& L, const T* p, T* q, double* out,
-                          const RedWS& ws, hipStream_t s);
+void launch_cg_apply(const Grid& G, const Level& L, const T* z, const T* pold, T* pnew, T* q, T* x,
+                     const CGArgs& g, int it, hipStream_t s);
 template <class T>
-void launch_cg_update(size_t n, const double* sc, int i_num, int i_den, T* x, const T* p, T* r,
-                      const T* q, double* rr, const RedWS& ws, hipStream_t s);
+void launch_cg_update(const Grid& G, const Level& L, const T* rold, const T* q, const T* p, T* x, T* rnew,
+                      T* xm, const CGArgs& g, int it, hipStream_t s);
+// when level 0 is itself the dense coarsest level: control reset with (b,b) partials; the
+// convergence decision; the (r,z) partials
 template <class T>
-void launch_cg_pupdate(size_t n, const double* sc, int i_num, int i_den, const T* z, T* p,
-                       hipStream_t s);
+void launch_cg_init(int n, const T* b, const CGArgs& g, hipStream_t s);
+void launch_cg_decide(const CGArgs& g, int it, hipStream_t s);
+template <class T>
+void launch_cg_dot_rz(int n, const T* r, const T* z, const CGArgs& g, hipStream_t s);
 // double <-> float with scaling by 1/sqrt(*nrm2) (to float) or sqrt(*nrm2) (back)
 void launch_cast_scale_f32(size_t n, const double* src, const double* nrm2, float* dst, hipStream_t s);
 void launch_uncast_scale_f64(size_t n, const float* src, const double* nrm2, double* dst, hipStream_t s);

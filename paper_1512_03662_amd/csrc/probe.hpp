@@ -29,6 +29,8 @@ enum KFam {
   KF_PBP_OUT,
   KF_SCALED,
   KF_MG_RESTRICT,
+  KF_MG_DOWN,
+  KF_MG_UP,
   KF_COUNT
 };
 

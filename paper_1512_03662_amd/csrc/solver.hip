@@ -28,12 +28,7 @@ enum Slot {
   S_ZN2 = 1,   // ||R^-1 Z_j||^2
   S_FN2 = 2,   // ||L^-1 F||^2
   S_DXMAX = 3, // ||R^-1 dX||_inf
-  S_BN2 = 4,   // ||b||^2 of an elliptic solve
-  S_PQ = 5,
-  S_RR = 6,
-  S_RZ0 = 7,
-  S_RZ1 = 8,
-  S_TMP = 9,
+  S_TMP = 9,   // ||b||^2 of an FP32 elliptic solve
   S_H1 = 16,                       // h of the first Gram-Schmidt pass (kMaxK)
   S_H2 = S_H1 + kMaxK,             // h of the second pass (kMaxK) then ||w||^2
   S_NRM3 = S_H2 + kMaxK + 1,       // ||w||^2 after the second pass
@@ -74,8 +69,12 @@ struct jfnk_ctx {
   // preconditioner
   EllOp ops[2];
   double *rhs_p = nullptr, *dp = nullptr, *rhs_T = nullptr, *dT = nullptr;
-  double *cg64[4] = {nullptr, nullptr, nullptr, nullptr};  // r, p, q, z
-  float *cg32[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // r p q z b x
+  double* cg64[6] = {};    // r1 r2 p1 p2 q z
+  float* cg32[8] = {};     // r1 r2 p1 p2 q z b x
+  CGCtl* ctl = nullptr;    // control block of the running CG solve
+  CGCtl* hctl = nullptr;   // pinned host copy
+  double* cgpart = nullptr;
+  int cg_pred[2][2] = {{4, 4}, {4, 4}};  // previous iteration count per operator and precision
   int cg_its = 0;
 
   // adjoint
@@ -320,64 +319,125 @@ void ell_setup(jfnk_ctx* c, const double* X, double dt) {
   }
 }
 
+// first level handled by the single-workgroup coarse kernel (nl - 1 when the coarsest
+// level is too large for it and is solved by the dense inverse alone)
+int first_fused(const std::vector<Level>& lv, bool* fused) {
+  const int nl = (int)lv.size();
+  int l0 = nl - 1;
+  *fused = lv[nl - 1].N <= kCoarseMaxN;
+  if (*fused)
+    while (l0 > 0 && lv[l0 - 1].N <= kCoarseMaxN && nl - (l0 - 1) <= kMaxLevels) --l0;
+  return l0;
+}
+
+// The V-cycle z = M r after level 0's first smoothing (already in z), ending with the (r, z)
+// partials; with it > 0 the convergence decision of iteration it is taken on the way down.
+// Requires first_fused(lv) >= 1.  When the coarsest levels run in the single-workgroup
+// kernel, level pairs are fused: down(l -> l+1) = restriction + first smoothing of l+1,
+// up(l -> l-1) = second smoothing of l + prolongation and first post-smoothing of l-1; the
+// coarse kernel starts from the first smoothing of its first level and stops after that
+// level's first post-smoothing step.
 template <class T>
-void vcycle(jfnk_ctx* c, std::vector<Level>& lv, const double* Ainv, const T* r, T* z) {
+void vcycle_rest(jfnk_ctx* c, std::vector<Level>& lv, const double* Ainv, const T* r, T* z,
+                 const CGArgs& g, int it) {
   const Grid& G = c->G;
   hipStream_t s = c->stream;
-  int nl = (int)lv.size();
+  const int nl = (int)lv.size();
+  bool fused;
+  const int l0 = first_fused(lv, &fused);
   auto B = [&](int l) -> const T* { return l == 0 ? r : (const T*)lv[l].b; };
   auto Xl = [&](int l) -> T* { return l == 0 ? z : (T*)lv[l].x; };
-  // levels l0..nl-1 run in one single-workgroup kernel when they are small enough
-  int l0 = nl - 1;
-  const bool fused = lv[nl - 1].N <= kCoarseMaxN;
-  if (fused)
-    while (l0 > 0 && lv[l0 - 1].N <= kCoarseMaxN && nl - (l0 - 1) <= kMaxLevels) --l0;
-  for (int l = 0; l < l0; ++l) {
-    launch_mg_presmooth<T>(G, lv[l], B(l), Xl(l), s);
-    launch_mg_restrict_resid<T>(G, lv[l], B(l), Xl(l), (T*)lv[l + 1].b, lv[l + 1], s);
+  if (fused) {
+    for (int l = 0; l < l0; ++l)
+      launch_mg_down<T>(G, lv[l], B(l), Xl(l), lv[l + 1], (T*)lv[l + 1].b, (T*)lv[l + 1].x, g,
+                        l == 0 ? it : 0, s);
+    launch_vcycle_coarse<T>(G, &lv[l0], nl - l0, Ainv, B(l0), Xl(l0), g, kCoarseFromPre | kCoarseToUp, 0, s);
+    for (int l = l0; l >= 1; --l)
+      launch_mg_up<T>(G, lv[l], B(l), (const T*)lv[l].t1, (const T*)lv[l].t2, lv[l - 1], B(l - 1), Xl(l - 1),
+                      (T*)lv[l - 1].t1, (T*)lv[l - 1].t2, g, s);
+    launch_mg_smooth2<T>(G, lv[0], r, (const T*)lv[0].t1, (const T*)lv[0].t2, z, g, true, s);
+    return;
   }
-  if (fused) launch_vcycle_coarse<T>(G, &lv[l0], nl - l0, Ainv, B(l0), Xl(l0), s);
-  else launch_dense_matvec<T>(lv[nl - 1].N, Ainv, B(nl - 1), Xl(nl - 1), s);
+  // coarsest level solved by its dense inverse alone: one kernel per V-cycle piece
+  launch_mg_restrict_resid<T>(G, lv[0], r, z, (T*)lv[1].b, lv[1], g, it, s);
+  for (int l = 1; l < l0; ++l) {
+    launch_mg_presmooth<T>(G, lv[l], B(l), Xl(l), g, false, s);
+    launch_mg_restrict_resid<T>(G, lv[l], B(l), Xl(l), (T*)lv[l + 1].b, lv[l + 1], g, 0, s);
+  }
+  launch_dense_matvec<T>(lv[nl - 1].N, Ainv, B(nl - 1), Xl(nl - 1), g, s);
   for (int l = l0 - 1; l >= 0; --l) {
     launch_mg_prolong_smooth1<T>(G, lv[l], B(l), Xl(l), Xl(l + 1), lv[l + 1], (T*)lv[l].t1,
-                                 (T*)lv[l].t2, s);
-    launch_mg_smooth2<T>(G, lv[l], B(l), (const T*)lv[l].t1, (const T*)lv[l].t2, Xl(l), s);
+                                 (T*)lv[l].t2, g, s);
+    launch_mg_smooth2<T>(G, lv[l], B(l), (const T*)lv[l].t1, (const T*)lv[l].t2, Xl(l), g, l == 0, s);
   }
 }
 
-// PCG on level 0 of lv: x = A^-1 b (x and b of type T, length N).  bn2 slot holds ||b||^2.
+// PCG on level 0 of lv: x = A^-1 b (x and b of type T, length N), stopping when
+// ||r|| < cg_eta ||b|| or after cg_maxit iterations.  The iterations run from the device
+// (CGCtl); the host enqueues `pred` of them (the previous count of this solver), then one
+// at a time until the control block reports a stop.  v: r1, r2, p1, p2, q, z.
 template <class T>
-int pcg(jfnk_ctx* c, std::vector<Level>& lv, const double* Ainv, const T* b, T* x, T* const* v) {
+int pcg(jfnk_ctx* c, std::vector<Level>& lv, const double* Ainv, const T* b, T* x, T* const* v,
+        int* pred) {
   const Grid& G = c->G;
   hipStream_t s = c->stream;
-  size_t N = (size_t)G.N;
-  T *r = v[0], *p = v[1], *q = v[2], *z = v[3];
-  launch_fill_t<T>(N, T(0), x, s);
-  copy_d2d(c, r, b, N * sizeof(T));
-  launch_dot<T>(N, b, b, c->scal + S_BN2, c->red, s);
-  vcycle<T>(c, lv, Ainv, r, z);
-  launch_dot<T>(N, r, z, c->scal + S_RZ0, c->red, s);
-  copy_d2d(c, p, z, N * sizeof(T));
-  pull(c, S_BN2, 1);
-  const double bn = std::sqrt(c->hscal[S_BN2]);
-  if (!std::isfinite(bn)) throw FiniteErr("non-finite right-hand side in an elliptic solve");
-  if (bn == 0.0) return 0;
-  int cur = S_RZ0, nxt = S_RZ1;
-  int it = 0;
-  for (it = 1; it <= c->opts.cg_maxit; ++it) {
-    launch_ell_apply_dot<T>(G, lv[0], p, q, c->scal + S_PQ, c->red, s);
-    launch_cg_update<T>(N, c->scal, cur, S_PQ, x, p, r, q, c->scal + S_RR, c->red, s);
-    pull(c, S_RR, 1);
-    double rn = std::sqrt(c->hscal[S_RR]);
-    if (!std::isfinite(rn)) throw FiniteErr("non-finite residual in an elliptic solve");
-    if (rn < c->opts.cg_eta * bn) break;
-    if (it == c->opts.cg_maxit) break;
-    vcycle<T>(c, lv, Ainv, r, z);
-    launch_dot<T>(N, r, z, c->scal + nxt, c->red, s);
-    launch_cg_pupdate<T>(N, c->scal, nxt, cur, z, p, s);
-    std::swap(cur, nxt);
+  const int N = G.N;
+  T *r1 = v[0], *r2 = v[1], *p1 = v[2], *p2 = v[3], *q = v[4], *z = v[5];
+  CGArgs g;
+  g.ctl = c->ctl;
+  g.part = c->cgpart;
+  g.np = cg_partials((size_t)N);
+  g.eta = c->opts.cg_eta;
+  g.maxit = c->opts.cg_maxit;
+  bool fused;
+  const int l0 = first_fused(lv, &fused);
+  const int nl = (int)lv.size();
+  // z = M b with the (b, b) and (b, z) partials
+  if (l0 >= 1) {
+    launch_mg_presmooth<T>(G, lv[0], b, z, g, true, s);
+    vcycle_rest<T>(c, lv, Ainv, b, z, g, 0);
+  } else if (fused) {
+    launch_vcycle_coarse<T>(G, &lv[0], nl, Ainv, b, z, g, kCoarseInit | kCoarseRZ, 0, s);
+  } else {
+    launch_cg_init<T>(N, b, g, s);
+    launch_dense_matvec<T>(N, Ainv, b, z, g, s);
+    launch_cg_dot_rz<T>(N, b, z, g, s);
   }
-  return std::min(it, c->opts.cg_maxit);
+  const T* rold = b;
+  T* rnew = r1;
+  const T* pold = z;
+  T* pnew = p1;
+  int enq = 0;
+  int batch = std::max(1, std::min(*pred, g.maxit));
+  for (;;) {
+    for (int k = 0; k < batch && enq < g.maxit; ++k) {
+      const int it = ++enq;
+      launch_cg_apply<T>(G, lv[0], z, pold, pnew, q, x, g, it, s);
+      launch_cg_update<T>(G, lv[0], rold, q, pnew, x, rnew, l0 >= 1 ? z : nullptr, g, it, s);
+      if (l0 >= 1) {
+        vcycle_rest<T>(c, lv, Ainv, rnew, z, g, it);
+      } else if (fused) {
+        launch_vcycle_coarse<T>(G, &lv[0], nl, Ainv, rnew, z, g, kCoarseConv | kCoarseRZ, it, s);
+      } else {
+        launch_cg_decide(g, it, s);
+        launch_dense_matvec<T>(N, Ainv, rnew, z, g, s);
+        launch_cg_dot_rz<T>(N, rnew, z, g, s);
+      }
+      rold = rnew;
+      rnew = (rnew == r1) ? r2 : r1;
+      pold = pnew;
+      pnew = (pnew == p1) ? p2 : p1;
+    }
+    check_launch();
+    HIPX(hipMemcpyAsync(c->hctl, c->ctl, sizeof(CGCtl), hipMemcpyDeviceToHost, s));
+    sync(c);
+    if (c->hctl->flag != 0 || enq >= g.maxit) break;
+    batch = 1;
+  }
+  if (c->hctl->flag < 0) throw FiniteErr("non-finite residual in an elliptic solve");
+  if (c->hctl->flag == 0) throw FiniteErr("elliptic solve ended without a decision");
+  *pred = std::max(1, c->hctl->its);
+  return c->hctl->its;
 }
 
 // x = A_op^-1 b in the configured precision (FP32: b normalised by ||b|| before the cast)
@@ -385,19 +445,14 @@ void ell_solve(jfnk_ctx* c, int o, const double* b, double* x) {
   EllOp& op = c->ops[o];
   size_t N = (size_t)c->G.N;
   if (c->opts.ell_precision == JFNK_FP64) {
-    c->cg_its += pcg<double>(c, op.lv64, op.Ainv, b, x, c->cg64);
+    c->cg_its += pcg<double>(c, op.lv64, op.Ainv, b, x, c->cg64, &c->cg_pred[o][0]);
   } else {
     launch_dot<double>(N, b, b, c->scal + S_TMP, c->red, c->stream);
-    pull(c, S_TMP, 1);
-    if (c->hscal[S_TMP] == 0.0) {
-      launch_fill(N, 0.0, x, c->stream);
-      return;
-    }
-    float* b32 = c->cg32[4];
-    float* x32 = c->cg32[5];
+    float* b32 = c->cg32[6];
+    float* x32 = c->cg32[7];
+    // S_TMP keeps ||b||^2 for the way back (a zero b gives b32 = 0 and x = 0)
     launch_cast_scale_f32(N, b, c->scal + S_TMP, b32, c->stream);
-    // keep ||b|| for the way back: S_TMP is reused by pcg only through S_BN2
-    c->cg_its += pcg<float>(c, op.lv32, op.Ainv, b32, x32, c->cg32);
+    c->cg_its += pcg<float>(c, op.lv32, op.Ainv, b32, x32, c->cg32, &c->cg_pred[o][1]);
     launch_uncast_scale_f64(N, x32, c->scal + S_TMP, x, c->stream);
   }
 }
@@ -702,6 +757,8 @@ void destroy_bufs(jfnk_ctx* c) {
   c->allocs.clear();
   if (c->hscal) (void)hipHostFree(c->hscal);
   c->hscal = nullptr;
+  if (c->hctl) (void)hipHostFree(c->hctl);
+  c->hctl = nullptr;
 }
 
 void create(jfnk_ctx* c) {
@@ -732,9 +789,14 @@ void create(jfnk_ctx* c) {
   c->dp = dalloc<double>(c, N);
   c->rhs_T = dalloc<double>(c, N);
   c->dT = dalloc<double>(c, N);
-  for (int i = 0; i < 4; ++i) c->cg64[i] = dalloc<double>(c, N);
+  for (int i = 0; i < 6; ++i) c->cg64[i] = dalloc<double>(c, N);
   bool want32 = true;  // precision may be switched by jfnk_set_opts
-  for (int i = 0; i < 6; ++i) c->cg32[i] = dalloc<float>(c, N);
+  for (int i = 0; i < 8; ++i) c->cg32[i] = dalloc<float>(c, N);
+  c->ctl = dalloc<CGCtl>(c, 1);
+  HIPX(hipMemsetAsync(c->ctl, 0, sizeof(CGCtl), c->stream));
+  c->cgpart = dalloc<double>(c, (size_t)kPartCount * kRedBlocks);
+  HIPX(hipHostMalloc((void**)&c->hctl, sizeof(CGCtl), hipHostMallocDefault));
+  std::memset(c->hctl, 0, sizeof(CGCtl));
   build_hierarchy(c, c->ops[0], want32);
   build_hierarchy(c, c->ops[1], want32);
   c->vjps = dalloc<double>(c, vjp_scratch_doubles(G));
