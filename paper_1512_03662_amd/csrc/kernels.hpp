@@ -155,6 +155,8 @@ struct CoarseArgs {
 template <class T>
 void launch_vcycle_coarse(const Grid& G, const Level* lv, int nl, const double* Ainv, const T* b0,
                           T* x0, const CGArgs& g, int mode, int it, hipStream_t s);
+// largest coarse level of a fused level pair
+constexpr int kFusePairMaxN = 65536;
 // fused level pairs: restriction f -> c with the first smoothing of c (conv_it > 0: also the
 // convergence decision); second smoothing of c with the prolongation to f and f's first
 // post-smoothing step

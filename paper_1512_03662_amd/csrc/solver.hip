@@ -348,13 +348,40 @@ void vcycle_rest(jfnk_ctx* c, std::vector<Level>& lv, const double* Ainv, const 
   auto B = [&](int l) -> const T* { return l == 0 ? r : (const T*)lv[l].b; };
   auto Xl = [&](int l) -> T* { return l == 0 ? z : (T*)lv[l].x; };
   if (fused) {
-    for (int l = 0; l < l0; ++l)
-      launch_mg_down<T>(G, lv[l], B(l), Xl(l), lv[l + 1], (T*)lv[l + 1].b, (T*)lv[l + 1].x, g,
-                        l == 0 ? it : 0, s);
-    launch_vcycle_coarse<T>(G, &lv[l0], nl - l0, Ainv, B(l0), Xl(l0), g, kCoarseFromPre | kCoarseToUp, 0, s);
-    for (int l = l0; l >= 1; --l)
-      launch_mg_up<T>(G, lv[l], B(l), (const T*)lv[l].t1, (const T*)lv[l].t2, lv[l - 1], B(l - 1), Xl(l - 1),
-                      (T*)lv[l - 1].t1, (T*)lv[l - 1].t2, g, s);
+    // a pair is fused while its coarse level is small (launch-latency bound); on large levels
+    // the halo recomputation costs more than the launch it saves
+    auto fuse = [&](int lc) { return lv[lc].N <= kFusePairMaxN; };
+    // when the fused part is the coarsest level alone it is solved exactly, without smoothing:
+    // the last pair down is a plain restriction and the first pair up a plain prolongation
+    const bool single = (nl - l0 == 1);
+    const int ltop = single ? l0 - 1 : l0;
+    for (int l = 0; l < ltop; ++l) {
+      const int conv = (l == 0) ? it : 0;
+      if (fuse(l + 1)) {
+        launch_mg_down<T>(G, lv[l], B(l), Xl(l), lv[l + 1], (T*)lv[l + 1].b, (T*)lv[l + 1].x, g, conv, s);
+      } else {
+        launch_mg_restrict_resid<T>(G, lv[l], B(l), Xl(l), (T*)lv[l + 1].b, lv[l + 1], g, conv, s);
+        launch_mg_presmooth<T>(G, lv[l + 1], B(l + 1), Xl(l + 1), g, false, s);
+      }
+    }
+    if (single) {
+      const int lp = l0 - 1;
+      launch_mg_restrict_resid<T>(G, lv[lp], B(lp), Xl(lp), (T*)lv[l0].b, lv[l0], g, lp == 0 ? it : 0, s);
+      launch_vcycle_coarse<T>(G, &lv[l0], 1, Ainv, B(l0), Xl(l0), g, 0, 0, s);
+      launch_mg_prolong_smooth1<T>(G, lv[lp], B(lp), Xl(lp), Xl(l0), lv[l0], (T*)lv[lp].t1, (T*)lv[lp].t2, g, s);
+    } else {
+      launch_vcycle_coarse<T>(G, &lv[l0], nl - l0, Ainv, B(l0), Xl(l0), g, kCoarseFromPre | kCoarseToUp, 0, s);
+    }
+    for (int l = ltop; l >= 1; --l) {
+      if (fuse(l)) {
+        launch_mg_up<T>(G, lv[l], B(l), (const T*)lv[l].t1, (const T*)lv[l].t2, lv[l - 1], B(l - 1), Xl(l - 1),
+                        (T*)lv[l - 1].t1, (T*)lv[l - 1].t2, g, s);
+      } else {
+        launch_mg_smooth2<T>(G, lv[l], B(l), (const T*)lv[l].t1, (const T*)lv[l].t2, Xl(l), g, false, s);
+        launch_mg_prolong_smooth1<T>(G, lv[l - 1], B(l - 1), Xl(l - 1), Xl(l), lv[l], (T*)lv[l - 1].t1,
+                                     (T*)lv[l - 1].t2, g, s);
+      }
+    }
     launch_mg_smooth2<T>(G, lv[0], r, (const T*)lv[0].t1, (const T*)lv[0].t2, z, g, true, s);
     return;
   }

@@ -114,8 +114,10 @@ def test_fd_jvp_parity_small(case):
 
 
 @pytest.mark.parametrize("mode", ["sound", "sound_thermal"])
-@pytest.mark.parametrize("shape,bc", [((32, 16), ("periodic", "wall")), ((8, 8, 16), ("periodic", "periodic", "wall"))])
+@pytest.mark.parametrize("shape,bc", [((32, 16), ("periodic", "wall")), ((8, 8, 16), ("periodic", "periodic", "wall")),
+                                      ((96, 20), ("periodic", "wall"))])
 def test_precond_parity(mode, shape, bc):
+    """(96, 20): two multigrid levels, the coarser solved exactly right below a grid level."""
     J = _lib()
     nd = len(shape)
     pd, X = W.random_state(shape, bc, seed=12, g=tuple([0.0] * (nd - 1) + [-1.0]), chi_model="power",
@@ -135,6 +137,27 @@ def test_precond_parity(mode, shape, bc):
     got2 = H(ctx.precond_apply(T(X), T(r)))
     for k in range(P.nvar):
         assert np.max(np.abs(got2[k] - ref2[k])) <= 1e-9 * np.max(np.abs(ref2[k])), k
+
+
+@pytest.mark.parametrize("shape,bc", [((1024, 512), ("periodic", "wall")),
+                                      ((128, 128, 48), ("periodic", "periodic", "wall"))])
+def test_precond_parity_large(shape, bc):
+    """Grids whose finer multigrid levels are large enough to run as separate restriction /
+    smoothing kernels while the coarser ones run fused: the default inner tolerance makes the
+    result depend on every V-cycle, so agreement with the oracle's multigrid CG pins both."""
+    J = _lib()
+    nd = len(shape)
+    pd, X = W.random_state(shape, bc, seed=16, g=tuple([0.0] * (nd - 1) + [-1.0]), chi_model="power",
+                           chi0=0.02, amp=0.2)
+    P = Problem.from_dict(pd)
+    dt = 0.05
+    r = W.random_vector(X, 17)
+    ref = PBP(P, X, dt, "sound_thermal", solver_factory=PCGSolver.factory(1e-4)).apply(r)
+    ctx = J.Context(pd, precond="sound_thermal", cg_eta=1e-4, cg_maxit=50)
+    ctx.set_state_n(T(X), dt)
+    got = H(ctx.precond_apply(T(X), T(r)))
+    for k in range(P.nvar):
+        assert np.max(np.abs(got[k] - ref[k])) <= 1e-9 * np.max(np.abs(ref[k])), k
 
 
 def test_precond_fp32_variant():
