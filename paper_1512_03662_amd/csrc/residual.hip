@@ -11,9 +11,10 @@
 //   R_m,d = -ddiv Phi - (p[c]-p[c-1])/dx_d + rho_f g_d  (zero on wall-normal wall faces).
 // Ideal gas with R = mu = 1: p = (gamma-1) rho e, T = (gamma-1) e.
 //
-// One thread per cell produces all nvar rows of that cell.  The scalar type is double for
-// values, dual for the exact forward-mode product (branches frozen at the value), and the
-// finite-difference product evaluates F at X + delta V with delta of eq. pert_old.
+// Every flux is evaluated once per tile (see tile_axis); each thread then produces all nvar
+// rows of its cell.  The scalar type is double for values, dual for the exact forward-mode
+// product (branches frozen at the value), and the finite-difference product evaluates F at
+// X + delta V with delta of eq. pert_old.
 #include "common.hpp"
 #include "kernels.hpp"
 #include "probe.hpp"
@@ -27,6 +28,7 @@ struct LoadVal {  // T(X)
   __device__ __forceinline__ T operator()(int var, int idx, double s) const {
     return T(s * X[var * N + idx]);
   }
+  __device__ __forceinline__ T operator()(int var, int idx) const { return T(X[var * N + idx]); }
 };
 struct LoadDual {  // dual(X, V)
   const double* X;
@@ -34,6 +36,9 @@ struct LoadDual {  // dual(X, V)
   int N;
   __device__ __forceinline__ dual operator()(int var, int idx, double s) const {
     return dual(s * X[var * N + idx], s * V[var * N + idx]);
+  }
+  __device__ __forceinline__ dual operator()(int var, int idx) const {
+    return dual(X[var * N + idx], V[var * N + idx]);
   }
 };
 struct LoadShift {  // X + delta V
@@ -43,6 +48,9 @@ struct LoadShift {  // X + delta V
   int N;
   __device__ __forceinline__ double operator()(int var, int idx, double s) const {
     return s * (X[var * N + idx] + delta * V[var * N + idx]);
+  }
+  __device__ __forceinline__ double operator()(int var, int idx) const {
+    return X[var * N + idx] + delta * V[var * N + idx];
   }
 };
 
@@ -93,84 +101,6 @@ struct Stencil {
   }
 };
 
-template <int ND, class T, class LD>
-__device__ __forceinline__ void cell_R(const Grid& G, const Pos& P, const LD& ld, T* R) {
-  Stencil<ND, T, LD> S(G, P, ld);
-  const Off o = off0();
-  const double gm1 = G.gamma - 1.0;
-  T f0[ND], f1[ND], fm[ND];
-  T rho0 = S.rho(o);
-  T e0 = S.e(o);
-  T p0 = gm1 * rho0 * e0;
-  T Rrho = T(0.0), RE = T(0.0), divu = T(0.0);
-#pragma unroll
-  for (int d = 0; d < ND; ++d) {
-    T g0, g1;
-    S.mass_energy(d, o, &f0[d], &g0);
-    S.mass_energy(d, shift(o, d, 1), &f1[d], &g1);
-    Rrho = Rrho - (f1[d] - f0[d]) * G.idx[d];
-    RE = RE - (g1 - g0) * G.idx[d];
-    divu = divu + (S.u(d, shift(o, d, 1)) - S.u(d, o)) * G.idx[d];
-  }
-  RE = RE - p0 * divu;
-  if (G.chi_model != 0) {
-#pragma unroll
-    for (int d = 0; d < ND; ++d) RE = RE + (S.cond(d, shift(o, d, 1)) - S.cond(d, o)) * G.idx[d];
-  }
-  R[0] = Rrho;
-  R[1] = RE;
-#pragma unroll
-  for (int d = 0; d < ND; ++d) {
-    if (G.bc[d] == 1 && P.c[d] == 0) {
-      R[2 + d] = T(0.0);
-      continue;
-    }
-    fm[d] = S.mass(d, shift(o, d, -1));
-    // Phi_dd at the centres of c and c - e_d
-    T m0 = 0.5 * (f0[d] + f1[d]);
-    T mm = 0.5 * (fm[d] + f0[d]);
-    T um2 = S.u(d, shift(o, d, -2)), um1 = S.u(d, shift(o, d, -1)), u00 = S.u(d, o);
-    T up1 = S.u(d, shift(o, d, 1)), up2 = S.u(d, shift(o, d, 2));
-    T Pc0 = m0 * upwind(um1, u00, up1, up2, val(m0));
-    T Pcm = mm * upwind(um2, um1, u00, up1, val(mm));
-    T acc = -(Pc0 - Pcm) * G.idx[d];
-#pragma unroll
-    for (int e = 0; e < ND; ++e) {
-      if (e == d) continue;
-      // Phi_de at the (low-d, low-e) edges of c and c + e_e
-      Off oe = shift(o, e, 1);
-      T fa = S.mass(e, shift(o, d, -1));      // f_e[c - e_d]
-      T fb = S.mass(e, shift(oe, d, -1));     // f_e[c - e_d + e_e]
-      T me0 = 0.5 * (fa + f0[e]);
-      T me1 = 0.5 * (fb + f1[e]);
-      T vm2 = S.u(d, shift(o, e, -2)), vm1 = S.u(d, shift(o, e, -1));
-      T vp1 = S.u(d, shift(o, e, 1)), vp2 = S.u(d, shift(o, e, 2));
-      T Pe0 = me0 * upwind(vm2, vm1, u00, vp1, val(me0));
-      T Pe1 = me1 * upwind(vm1, u00, vp1, vp2, val(me1));
-      acc = acc - (Pe1 - Pe0) * G.idx[e];
-    }
-    T rhom = S.rho(shift(o, d, -1));
-    T pm = gm1 * rhom * S.e(shift(o, d, -1));
-    acc = acc - (p0 - pm) * G.idx[d] + 0.5 * (rhom + rho0) * G.g[d];
-    R[2 + d] = acc;
-  }
-}
-
-// U(X) at the cell with the stored (not ghosted) face velocity.
-template <int ND, class T, class LD>
-__device__ __forceinline__ void cell_U(const Grid& G, const Pos& P, const LD& ld, T* U) {
-  Stencil<ND, T, LD> S(G, P, ld);
-  const Off o = off0();
-  T rho0 = S.rho(o);
-  U[0] = rho0;
-  U[1] = rho0 * S.e(o);
-#pragma unroll
-  for (int d = 0; d < ND; ++d) {
-    T rf = 0.5 * (S.rho(shift(o, d, -1)) + rho0);
-    U[2 + d] = rf * ld(2 + d, P.lin, 1.0);
-  }
-}
-
 // L (residual scaling) of the rows of one cell, from X (Sect. 4.1).
 template <int ND>
 __device__ __forceinline__ void cell_L(const Grid& G, const Pos& P, const double* X, double alpha1,
@@ -213,17 +143,298 @@ __device__ __forceinline__ void cell_Rs(const Grid& G, const Pos& P, const doubl
   }
 }
 
+// ---- tiled evaluation of R -------------------------------------------------------------
+// One workgroup owns a tile of cells (32 x 8 in 2D, 8 x 8 x 4 in 3D; one cell per thread).
+// Axis by axis it computes, once per face of the tile and of a one-cell halo, the mass flux
+// f_D and the energy flux minus the conductive flux g_D - q_D into LDS; then, once per cell
+// centre and edge, the momentum fluxes Phi_DD and Phi_eD (e != D) carried along D; finally
+// every thread adds the D-differences of these fluxes to the rows of its own cell.  The
+// state is read from memory through the caches (staging it in LDS with its radius-3 halo
+// costs more occupancy than it saves); tiles whose footprint stays inside the grid skip the
+// ghost rules.
+template <int ND>
+struct RTile;
+template <>
+struct RTile<2> {
+  static constexpr int X = 32, Y = 8, Z = 1;
+};
+template <>
+struct RTile<3> {
+  static constexpr int X = 8, Y = 8, Z = 4;
+};
+
+template <int ND>
+__host__ __device__ constexpr int tile_n(int i) {
+  return i == 0 ? RTile<ND>::X : (i == 1 ? RTile<ND>::Y : RTile<ND>::Z);
+}
+// flux grid of axis D: faces [-1, T_D] along D, [-1, T_e - 1] along the other active axes
+template <int ND, int D>
+__host__ __device__ constexpr int fext(int i) {
+  return i >= ND ? 1 : (i == D ? tile_n<ND>(i) + 2 : tile_n<ND>(i) + 1);
+}
+template <int ND>
+__host__ __device__ constexpr int flo(int i) {
+  return i >= ND ? 0 : -1;
+}
+// cell grid of axis D: [0, T_D] along D, [0, T_e - 1] along the others
+template <int ND, int D>
+__host__ __device__ constexpr int sext(int i) {
+  return i == D ? tile_n<ND>(i) + 1 : tile_n<ND>(i);
+}
+template <int ND, int D>
+__host__ __device__ constexpr int fsize() {
+  return fext<ND, D>(0) * fext<ND, D>(1) * fext<ND, D>(2);
+}
+template <int ND, int D>
+__host__ __device__ constexpr int ssize() {
+  return sext<ND, D>(0) * sext<ND, D>(1) * sext<ND, D>(2);
+}
+__host__ __device__ constexpr int cmax(int a, int b) { return a > b ? a : b; }
+template <int ND>
+__host__ __device__ constexpr int fmaxsz() {
+  return ND == 2 ? cmax(fsize<2, 0>(), fsize<2, 1>()) : cmax(fsize<3, 0>(), cmax(fsize<3, 1>(), fsize<3, 2>()));
+}
+template <int ND>
+__host__ __device__ constexpr int smaxsz() {
+  return ND == 2 ? cmax(ssize<2, 0>(), ssize<2, 1>()) : cmax(ssize<3, 0>(), cmax(ssize<3, 1>(), ssize<3, 2>()));
+}
+static_assert(RTile<2>::X * RTile<2>::Y * RTile<2>::Z == kBlock, "2D tile must have one cell per thread");
+static_assert(RTile<3>::X * RTile<3>::Y * RTile<3>::Z == kBlock, "3D tile must have one cell per thread");
+
+// index and sign of field var at tile-local coordinates q.  IN: the tile's radius-3
+// footprint lies inside the grid (no ghost rules, sign 1).
+template <int ND>
+struct TileIdx {
+  int o[3];
+  int base;
+  bool interior;
+  template <bool IN>
+  __device__ __forceinline__ int at(const Grid& G, int var, const int* q, double* s) const {
+    if constexpr (IN) {
+      *s = 1.0;
+      int i = base + q[0] + q[1] * G.stride[1];
+      if (ND == 3) i += q[2] * G.stride[2];
+      return i;
+    } else {
+      double sign = 1.0;
+      int idx = 0;
+#pragma unroll
+      for (int d = 0; d < ND; ++d) {
+        // coordinates of tiles that overhang the grid are clamped (those cells are not written)
+        int i = min(max(o[d] + q[d], -3), G.n[d] + 2);
+        int src;
+        if (var == 2 + d) {
+          double sd;
+          src = ghost_normal(i, G.n[d], G.bc[d], &sd);
+          sign *= sd;
+        } else {
+          src = ghost_even(i, G.n[d], G.bc[d]);
+        }
+        idx += src * G.stride[d];
+      }
+      *s = sign;
+      return idx;
+    }
+  }
+};
+
+template <int ND>
+__device__ __forceinline__ TileIdx<ND> tile_setup(const Grid& G) {
+  using TT = RTile<ND>;
+  const int nbx = (G.n[0] + TT::X - 1) / TT::X, nby = (G.n[1] + TT::Y - 1) / TT::Y;
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  TileIdx<ND> t;
+  t.o[0] = (b % nbx) * TT::X;
+  t.o[1] = ((b / nbx) % nby) * TT::Y;
+  t.o[2] = (ND == 3) ? (b / (nbx * nby)) * TT::Z : 0;
+  bool in = true;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) in = in && (t.o[d] >= 4) && (t.o[d] + tile_n<ND>(d) + 3 <= G.n[d]);
+  t.interior = in;
+  t.base = t.o[0] + t.o[1] * G.stride[1] + ((ND == 3) ? t.o[2] * G.stride[2] : 0);
+  return t;
+}
+
+template <class T>
+__device__ __forceinline__ T chi_of(const Grid& G, T Tc) {
+  if (G.chi_model == 1) return T(G.chi0);
+  return G.chi0 * powr(Tc * G.chi_tref_inv, G.chi_exp);
+}
+
+// contributions of the fluxes along axis D to the rows R of the thread's own cell l
+template <int ND, int D, class T, class AT>
+__device__ __forceinline__ void tile_axis(const Grid& G, const AT& at, const TileIdx<ND>& ti, const int* l,
+                                          bool own, T* R, T& divu, T* sF, T* sE, T* sP) {
+  constexpr int E0 = fext<ND, D>(0), E1 = fext<ND, D>(1), E2 = fext<ND, D>(2);
+  constexpr int NF = E0 * E1 * E2;
+  constexpr int S0 = sext<ND, D>(0), S1 = sext<ND, D>(1), S2 = sext<ND, D>(2);
+  constexpr int NS = S0 * S1 * S2;
+  constexpr int SM = smaxsz<ND>();
+  const int tid = threadIdx.x;
+  const double gm1 = G.gamma - 1.0;
+  const double ix = G.idx[D];
+  auto fid = [&](const int* q) {
+    return (q[0] - flo<ND>(0)) + (q[1] - flo<ND>(1)) * E0 + (q[2] - flo<ND>(2)) * E0 * E1;
+  };
+  auto sid = [&](const int* q) { return q[0] + q[1] * S0 + q[2] * S0 * S1; };
+  // mass flux on the flux grid; energy minus conductive flux on the cell grid
+  for (int p = tid; p < NF; p += kBlock) {
+    int q[3] = {p % E0 + flo<ND>(0), (p / E0) % E1 + flo<ND>(1), p / (E0 * E1) + flo<ND>(2)};
+    T r[4], ee[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      int qq[3] = {q[0], q[1], q[2]};
+      qq[D] += k - 2;
+      r[k] = at(0, qq);
+      ee[k] = at(1, qq);
+    }
+    const T w = at(2 + D, q);
+    const double wv = val(w);
+    const T f = w * upwind(r[0], r[1], r[2], r[3], wv);
+    sF[p] = f;
+    bool ins = q[D] >= 0;
+#pragma unroll
+    for (int e = 0; e < ND; ++e)
+      if (e != D) ins = ins && q[e] >= 0;
+    if (ins) {
+      T gq = f * upwind(ee[0], ee[1], ee[2], ee[3], wv);
+      if (G.chi_model != 0) {
+        const int fi = ti.o[D] + q[D];
+        T qc;
+        if (G.bc[D] == 1 && fi == 0) {
+          qc = T(G.qwall[D][0]);
+        } else if (G.bc[D] == 1 && fi == G.n[D]) {
+          qc = T(G.qwall[D][1]);
+        } else {
+          const T Tm = gm1 * ee[1], T0 = gm1 * ee[2];
+          const T chif = 0.5 * (chi_of(G, Tm) + chi_of(G, T0));
+          qc = chif * (T0 - Tm) * ix;
+        }
+        gq = gq - qc;
+      }
+      sE[sid(q)] = gq;
+    }
+  }
+  __syncthreads();
+  // momentum fluxes: Phi_DD at the centre of cell q - e_D, Phi_eD at the (low-e, low-D)
+  // edge of cell q
+  for (int p = tid; p < NS; p += kBlock) {
+    int q[3] = {p % S0, (p / S0) % S1, p / (S0 * S1)};
+    int k[3] = {q[0], q[1], q[2]};
+    k[D] -= 1;
+    const T m = 0.5 * (sF[fid(k)] + sF[fid(q)]);
+    T u[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      int kk[3] = {k[0], k[1], k[2]};
+      kk[D] += j - 1;
+      u[j] = at(2 + D, kk);
+    }
+    sP[p] = m * upwind(u[0], u[1], u[2], u[3], val(m));
+    int slot = 1;
+#pragma unroll
+    for (int e = 0; e < ND; ++e) {
+      if (e == D) continue;
+      int qe[3] = {q[0], q[1], q[2]};
+      qe[e] -= 1;
+      const T me = 0.5 * (sF[fid(qe)] + sF[fid(q)]);
+      T v[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        int qq[3] = {q[0], q[1], q[2]};
+        qq[D] += j - 2;
+        v[j] = at(2 + e, qq);
+      }
+      sP[slot * SM + p] = me * upwind(v[0], v[1], v[2], v[3], val(me));
+      ++slot;
+    }
+  }
+  __syncthreads();
+  if (own) {
+    int lp[3] = {l[0], l[1], l[2]};
+    lp[D] += 1;
+    R[0] = R[0] - (sF[fid(lp)] - sF[fid(l)]) * ix;
+    R[1] = R[1] - (sE[sid(lp)] - sE[sid(l)]) * ix;
+    divu = divu + (at(2 + D, lp) - at(2 + D, l)) * ix;
+    R[2 + D] = R[2 + D] - (sP[sid(lp)] - sP[sid(l)]) * ix;
+    int slot = 1;
+#pragma unroll
+    for (int e = 0; e < ND; ++e) {
+      if (e == D) continue;
+      R[2 + e] = R[2 + e] - (sP[slot * SM + sid(lp)] - sP[slot * SM + sid(l)]) * ix;
+      ++slot;
+    }
+  }
+  __syncthreads();
+}
+
+template <int ND, bool IN, class T, class LD>
+__device__ __forceinline__ bool tile_RU_in(const Grid& G, const LD& ld, const TileIdx<ND>& ti, T* R, T* U,
+                                           int* lin_out, T* sF, T* sE, T* sP) {
+  using TT = RTile<ND>;
+  const int t = threadIdx.x;
+  auto at = [&](int var, const int* q) -> T {
+    double s;
+    const int i = ti.template at<IN>(G, var, q, &s);
+    if constexpr (IN) return ld(var, i);
+    else return ld(var, i, s);
+  };
+  const int l[3] = {t % TT::X, (t / TT::X) % TT::Y, t / (TT::X * TT::Y)};
+  bool own = true;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) own = own && (ti.o[d] + l[d] < G.n[d]);
+#pragma unroll
+  for (int v = 0; v < 2 + ND; ++v) R[v] = T(0.0);
+  T divu = T(0.0);
+  tile_axis<ND, 0>(G, at, ti, l, own, R, divu, sF, sE, sP);
+  tile_axis<ND, 1>(G, at, ti, l, own, R, divu, sF, sE, sP);
+  if constexpr (ND == 3) tile_axis<ND, 2>(G, at, ti, l, own, R, divu, sF, sE, sP);
+  if (!own) return false;
+  const double gm1 = G.gamma - 1.0;
+  const T rho0 = at(0, l), e0 = at(1, l);
+  const T p0 = gm1 * rho0 * e0;
+  R[1] = R[1] - p0 * divu;
+  const int lin = ti.base + l[0] + l[1] * G.stride[1] + ((ND == 3) ? l[2] * G.stride[2] : 0);
+  U[0] = rho0;
+  U[1] = rho0 * e0;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    int lm[3] = {l[0], l[1], l[2]};
+    lm[d] -= 1;
+    const T rhom = at(0, lm);
+    const T rf = 0.5 * (rhom + rho0);
+    U[2 + d] = rf * ld(2 + d, lin, 1.0);  // the stored (not ghosted) face velocity
+    if (G.bc[d] == 1 && ti.o[d] + l[d] == 0) {
+      R[2 + d] = T(0.0);
+    } else {
+      const T pm = gm1 * rhom * at(1, lm);
+      R[2 + d] = R[2 + d] - (p0 - pm) * G.idx[d] + rf * G.g[d];
+    }
+  }
+  *lin_out = lin;
+  return true;
+}
+
+// R and U of the thread's cell; returns false (outputs unset) when the thread's cell lies
+// outside the grid.  Every thread of the block must call it (it synchronises the block).
+template <int ND, class T, class LD>
+__device__ __forceinline__ bool tile_RU(const Grid& G, const LD& ld, T* R, T* U, int* lin_out) {
+  __shared__ T sF[fmaxsz<ND>()];
+  __shared__ T sE[smaxsz<ND>()];
+  __shared__ T sP[ND * smaxsz<ND>()];
+  const TileIdx<ND> ti = tile_setup<ND>(G);
+  if (ti.interior) return tile_RU_in<ND, true>(G, ld, ti, R, U, lin_out, sF, sE, sP);
+  return tile_RU_in<ND, false>(G, ld, ti, R, U, lin_out, sF, sE, sP);
+}
+
 // ---- kernels --------------------------------------------------------------------------
 template <int ND>
 __global__ void __launch_bounds__(kBlock) k_resid_value(Grid G, ResidArgs a) {
-  int lin = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (lin >= G.N) return;
-  Pos P = make_pos<ND>(G, lin);
   LoadVal<double> ld{a.X, G.N};
   double R[2 + ND], U[2 + ND], L[2 + ND];
-  cell_R<ND>(G, P, ld, R);
-  cell_U<ND>(G, P, ld, U);
-  if (a.scaleL) cell_L<ND>(G, P, a.X, a.alpha1, L);
+  int lin;
+  if (!tile_RU<ND>(G, ld, R, U, &lin)) return;
+  if (a.scaleL) cell_L<ND>(G, make_pos<ND>(G, lin), a.X, a.alpha1, L);
 #pragma unroll
   for (int v = 0; v < 2 + ND; ++v) {
     double gv = a.cU * U[v] + a.cR * R[v];
@@ -237,15 +448,12 @@ __global__ void __launch_bounds__(kBlock) k_resid_value(Grid G, ResidArgs a) {
 
 template <int ND>
 __global__ void __launch_bounds__(kBlock) k_resid_tangent(Grid G, ResidArgs a) {
-  int lin = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (lin >= G.N) return;
-  Pos P = make_pos<ND>(G, lin);
   LoadDual ld{a.X, a.V, G.N};
   dual R[2 + ND], U[2 + ND];
   double L[2 + ND];
-  cell_R<ND>(G, P, ld, R);
-  cell_U<ND>(G, P, ld, U);
-  if (a.scaleL) cell_L<ND>(G, P, a.X, a.alpha1, L);
+  int lin;
+  if (!tile_RU<ND>(G, ld, R, U, &lin)) return;
+  if (a.scaleL) cell_L<ND>(G, make_pos<ND>(G, lin), a.X, a.alpha1, L);
 #pragma unroll
   for (int v = 0; v < 2 + ND; ++v) {
     double out = a.cU * U[v].d + a.cR * R[v].d;
@@ -256,26 +464,27 @@ __global__ void __launch_bounds__(kBlock) k_resid_tangent(Grid G, ResidArgs a) {
 
 template <int ND>
 __global__ void __launch_bounds__(kBlock) k_resid_fd(Grid G, ResidArgs a) {
-  int lin = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (lin >= G.N) return;
   const double xn2 = a.fd_norms[0], zn2 = a.fd_norms[1];
-  double L[2 + ND];
-  if (a.scaleL) {
-    Pos P0 = make_pos<ND>(G, lin);
-    cell_L<ND>(G, P0, a.X, a.alpha1, L);
-  }
-  if (!(zn2 > 0.0)) {
+  if (!(zn2 > 0.0)) {  // the same for every thread: no block-wide work follows
+    const TileIdx<ND> ti = tile_setup<ND>(G);
+    using TT = RTile<ND>;
+    const int t = threadIdx.x;
+    const int l[3] = {t % TT::X, (t / TT::X) % TT::Y, t / (TT::X * TT::Y)};
+#pragma unroll
+    for (int d = 0; d < ND; ++d)
+      if (ti.o[d] + l[d] >= G.n[d]) return;
+    const int lin = ti.base + l[0] + l[1] * G.stride[1] + ((ND == 3) ? l[2] * G.stride[2] : 0);
 #pragma unroll
     for (int v = 0; v < 2 + ND; ++v) a.out[v * G.N + lin] = 0.0;
     return;
   }
   const double lam = a.fd_lambda;
   const double delta = lam * (lam + sqrt(xn2) / sqrt(zn2));
-  Pos P = make_pos<ND>(G, lin);
   LoadShift ld{a.X, a.V, delta, G.N};
-  double R[2 + ND], U[2 + ND];
-  cell_R<ND>(G, P, ld, R);
-  cell_U<ND>(G, P, ld, U);
+  double R[2 + ND], U[2 + ND], L[2 + ND];
+  int lin;
+  if (!tile_RU<ND>(G, ld, R, U, &lin)) return;
+  if (a.scaleL) cell_L<ND>(G, make_pos<ND>(G, lin), a.X, a.alpha1, L);
 #pragma unroll
   for (int v = 0; v < 2 + ND; ++v) {
     double out = (a.cU * U[v] + a.cR * R[v] - a.B[v * G.N + lin]) / delta;
@@ -304,8 +513,15 @@ __global__ void __launch_bounds__(kBlock) k_scale_LR(Grid G, const double* X, do
 // ---- launchers ------------------------------------------------------------------------
 static inline dim3 cells_grid(const Grid& G) { return dim3((G.N + kBlock - 1) / kBlock); }
 
+template <int ND>
+static dim3 tile_grid(const Grid& G) {
+  int b = 1;
+  for (int d = 0; d < ND; ++d) b *= (G.n[d] + tile_n<ND>(d) - 1) / tile_n<ND>(d);
+  return dim3(b);
+}
+
 void launch_resid(const Grid& G, const ResidArgs& a, int mode, hipStream_t s) {
-  dim3 gr = cells_grid(G), bl(kBlock);
+  dim3 gr = (G.nd == 2) ? tile_grid<2>(G) : tile_grid<3>(G), bl(kBlock);
   // algorithmic bytes: every field read or written once (FP64)
   const double nvN = 8.0 * (2 + G.nd) * G.N;
   int fam;
