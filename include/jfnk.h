@@ -116,7 +116,10 @@ const char* jfnk_last_error(const jfnk_ctx* ctx);
 int jfnk_set_state_n(jfnk_ctx* ctx, const double* Xn, double dt);
 
 /* F = U(X)/dt - theta R(X) - b (eq. crank_nicholson), R the staggered finite-volume
- * operator (Sect. 2) as specified in the design notes.  Needs jfnk_set_state_n.        */
+ * operator of Sect. 2 (van Leer upwind mass, energy and momentum fluxes, p div u,
+ * conduction, gravity; ghost rules per axis: periodic wrap, or walls with even mirror and
+ * zero wall-normal velocity).  Device pointers, FP64 SoA; async on the context's stream.
+ * Needs jfnk_set_state_n.                                                              */
 int jfnk_residual(jfnk_ctx* ctx, const double* X, double* F);
 
 /* J v with J = dF/dX at X.  mode JFNK_JV_FD: (F(X + delta v) - F(X))/delta with

@@ -8,7 +8,7 @@ apply the semi-implicit scheme, transform back) with the semi-implicit schemes o
 the energy row) and Sect. 3.4 (sound + thermal diffusion, eqs. SI4_p_final..SI4_u_final),
 and the transformation matrices of Sect. 3.2 (internal-energy form, derived in App. B).
 
-Readings where the paper is silent (each stated in the design notes):
+Readings where the paper is silent:
 * the operator maps r -> z ~ +J^-1 r (the paper's delta form gives -J^-1 r);
 * coefficients are frozen at the current Newton iterate;
 * the pressure row is row-scaled by 1/(Gamma1 p) so that
