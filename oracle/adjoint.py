@@ -4,8 +4,8 @@ TEST INFRASTRUCTURE ONLY.
 
 For the step F(X^{n+1}; X^n) = 0 with F = U(X)/dt - theta R(X) - U(X^n)/dt - (1-theta) R(X^n)
 (eq. crank_nicholson, theta-weighted) and a loss L(X^{n+1}), the implicit-function theorem
-gives dL/dX^n = -(dF/dX^n)^T lam with J^T lam = dL/dX^{n+1}, J = dF/dX^{n+1}.  For
-theta = 1: dL/dX^n = (dU/dX|_{X^n})^T lam / dt.
+gives dL/dX^n = -(dF/dX^n)^T lam with J^T lam = dL/dX^{n+1}, J = dF/dX^{n+1}, i.e.
+dL/dX^n = (dU/dX|_{X^n})^T lam / dt + (1 - theta) (dR/dX|_{X^n})^T lam.
 
 * ``vjp_sparse``   J^T w from the coloured complex-step Jacobian (exact, frozen branches).
 * ``dU_dX_T``      (dU/dX)^T lam written out from U = (rho, rho e, rho_f u_d).
@@ -19,6 +19,8 @@ complex-step J.v; dU_dX_T against complex steps of U; the step adjoint against c
 finite differences of whole exact steps; FGMRES adjoint against the LU adjoint.
 """
 from __future__ import annotations
+
+import dataclasses
 
 import numpy as np
 import scipy.sparse.linalg as spla
@@ -60,20 +62,29 @@ def dU_dX_T(prob: Problem, X, lam):
     return out
 
 
-def adjoint_step_exact(prob: Problem, Xn1, Xn, dt, gbar):
+def dXn_T(prob: Problem, Xn, dt, lam):
+    """-(dF/dX^n)^T lam = (dU/dX)^T lam / dt + (1 - theta) (dR/dX)^T lam at X^n."""
+    out = dU_dX_T(prob, Xn, lam) / dt
     if prob.theta != 1.0:
-        raise NotImplementedError("adjoint written for backward Euler (theta = 1)")
+        # dR/dX from the complex-step Jacobian of the backward-Euler residual at X^n:
+        # J1 = dU/dX / dt - dR/dX, so (dR/dX)^T lam = (dU/dX)^T lam / dt - J1^T lam
+        p1 = dataclasses.replace(prob, theta=1.0)
+        J1 = jacobian_sparse(p1, Xn, np.zeros_like(Xn), dt)
+        dRT = dU_dX_T(prob, Xn, lam) / dt - (J1.T @ lam.ravel()).reshape(lam.shape)
+        out = out + (1.0 - prob.theta) * dRT
+    return out
+
+
+def adjoint_step_exact(prob: Problem, Xn1, Xn, dt, gbar):
     b = rhs_b(prob, Xn, dt)
     J = jacobian_sparse(prob, Xn1, b, dt)
     lam = spla.spsolve(J.T.tocsc(), gbar.ravel()).reshape(Xn1.shape)
-    return dU_dX_T(prob, Xn, lam) / dt, lam
+    return dXn_T(prob, Xn, dt, lam), lam
 
 
 def adjoint_step_fgmres(prob: Problem, Xn1, Xn, dt, gbar, precond="sound", eta=1e-10,
                         m=30, maxit=300, alpha1=1e-5, alpha2=1.0, elliptic="direct",
                         cg_eta=1e-4, info_out=None):
-    if prob.theta != 1.0:
-        raise NotImplementedError("adjoint written for backward Euler (theta = 1)")
     b = rhs_b(prob, Xn, dt)
     J = jacobian_sparse(prob, Xn1, b, dt)
     L, R = scaling_LR(prob, Xn1, alpha1, alpha2)
@@ -87,4 +98,4 @@ def adjoint_step_fgmres(prob: Problem, Xn1, Xn, dt, gbar, precond="sound", eta=1
     lam, info = fgmres(apply_op, apply_prec, R * gbar, eta, m, maxit)
     if info_out is not None:
         info_out.update(info)
-    return dU_dX_T(prob, Xn, lam) / dt, lam
+    return dXn_T(prob, Xn, dt, lam), lam

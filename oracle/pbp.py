@@ -228,7 +228,13 @@ class PBP:
     """
 
     def __init__(self, prob: Problem, X, dt, mode="sound", solver_factory=None):
-        self.prob, self.X, self.dt, self.mode = prob, X, dt, mode
+        # theta-weighted step (eq. crank_nicholson): J = dU/dX / dt - theta dR/dX
+        # = theta (dU/dX / tau - dR/dX) with tau = theta dt, so the scheme is built with the
+        # implicit time step tau and its result divided by theta (theta = 1: tau = dt).
+        self.prob, self.X, self.mode = prob, X, mode
+        self.dt = prob.theta * dt
+        self.zscale = 1.0 / prob.theta
+        dt = self.dt
         sf = solver_factory or DirectSolver
         self.Ap = pressure_operator(prob, X, dt)
         self.solve_p = sf(self.Ap)
@@ -257,7 +263,7 @@ class PBP:
             z[2 + d] = dt * (Fu[d] - grad_face(prob, X, dp, d))
         z[1] = de
         z[0] = (dp - dpde * de) / dpdr
-        return z
+        return z * self.zscale
 
     def apply_T(self, w):
         """Transpose of ``apply`` (the elliptic solves are self-adjoint)."""
@@ -285,4 +291,4 @@ class PBP:
             Fp_b = -t / g
         s = self.solve_p(dp_b)
         Fp_b = Fp_b + s / (g * p)
-        return transform_in_T(prob, X, Fp_b, Fe_b, Fu_b)
+        return transform_in_T(prob, X, Fp_b, Fe_b, Fu_b) * self.zscale

@@ -1101,7 +1101,7 @@ __global__ void __launch_bounds__(kBlock) k_pbp_rhsT(Grid G, const double* X, co
 template <int ND>
 __global__ void __launch_bounds__(kBlock) k_pbp_out(Grid G, const double* X, const double* v, int scaled,
                                                     double alpha1, double dt, const double* dp,
-                                                    const double* dT, double* z) {
+                                                    const double* dT, double zs, double* z) {
   int lin = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (lin >= G.N) return;
   Pos P = make_pos<ND>(G, lin);
@@ -1117,8 +1117,8 @@ __global__ void __launch_bounds__(kBlock) k_pbp_out(Grid G, const double* X, con
   double de;
   if (dT) de = dT[lin] / gm1;
   else de = dt * Fe + (dpc - dt * Fp) / (G.gamma * rho);
-  z[lin] = (dpc - dpde * de) / dpdr;
-  z[G.N + lin] = de;
+  z[lin] = zs * ((dpc - dpde * de) / dpdr);
+  z[G.N + lin] = zs * de;
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
     double s;
@@ -1139,7 +1139,7 @@ __global__ void __launch_bounds__(kBlock) k_pbp_out(Grid G, const double* X, con
     double rbar = 0.5 * (r0m + r0c);
     double Fu = (rm - ud * rbar) / rf;
     double grad = (G.bc[d] == 1 && P.c[d] == 0) ? 0.0 : (dpc - dp[im]) / (rf * G.dx[d]);
-    z[(2 + d) * G.N + lin] = dt * (Fu - grad);
+    z[(2 + d) * G.N + lin] = zs * (dt * (Fu - grad));
   }
 }
 
@@ -1156,10 +1156,12 @@ void launch_pbp_rhsT(const Grid& G, const double* X, const double* v, int scaled
   k_pbp_rhsT<<<CELLS(G.N), 0, s>>>(G, X, v, scaled, dt, dp, rhs_T);
 }
 void launch_pbp_out(const Grid& G, const double* X, const double* v, int scaled, double alpha1,
-                    double dt, const double* dp, const double* dT, double* z, hipStream_t s) {
+                    double dt, const double* dp, const double* dT, double zscale, double* z, hipStream_t s) {
   const double by = 8.0 * G.N * (3.0 * (2 + G.nd) + 1 + (dT ? 1 : 0));
-  if (G.nd == 2) launch_k(KF_PBP_OUT, by, k_pbp_out<2>, CELLS(G.N), 0, s, G, X, v, scaled, alpha1, dt, dp, dT, z);
-  else launch_k(KF_PBP_OUT, by, k_pbp_out<3>, CELLS(G.N), 0, s, G, X, v, scaled, alpha1, dt, dp, dT, z);
+  if (G.nd == 2)
+    launch_k(KF_PBP_OUT, by, k_pbp_out<2>, CELLS(G.N), 0, s, G, X, v, scaled, alpha1, dt, dp, dT, zscale, z);
+  else
+    launch_k(KF_PBP_OUT, by, k_pbp_out<3>, CELLS(G.N), 0, s, G, X, v, scaled, alpha1, dt, dp, dT, zscale, z);
 }
 
 // ---- explicit instantiations ---------------------------------------------------------------

@@ -484,6 +484,11 @@ void ell_solve(jfnk_ctx* c, int o, const double* b, double* x) {
   }
 }
 
+// Implicit time step of the semi-implicit scheme: a theta-weighted step has
+// J = dU/dX / dt - theta dR/dX = theta (dU/dX / tau - dR/dX) with tau = theta dt, so the
+// scheme is built with tau and its result divided by theta (eq. crank_nicholson).
+double si_dt(const jfnk_ctx* c) { return c->prob.theta * c->dt; }
+
 // Z = M^-1 v (scaled = 1: v is a scaled basis vector, r = L v) at the frozen state X
 void precond(jfnk_ctx* c, const double* X, const double* v, int scaled, double* z) {
   const Grid& G = c->G;
@@ -494,15 +499,16 @@ void precond(jfnk_ctx* c, const double* X, const double* v, int scaled, double* 
     else copy_d2d(c, z, v, c->n * sizeof(double));
     return;
   }
-  launch_pbp_in(G, X, v, scaled, o.alpha1, c->dt, c->rhs_p, s);
+  const double tau = si_dt(c);
+  launch_pbp_in(G, X, v, scaled, o.alpha1, tau, c->rhs_p, s);
   ell_solve(c, 0, c->rhs_p, c->dp);
   const double* dT = nullptr;
   if (o.precond == JFNK_PC_SOUND_THERMAL) {
-    launch_pbp_rhsT(G, X, v, scaled, o.alpha1, c->dt, c->dp, c->rhs_T, s);
+    launch_pbp_rhsT(G, X, v, scaled, o.alpha1, tau, c->dp, c->rhs_T, s);
     ell_solve(c, 1, c->rhs_T, c->dT);
     dT = c->dT;
   }
-  launch_pbp_out(G, X, v, scaled, o.alpha1, c->dt, c->dp, dT, z, s);
+  launch_pbp_out(G, X, v, scaled, o.alpha1, tau, c->dp, dT, 1.0 / c->prob.theta, z, s);
   check_launch();
 }
 
@@ -517,15 +523,16 @@ void precond_T(jfnk_ctx* c, const double* X, const double* v, int scaled, double
     return;
   }
   const bool thermal = (o.precond == JFNK_PC_SOUND_THERMAL);
-  launch_pbpT_in(G, X, v, scaled, o.alpha2, c->dt, thermal ? 1 : 0, c->rhs_p, c->rhs_T, s);
+  const double tau = si_dt(c);
+  launch_pbpT_in(G, X, v, scaled, o.alpha2, tau, thermal ? 1 : 0, c->rhs_p, c->rhs_T, s);
   const double* t = nullptr;
   if (thermal) {
     ell_solve(c, 1, c->rhs_T, c->dT);
-    launch_pbpT_mid(G, c->dt, c->dT, c->rhs_p, s);
+    launch_pbpT_mid(G, tau, c->dT, c->rhs_p, s);
     t = c->dT;
   }
   ell_solve(c, 0, c->rhs_p, c->dp);
-  launch_pbpT_out(G, X, v, scaled, o.alpha2, c->dt, c->dp, t, z, s);
+  launch_pbpT_out(G, X, v, scaled, o.alpha2, tau, c->dp, t, 1.0 / c->prob.theta, z, s);
   check_launch();
 }
 
@@ -707,7 +714,7 @@ int implicit_step(jfnk_ctx* c, double* X, double dt, jfnk_step_stats* st) {
     S.f_norm = fn;
     double dxmax = 0.0;
     if (fn > 0.0) {
-      if (o.precond != JFNK_PC_NONE) ell_setup(c, X, dt);
+      if (o.precond != JFNK_PC_NONE) ell_setup(c, X, c->prob.theta * dt);
       GmresOut go = fgmres(c, X, fn, -1.0);
       S.gmres_its += go.iters;
       launch_scaled_maxabs(G, X, c->dX, o.alpha2, c->scal + S_DXMAX, c->red, s);
@@ -761,7 +768,7 @@ int adjoint_step(jfnk_ctx* c, const double* Xn1, const double* Xn, double dt, co
     S.converged = 1;
   } else {
     AdjGuard guard(c);
-    if (o.precond != JFNK_PC_NONE) ell_setup(c, Xn1, dt);
+    if (o.precond != JFNK_PC_NONE) ell_setup(c, Xn1, c->prob.theta * dt);
     GmresOut go = fgmres(c, Xn1, bn, 1.0);
     S.gmres_its = go.iters;
     S.converged = go.converged ? 1 : 0;
@@ -996,7 +1003,7 @@ int jfnk_precond_apply(jfnk_ctx* c, const double* X, const double* r, double* z)
   if (!X || !r || !z) throw InvErr("null array");
   if (!c->have_state) throw InvErr("jfnk_set_state_n must be called first");
   c->cg_its = 0;
-  if (c->opts.precond != JFNK_PC_NONE) ell_setup(c, X, c->dt);
+  if (c->opts.precond != JFNK_PC_NONE) ell_setup(c, X, si_dt(c));
   precond(c, X, r, 0, z);
   sync(c);
   return JFNK_OK;

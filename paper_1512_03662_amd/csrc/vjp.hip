@@ -557,7 +557,7 @@ __global__ void __launch_bounds__(kBlock) k_pbpT_mid(Grid G, double dt, const do
 template <int ND>
 __global__ void __launch_bounds__(kBlock) k_pbpT_out(Grid G, const double* X, const double* v, int scaled,
                                                      double alpha2, double dt, const double* sp,
-                                                     const double* t, double* z) {
+                                                     const double* t, double zs, double* z) {
   int lin = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (lin >= G.N) return;
   Pos P = make_pos<ND>(G, lin);
@@ -589,7 +589,7 @@ __global__ void __launch_bounds__(kBlock) k_pbpT_out(Grid G, const double* X, co
     int im = gidx<ND>(G, P, 0, shift(off0(), d, -1), &s);
     double rf = 0.5 * (X[im] + rho);
     double Fu_b = dt * w_face<ND>(G, X, v, scaled, alpha2, d, lin);
-    z[(2 + d) * N + lin] = Fu_b / rf;
+    z[(2 + d) * N + lin] = zs * (Fu_b / rf);
     // the F_u row of face f reads rbar = (r_rho[f-1] + r_rho[f])/2 with coefficient -u/rho_f
     double a0 = -X[(2 + d) * N + lin] * Fu_b / rf;
     r0 += 0.5 * a0;
@@ -602,8 +602,8 @@ __global__ void __launch_bounds__(kBlock) k_pbpT_out(Grid G, const double* X, co
       r0 += 0.5 * (-X[(2 + d) * N + ip] * Fu_bp / rfp);
     }
   }
-  z[lin] = r0;
-  z[N + lin] = r1;
+  z[lin] = zs * r0;
+  z[N + lin] = zs * r1;
 }
 
 void launch_pbpT_in(const Grid& G, const double* X, const double* v, int scaled, double alpha2,
@@ -617,10 +617,10 @@ void launch_pbpT_mid(const Grid& G, double dt, const double* t, double* rhs_p, h
   k_pbpT_mid<<<gr, kBlock, 0, s>>>(G, dt, t, rhs_p);
 }
 void launch_pbpT_out(const Grid& G, const double* X, const double* v, int scaled, double alpha2,
-                     double dt, const double* sp, const double* t, double* z, hipStream_t s) {
+                     double dt, const double* sp, const double* t, double zscale, double* z, hipStream_t s) {
   dim3 gr((G.N + kBlock - 1) / kBlock);
-  if (G.nd == 2) k_pbpT_out<2><<<gr, kBlock, 0, s>>>(G, X, v, scaled, alpha2, dt, sp, t, z);
-  else k_pbpT_out<3><<<gr, kBlock, 0, s>>>(G, X, v, scaled, alpha2, dt, sp, t, z);
+  if (G.nd == 2) k_pbpT_out<2><<<gr, kBlock, 0, s>>>(G, X, v, scaled, alpha2, dt, sp, t, zscale, z);
+  else k_pbpT_out<3><<<gr, kBlock, 0, s>>>(G, X, v, scaled, alpha2, dt, sp, t, zscale, z);
 }
 
 size_t vjp_scratch_doubles(const Grid& G) {

@@ -90,11 +90,20 @@ def test_vjp_prev_parity():
     assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref))
 
 
+def _with_theta(w_, theta):
+    w_ = dict(w_)
+    w_["problem"] = dict(w_["problem"], theta=theta)
+    return w_
+
+
 ADJ_CASES = [
     ("bump_16", lambda: W.acoustic_bump_2d(n=16), "sound"),
     ("strat_16x24_thermal", lambda: W.polytrope((16, 24), 10.0, mach=1e-3, seed=5, chi_model="power",
                                                 steps=1, cfl=50.0), "sound_thermal"),
     ("tg_3d_8", lambda: W.taylor_green_3d(n=8, mach=1e-2), "sound"),
+    ("strat_16x24_thermal_cn", lambda: _with_theta(W.polytrope((16, 24), 10.0, mach=1e-3, seed=5,
+                                                               chi_model="power", steps=1, cfl=50.0), 0.5),
+     "sound_thermal"),
 ]
 
 

@@ -205,6 +205,33 @@ def test_implicit_step_stratified_thermal(prec):
     assert err <= 1e-8, (err, st)
 
 
+@pytest.mark.parametrize("prec,jv", [("sound", "fd"), ("sound_thermal", "exact")])
+def test_implicit_step_crank_nicolson(prec, jv):
+    """theta = 1/2 (eq. crank_nicholson): the step against the oracle's exact root."""
+    w = W.polytrope((32, 32), 10.0, mach=1e-3, seed=5, chi_model="power", steps=1, cfl=50.0)
+    pd = dict(w["problem"])
+    pd["theta"] = 0.5
+    err, st = _step_parity(pd, w["X0"], 50.0, precond=prec, jv_mode=jv)
+    assert err <= 1e-8, (err, st)
+
+
+@pytest.mark.parametrize("mode", ["sound", "sound_thermal"])
+def test_precond_parity_crank_nicolson(mode):
+    J = _lib()
+    pd, X = W.random_state((32, 16), ("periodic", "wall"), seed=12, g=(0.0, -1.0), chi_model="power",
+                           chi0=0.02, amp=0.2)
+    pd["theta"] = 0.5
+    P = Problem.from_dict(pd)
+    dt = 0.05
+    r = W.random_vector(X, 13)
+    ref = PBP(P, X, dt, mode).apply(r)
+    ctx = J.Context(pd, precond=mode, cg_eta=1e-13, cg_maxit=200)
+    ctx.set_state_n(T(X), dt)
+    got = H(ctx.precond_apply(T(X), T(r)))
+    for k in range(P.nvar):
+        assert np.max(np.abs(got[k] - ref[k])) <= 1e-10 * np.max(np.abs(ref[k])), k
+
+
 def test_implicit_step_unpreconditioned_small_cfl():
     w = W.acoustic_bump_2d(n=16)
     err, st = _step_parity(w["problem"], w["X0"], 1.0, precond="none", alpha1=1.0)

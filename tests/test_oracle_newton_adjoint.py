@@ -1,8 +1,9 @@
 """Pins of the oracle implicit step (Sect. 4) and its adjoint.
 
 * exact Newton converges quadratically to roundoff;
-* linear acoustics: one backward-Euler step of a standing sound wave damps it by the closed
-  form of the discrete wave equation (Sect. 3.3.1 derives the wave equation a^2 = Gamma1 p/rho);
+* linear acoustics: one theta-step (backward Euler, Crank-Nicolson, theta = 3/4) of a
+  standing sound wave scales it by the closed form of the discrete wave equation (Sect. 3.3.1
+  derives the wave equation a^2 = Gamma1 p/rho; eq. crank_nicholson the theta-weighting);
 * hydrostatic equilibrium survives a large step;
 * JFNK + PBP (Sect. 4) reaches the exact root within its tolerance;
 * the adjoint step matches central differences of whole exact steps.
@@ -33,9 +34,14 @@ def test_exact_newton_quadratic():
     assert np.max(np.abs(F)) < 1e-10
 
 
+@pytest.mark.parametrize("theta", [1.0, 0.5, 0.75])
 @pytest.mark.parametrize("shape,modes,cfl", [((16, 16), (1, 2), 1.0), ((16, 16), (2, 1), 30.0),
                                              ((8, 8, 8), (1, 1, 2), 100.0)])
-def test_linear_acoustics_backward_euler(shape, modes, cfl):
+def test_linear_acoustics_theta_step(shape, modes, cfl, theta):
+    """A standing wave at rest is the sum of the two modes exp(+-i w t); one theta-step maps
+    each by g = (1 + i(1-theta) w dt)/(1 - i theta w dt), so the pressure amplitude scales by
+    Re g = (1 - theta(1-theta) w^2 dt^2)/(1 + theta^2 w^2 dt^2): 1/(1 + w^2 dt^2) for
+    backward Euler, (1 - w^2 dt^2/4)/(1 + w^2 dt^2/4) for Crank-Nicolson."""
     nd = len(shape)
     gamma, p0, rho0, A = 1.4, 1.0, 1.0, 1e-6
     L = 1.0
@@ -50,7 +56,7 @@ def test_linear_acoustics_backward_euler(shape, modes, cfl):
     X = np.zeros((2 + nd,) + gs)
     X[0] = rho
     X[1] = p / ((gamma - 1) * rho)
-    pd = W.make_problem(shape, (h,) * nd, ("periodic",) * nd, gamma)
+    pd = W.make_problem(shape, (h,) * nd, ("periodic",) * nd, gamma, theta=theta)
     P = Problem.from_dict(pd)
     c = np.sqrt(gamma * p0 / rho0)
     dt = cfl * h / c
@@ -59,8 +65,8 @@ def test_linear_acoustics_backward_euler(shape, modes, cfl):
     basis = np.cos(phase)
     ratio = np.sum(pn1 * basis) / np.sum((p - p0) * basis)
     w2 = c ** 2 * sum((2 / h) ** 2 * np.sin(k[d] * h / 2) ** 2 for d in range(nd))
-    expect = 1 / (1 + w2 * dt ** 2)
-    assert abs(ratio - expect) <= 1e-5 * max(expect, 1e-3), (ratio, expect)
+    expect = (1 - theta * (1 - theta) * w2 * dt ** 2) / (1 + theta ** 2 * w2 * dt ** 2)
+    assert abs(ratio - expect) <= 1e-5 * max(abs(expect), 1e-3), (ratio, expect)
 
 
 def test_hydrostatic_equilibrium_survives_step():
@@ -99,6 +105,37 @@ def test_jfnk_reaches_exact_root_bump(jv, elliptic):
     assert max(st.gmres_its) <= 20
 
 
+@pytest.mark.parametrize("precond", ["sound", "sound_thermal"])
+def test_jfnk_crank_nicolson(precond):
+    """theta = 1/2: the preconditioner built with tau = dt/2 and scaled by 2 keeps GMRES as
+    short as for backward Euler, and the step reaches the exact root."""
+    w = W.polytrope((16, 16), 10.0, mach=1e-3, seed=5, chi_model="power", steps=1, cfl=50.0)
+    pd = dict(w["problem"])
+    pd["theta"] = 0.5
+    P = Problem.from_dict(pd)
+    X0 = w["X0"]
+    dt = cfl_dt(P, X0, 50.0)
+    Xs, _ = exact_step(P, X0, dt)
+    st = Stats()
+    X = jfnk_step(P, X0, dt, Opts(precond=precond, elliptic="direct"), st)
+    _, R = scaling_LR(P, Xs)
+    assert st.converged
+    assert np.max(np.abs((X - Xs) / R)) <= 1e-9
+    # the same step without the theta weighting of the preconditioner needs more iterations
+    import oracle.pbp as pbp_mod
+    st1 = Stats()
+    orig = pbp_mod.PBP.__init__
+    def unweighted(self, prob, X, dt, mode="sound", solver_factory=None):
+        import dataclasses
+        orig(self, dataclasses.replace(prob, theta=1.0), X, dt, mode, solver_factory)
+    pbp_mod.PBP.__init__ = unweighted
+    try:
+        jfnk_step(P, X0, dt, Opts(precond=precond, elliptic="direct"), st1)
+    finally:
+        pbp_mod.PBP.__init__ = orig
+    assert sum(st.gmres_its) < sum(st1.gmres_its)
+
+
 def test_jfnk_stratified_thermal():
     w = W.polytrope((16, 16), 10.0, mach=1e-3, seed=5, chi_model="power", steps=1, cfl=50.0)
     P = Problem.from_dict(w["problem"])
@@ -126,9 +163,10 @@ def test_unpreconditioned_needs_more_iterations():
 # ---------------------------------------------------------------------------------------
 # adjoint
 # ---------------------------------------------------------------------------------------
-def _adj_case(seed=1):
+def _adj_case(seed=1, theta=1.0):
     pd, X = W.random_state((6, 8), ("periodic", "wall"), seed=seed, g=(0.0, -1.0),
                            chi_model="power", chi0=0.05, qwall=((0, 0), (0.1, 0.05)), umag=0.05)
+    pd["theta"] = theta
     return Problem.from_dict(pd), X
 
 
@@ -152,8 +190,9 @@ def test_dU_dX_transpose():
     assert abs(np.sum(lam * dU) - np.sum(dU_dX_T(P, X, lam) * v)) <= 1e-13 * np.abs(lam * dU).sum()
 
 
-def test_adjoint_step_matches_finite_differences():
-    P, X = _adj_case(seed=2)
+@pytest.mark.parametrize("theta", [1.0, 0.5])
+def test_adjoint_step_matches_finite_differences(theta):
+    P, X = _adj_case(seed=2, theta=theta)
     dt = 0.02
     Xn1, _ = exact_step(P, X, dt)
     # loss: kinetic energy sum rho_f u^2 / 2 on faces
@@ -181,9 +220,10 @@ def test_adjoint_step_matches_finite_differences():
         assert abs(fd - an) <= 1e-6 * abs(an), (fd, an)
 
 
+@pytest.mark.parametrize("theta", [1.0, 0.5])
 @pytest.mark.parametrize("precond", ["sound", "sound_thermal"])
-def test_adjoint_fgmres_matches_lu(precond):
-    P, X = _adj_case(seed=3)
+def test_adjoint_fgmres_matches_lu(precond, theta):
+    P, X = _adj_case(seed=3, theta=theta)
     dt = 0.05
     Xn1, _ = exact_step(P, X, dt)
     gbar = W.random_vector(X, 8)

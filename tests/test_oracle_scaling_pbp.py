@@ -5,6 +5,8 @@ identities of App. B; symmetry, positivity and Fourier eigenvalues of the ellipt
 the identity-based energy update equals the explicit-Laplacian semi-implicit equations
 (Sect. 3.3 and 3.4); the transposed preconditioner passes the dot-product test.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -121,17 +123,21 @@ def _div_chi(P, X, phi):
     return -(op.apply(phi) - op.diag * phi)
 
 
+@pytest.mark.parametrize("theta", [1.0, 0.5])
 @pytest.mark.parametrize("mode", ["sound", "sound_thermal"])
 @pytest.mark.parametrize("shape,bc", [((8, 6), ("periodic", "wall")), ((4, 4, 6), ("periodic", "periodic", "wall"))])
-def test_pbp_solves_semi_implicit_equations(mode, shape, bc):
+def test_pbp_solves_semi_implicit_equations(mode, shape, bc, theta):
     """With direct elliptic solves, z = M^-1 r satisfies the semi-implicit equations in the
     explicit-Laplacian form (eqs. SI3_p..SI3_u; SI4_p_final..SI4_u_final with the conduction
-    coupling of the pressure row lagged), the linearised EOS, and du = dt r_m/rho_f on walls."""
+    coupling of the pressure row lagged), the linearised EOS, and du = dt r_m/rho_f on walls.
+    For a theta-step (J = dU/dX/dt - theta dR/dX) theta z satisfies them with the implicit
+    time step theta dt."""
     P, X = _state(shape, bc, seed=3)
-    dt = 0.2
+    P = dataclasses.replace(P, theta=theta)
     r = W.random_vector(X, 5)
-    pbp = PBP(P, X, dt, mode)
-    z = pbp.apply(r)
+    pbp = PBP(P, X, 0.2, mode)
+    z = theta * pbp.apply(r)
+    dt = theta * 0.2
     g = P.gamma
     rho, e = X[0], X[1]
     p = (g - 1) * rho * e
@@ -159,9 +165,11 @@ def test_pbp_solves_semi_implicit_equations(mode, shape, bc):
             assert np.allclose(z[2 + d][sl], dt * r[2 + d][sl] / rf[sl])
 
 
+@pytest.mark.parametrize("theta", [1.0, 0.5])
 @pytest.mark.parametrize("mode", ["sound", "sound_thermal"])
-def test_pbp_transpose_dot_product(mode):
+def test_pbp_transpose_dot_product(mode, theta):
     P, X = _state((8, 6), ("periodic", "wall"), seed=4)
+    P = dataclasses.replace(P, theta=theta)
     pbp = PBP(P, X, 0.15, mode)
     r = W.random_vector(X, 6)
     w = W.random_vector(X, 7)
