@@ -1,0 +1,127 @@
+"""Iteration-count studies of the paper's test problems, run with this library.
+
+    python -m paper_1512_03662_amd.studies tgv [--steps 10]
+    python -m paper_1512_03662_amd.studies vortex [--steps 5]
+
+tgv:    the 3D Taylor-Green vortex at 64^3 for the Mach numbers and hydrodynamic CFL numbers
+        of the paper's timing table (Results section, Taylor-Green vortex): average Newton
+        iterations per time step, GMRES iterations per Newton iteration and elliptic (CG)
+        iterations per GMRES iteration, with the paper's figures beside them.
+vortex: the 2D isentropic vortex at 64^2 (T_inf = 1, 1e2, 1e6, 1e10, i.e. Mach 1e-1 .. 1e-6)
+        over a range of advective CFL numbers, with and without the physics-based
+        preconditioner: GMRES iterations per Newton iteration (the paper shows these as a
+        figure; no numbers are printed there, so only the trend can be compared).
+
+The paper's runs used its own code (MUSIC with Trilinos), Newton tolerance 1e-6 and an
+algebraic-multigrid preconditioned parabolic solver; here Newton tolerance 1e-8, FGMRES(30)
+with CGS2, eta = 1e-4, and geometric multigrid CG to 1e-4.  Prints one JSON line per case.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Mach number, CFL_hydro, CFL_adv, Newton/dt, GMRES/Newton, parabolic/GMRES (paper's table)
+TGV_TABLE = [
+    (1e-1, 7.1e0, 0.5, 3.8, 16.6, 2.4),
+    (1e-2, 7.0e1, 0.5, 3.1, 15.4, 2.5),
+    (1e-3, 8.2e2, 0.5, 2.7, 16.2, 2.5),
+    (1e-4, 1.1e4, 0.5, 2.0, 16.1, 2.8),
+    (1e-5, 8.1e4, 0.5, 2.0, 22.2, 2.9),
+    (1e-6, 4.9e5, 0.49, 4.5, 291.5, 3.0),
+    (1e-6, 5.0e4, 0.05, 2.0, 7.0, 2.8),
+]
+
+
+def _run(ctx, X0, cfl, steps, torch):
+    X = X0.clone()
+    st = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    err = None
+    for _ in range(steps):
+        dt = ctx.cfl_dt(X, cfl)
+        try:
+            st.append(ctx.implicit_step(X, dt, raise_on_noconv=False))
+        except Exception as e:  # a failed solve ends the case; it is reported, not hidden
+            err = str(e)
+            break
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    steps = max(len(st), 1)
+    newton = sum(s["newton_its"] for s in st)
+    gmres = sum(s["gmres_its"] for s in st)
+    cg = sum(s["cg_its"] for s in st)
+    return {
+        "steps": steps,
+        "converged_steps": sum(s["converged"] for s in st),
+        "newton_per_step": newton / steps,
+        "gmres_per_newton": gmres / max(newton, 1),
+        "cg_per_gmres": cg / max(gmres, 1),
+        "ms_per_step": 1e3 * sec / steps,
+        "error": err,
+    }
+
+
+def tgv(args):
+    import torch
+
+    import workloads as W
+    import paper_1512_03662_amd as J
+    dev = torch.device("cuda:0")
+    for mach, cfl, cfl_adv, pn, pg, pp in TGV_TABLE:
+        w = W.taylor_green_3d(n=64, mach=mach, noise=0.0)
+        X0 = torch.tensor(w["X0"], dtype=torch.float64, device=dev)
+        ctx = J.Context(w["problem"], precond="sound", jv_mode="fd")
+        r = _run(ctx, X0, cfl, args.steps, torch)
+        ctx.close()
+        r.update({"study": "taylor_green_3d_64^3", "mach": mach, "cfl_hydro": cfl,
+                  "paper": {"cfl_adv": cfl_adv, "newton_per_step": pn, "gmres_per_newton": pg,
+                            "parabolic_per_gmres": pp}})
+        print(json.dumps(r), flush=True)
+
+
+def vortex(args):
+    import torch
+
+    import workloads as W
+    import paper_1512_03662_amd as J
+    dev = torch.device("cuda:0")
+    for t_inf in (1.0, 1e2, 1e6, 1e10):
+        w = W.isentropic_vortex_2d(n=64, t_inf=t_inf)
+        pd = w["problem"]
+        mach = 0.75 / (2 * math.pi * math.sqrt(1.4 * t_inf))
+        h = pd["dx"][0]
+        c_inf = math.sqrt(1.4 * t_inf)
+        X0 = torch.tensor(w["X0"], dtype=torch.float64, device=dev)
+        for cfl_adv in (0.01, 0.05, 0.2, 0.5):
+            # CFL_hydro from the advective CFL: dt = cfl_adv dx / u_inf
+            cfl = cfl_adv * (1.0 + c_inf + 0.75 / (2 * math.pi))
+            for prec in ("sound", "none"):
+                ctx = J.Context(pd, precond=prec, jv_mode="fd", gmres_maxit=300,
+                                alpha1=1.0 if prec == "none" else 1e-5)
+                r = _run(ctx, X0, cfl, args.steps, torch)
+                ctx.close()
+                r.update({"study": "isentropic_vortex_2d_64^2", "mach": mach, "t_inf": t_inf,
+                          "cfl_adv": cfl_adv, "cfl_hydro": cfl, "precond": prec, "dx": h})
+                print(json.dumps(r), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("study", choices=["tgv", "vortex"])
+    ap.add_argument("--steps", type=int, default=10)
+    args = ap.parse_args()
+    {"tgv": tgv, "vortex": vortex}[args.study](args)
+
+
+if __name__ == "__main__":
+    main()
