@@ -81,6 +81,11 @@ typedef struct {
   int32_t ell_precision; /* JFNK_FP64 | JFNK_FP32 elliptic solves                       */
   double cg_eta;         /* parabolic-solve tolerance eta' (eq. forcing_term2)          */
   int32_t cg_maxit;      /* maximum CG iterations per elliptic solve                    */
+  int32_t pc_schur;      /* 0: the paper's J~_V, which drops the velocity residual from  *
+                          * the pressure equation (Sect. 3.3, delta form); 1: eliminate   *
+                          * du exactly, keeping -dt div F~_u in the pressure right-hand  *
+                          * side (exact inverse of J at a uniform state at rest without  *
+                          * gravity or conduction)                                        */
 } jfnk_opts;
 
 typedef struct {

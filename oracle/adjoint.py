@@ -84,7 +84,7 @@ def adjoint_step_exact(prob: Problem, Xn1, Xn, dt, gbar):
 
 def adjoint_step_fgmres(prob: Problem, Xn1, Xn, dt, gbar, precond="sound", eta=1e-10,
                         m=30, maxit=300, alpha1=1e-5, alpha2=1.0, elliptic="direct",
-                        cg_eta=1e-4, info_out=None):
+                        cg_eta=1e-4, info_out=None, schur=False):
     b = rhs_b(prob, Xn, dt)
     J = jacobian_sparse(prob, Xn1, b, dt)
     L, R = scaling_LR(prob, Xn1, alpha1, alpha2)
@@ -93,7 +93,7 @@ def adjoint_step_fgmres(prob: Problem, Xn1, Xn, dt, gbar, precond="sound", eta=1
         apply_prec = lambda v: v / L
     else:
         fac = None if elliptic == "direct" else PCGSolver.factory(cg_eta)
-        pbp = PBP(prob, Xn1, dt, precond, solver_factory=fac)
+        pbp = PBP(prob, Xn1, dt, precond, solver_factory=fac, schur=schur)
         apply_prec = lambda v: pbp.apply_T(v / R)
     lam, info = fgmres(apply_op, apply_prec, R * gbar, eta, m, maxit)
     if info_out is not None:

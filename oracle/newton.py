@@ -48,6 +48,7 @@ class Opts:
     alpha1: float = 1e-5
     alpha2: float = 1.0
     precond: str = "sound"       # 'none' | 'sound' | 'sound_thermal'
+    pc_schur: bool = False       # keep div F_u in the pressure equation (Schur complement)
     elliptic: str = "pcg"        # 'pcg' | 'direct'
     ell_dtype: object = np.float64
     cg_eta: float = 1e-4
@@ -111,7 +112,7 @@ def jfnk_step(prob: Problem, Xn, dt, opts: Opts = None, stats: Stats = None):
             solvers = []
         else:
             if opts.elliptic == "direct":
-                pbp = PBP(prob, X, dt, opts.precond)
+                pbp = PBP(prob, X, dt, opts.precond, schur=opts.pc_schur)
                 solvers = []
             else:
                 fac_list = []
@@ -120,7 +121,7 @@ def jfnk_step(prob: Problem, Xn, dt, opts: Opts = None, stats: Stats = None):
                     s = PCGSolver(op, opts.cg_eta, opts.cg_maxit, opts.ell_dtype)
                     fac_list.append(s)
                     return s
-                pbp = PBP(prob, X, dt, opts.precond, solver_factory=fac)
+                pbp = PBP(prob, X, dt, opts.precond, solver_factory=fac, schur=opts.pc_schur)
                 solvers = fac_list
             apply_prec = lambda v, L=L, pbp=pbp: pbp.apply(L * v)
 

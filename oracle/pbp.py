@@ -212,6 +212,27 @@ def grad_face_T(prob: Problem, X, a, d):
     return c - up
 
 
+def div_face(prob: Problem, F, d):
+    """(F[c + e_d] - F[c]) / dx_d of values F on the low-d faces; wall faces (the low face of
+    the first cell and the high face of the last) carry zero."""
+    Fz = F
+    if prob.bc[d] == WALL:
+        Fz = F.copy()
+        Fz[_wall_slice(prob, d, 0)] = 0.0
+    up = _roll(Fz, prob, d, 1)
+    if prob.bc[d] == WALL:
+        up[_wall_slice(prob, d, -1)] = 0.0
+    return (up - Fz) / prob.dx[d]
+
+
+def div_face_T(prob: Problem, s, d):
+    """Transpose of div_face: face f receives (s[f - e_d] - s[f]) / dx_d, zero on wall faces."""
+    out = (_roll(s, prob, d, -1) - s) / prob.dx[d]
+    if prob.bc[d] == WALL:
+        out[_wall_slice(prob, d, 0)] = 0.0
+    return out
+
+
 class DirectSolver:
     def __init__(self, op: EllOp):
         self.op = op
@@ -227,11 +248,14 @@ class PBP:
     ``solver_factory(op)`` returns a callable b -> A^-1 b; default: direct sparse LU.
     """
 
-    def __init__(self, prob: Problem, X, dt, mode="sound", solver_factory=None):
+    def __init__(self, prob: Problem, X, dt, mode="sound", solver_factory=None, schur=False):
         # theta-weighted step (eq. crank_nicholson): J = dU/dX / dt - theta dR/dX
         # = theta (dU/dX / tau - dR/dX) with tau = theta dt, so the scheme is built with the
         # implicit time step tau and its result divided by theta (theta = 1: tau = dt).
-        self.prob, self.X, self.mode = prob, X, mode
+        # schur: keep the velocity residual in the pressure equation (eliminate du exactly
+        # instead of dropping F_u there): rhs_p = F_p/(Gamma1 p) - tau div F_u.  The energy
+        # update goes through the pressure equation's identity, where the term cancels.
+        self.prob, self.X, self.mode, self.schur = prob, X, mode, schur
         self.dt = prob.theta * dt
         self.zscale = 1.0 / prob.theta
         dt = self.dt
@@ -251,7 +275,11 @@ class PBP:
         p = (g - 1.0) * rho * e
         dpdr, dpde = eos_derivs(prob, X)
         Fp, Fe, Fu = transform_in(prob, X, r)
-        dp = self.solve_p(Fp / (g * p))
+        rhs_p = Fp / (g * p)
+        if self.schur:
+            for d in range(prob.nd):
+                rhs_p = rhs_p - dt * div_face(prob, Fu[d], d)
+        dp = self.solve_p(rhs_p)
         if self.mode == "sound":
             de = dt * Fe + (dp - dt * Fp) / (g * rho)
         else:
@@ -291,4 +319,7 @@ class PBP:
             Fp_b = -t / g
         s = self.solve_p(dp_b)
         Fp_b = Fp_b + s / (g * p)
+        if self.schur:
+            for d in range(prob.nd):
+                Fu_b[d] = Fu_b[d] - dt * div_face_T(prob, s, d)
         return transform_in_T(prob, X, Fp_b, Fe_b, Fu_b) * self.zscale

@@ -60,6 +60,7 @@ class Opts(C.Structure):
         ("ell_precision", C.c_int32),
         ("cg_eta", C.c_double),
         ("cg_maxit", C.c_int32),
+        ("pc_schur", C.c_int32),
     ]
 
 

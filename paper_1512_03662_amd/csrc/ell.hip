@@ -1070,9 +1070,28 @@ __device__ __forceinline__ void r_cell(const Grid& G, const double* X, const dou
   *rE = vE;
 }
 
+// F~_u on the low-d face of cell lf (lower cell lm): (r_m - u_d rbar_rho)/rho_f, r = L v when
+// scaled
+__device__ __forceinline__ double fu_face(const Grid& G, const double* X, const double* v, int scaled,
+                                          double alpha1, int d, int lf, int lm) {
+  const double k = G.gamma * (G.gamma - 1.0);
+  const double rho = X[lf], rhom = X[lm];
+  const double rf = 0.5 * (rhom + rho);
+  const double ud = X[(2 + d) * G.N + lf];
+  double rm = v[(2 + d) * G.N + lf], r0m = v[lm], r0c = v[lf];
+  if (scaled) {
+    const double csf = 0.5 * (sqrt(k * X[G.N + lm]) + sqrt(k * X[G.N + lf]));
+    rm *= rf * fmax(fabs(ud), alpha1 * csf);
+    r0m *= rhom;
+    r0c *= rho;
+  }
+  return (rm - ud * (0.5 * (r0m + r0c))) / rf;
+}
+
+// rhs_p = F_p/(Gamma1 p); schur: minus dt div F~_u (wall faces carry no F~_u)
 template <int ND>
 __global__ void __launch_bounds__(kBlock) k_pbp_in(Grid G, const double* X, const double* v, int scaled,
-                                                   double* rhs_p) {
+                                                   double alpha1, double dt, int schur, double* rhs_p) {
   int lin = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (lin >= G.N) return;
   const double gm1 = G.gamma - 1.0;
@@ -1081,7 +1100,28 @@ __global__ void __launch_bounds__(kBlock) k_pbp_in(Grid G, const double* X, cons
   r_cell(G, X, v, scaled, lin, &r0, &rE);
   double dpdr = gm1 * e, dpde = gm1 * rho;
   double Fp = (dpdr - (e / rho) * dpde) * r0 + (dpde / rho) * rE;
-  rhs_p[lin] = Fp / (G.gamma * gm1 * rho * e);
+  double rhs = Fp / (G.gamma * gm1 * rho * e);
+  if (schur) {
+    Pos P = make_pos<ND>(G, lin);
+    double div = 0.0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      double flo = 0.0, fhi = 0.0;
+      if (!(G.bc[d] == 1 && P.c[d] == 0)) {
+        double s;
+        const int im = gidx<ND>(G, P, 0, shift(off0(), d, -1), &s);
+        flo = fu_face(G, X, v, scaled, alpha1, d, lin, im);
+      }
+      const bool top = (P.c[d] == G.n[d] - 1);
+      if (!(G.bc[d] == 1 && top)) {
+        const int ip = top ? lin - (G.n[d] - 1) * G.stride[d] : lin + G.stride[d];
+        fhi = fu_face(G, X, v, scaled, alpha1, d, ip, lin);
+      }
+      div += (fhi - flo) * G.idx[d];
+    }
+    rhs -= dt * div;
+  }
+  rhs_p[lin] = rhs;
 }
 
 __global__ void __launch_bounds__(kBlock) k_pbp_rhsT(Grid G, const double* X, const double* v, int scaled,
@@ -1144,11 +1184,12 @@ __global__ void __launch_bounds__(kBlock) k_pbp_out(Grid G, const double* X, con
 }
 
 void launch_pbp_in(const Grid& G, const double* X, const double* v, int scaled, double alpha1,
-                   double dt, double* rhs_p, hipStream_t s) {
-  (void)alpha1;
-  (void)dt;
-  if (G.nd == 2) launch_k(KF_PBP_IN, 40.0 * G.N, k_pbp_in<2>, CELLS(G.N), 0, s, G, X, v, scaled, rhs_p);
-  else launch_k(KF_PBP_IN, 40.0 * G.N, k_pbp_in<3>, CELLS(G.N), 0, s, G, X, v, scaled, rhs_p);
+                   double dt, int schur, double* rhs_p, hipStream_t s) {
+  const double by = 8.0 * G.N * (schur ? 2.0 * (2 + G.nd) + 1 : 5.0);
+  if (G.nd == 2)
+    launch_k(KF_PBP_IN, by, k_pbp_in<2>, CELLS(G.N), 0, s, G, X, v, scaled, alpha1, dt, schur, rhs_p);
+  else
+    launch_k(KF_PBP_IN, by, k_pbp_in<3>, CELLS(G.N), 0, s, G, X, v, scaled, alpha1, dt, schur, rhs_p);
 }
 void launch_pbp_rhsT(const Grid& G, const double* X, const double* v, int scaled, double alpha1,
                      double dt, const double* dp, double* rhs_T, hipStream_t s) {

@@ -187,11 +187,11 @@ void launch_cg_dot_rz(int n, const T* r, const T* z, const CGArgs& g, hipStream_
 void launch_cast_scale_f32(size_t n, const double* src, const double* nrm2, float* dst, hipStream_t s);
 void launch_uncast_scale_f64(size_t n, const float* src, const double* nrm2, double* dst, hipStream_t s);
 
-// transforms: rhs_p = F_p / (Gamma1 p);  rhs_T = rho F_e + (dp/dt - F_p)/Gamma1;
+// transforms: rhs_p = F_p / (Gamma1 p) (schur: - dt div F_u);  rhs_T = rho F_e + (dp/dt - F_p)/Gamma1;
 // z = zscale dX from dp (and dT).  scaled != 0: the input is v with r = L v.  For a
 // theta-weighted step dt is the implicit step theta dt and zscale = 1/theta.
 void launch_pbp_in(const Grid& G, const double* X, const double* v, int scaled, double alpha1,
-                   double dt, double* rhs_p, hipStream_t s);
+                   double dt, int schur, double* rhs_p, hipStream_t s);
 void launch_pbp_rhsT(const Grid& G, const double* X, const double* v, int scaled, double alpha1,
                      double dt, const double* dp, double* rhs_T, hipStream_t s);
 void launch_pbp_out(const Grid& G, const double* X, const double* v, int scaled, double alpha1,
@@ -210,6 +210,7 @@ void launch_pbpT_in(const Grid& G, const double* X, const double* v, int scaled,
                     double dt, int thermal, double* rhs_p, double* rhs_T, hipStream_t s);
 void launch_pbpT_mid(const Grid& G, double dt, const double* t, double* rhs_p, hipStream_t s);
 void launch_pbpT_out(const Grid& G, const double* X, const double* v, int scaled, double alpha2,
-                     double dt, const double* sp, const double* t, double zscale, double* z, hipStream_t s);
+                     double dt, const double* sp, const double* t, int schur, double zscale, double* z,
+                     hipStream_t s);
 
 }  // namespace jfnk

@@ -187,6 +187,7 @@ void validate(const jfnk_problem* p, const jfnk_opts* o) {
   if (o->precond < 0 || o->precond > 2) throw InvErr("bad precond");
   if (o->ell_precision != JFNK_FP64 && o->ell_precision != JFNK_FP32) throw InvErr("bad ell_precision");
   if (o->cg_maxit < 1) throw InvErr("cg_maxit must be >= 1");
+  if (o->pc_schur != 0 && o->pc_schur != 1) throw InvErr("pc_schur must be 0 or 1");
 }
 
 // ---- multigrid hierarchy ----------------------------------------------------------------
@@ -500,7 +501,7 @@ void precond(jfnk_ctx* c, const double* X, const double* v, int scaled, double* 
     return;
   }
   const double tau = si_dt(c);
-  launch_pbp_in(G, X, v, scaled, o.alpha1, tau, c->rhs_p, s);
+  launch_pbp_in(G, X, v, scaled, o.alpha1, tau, o.pc_schur, c->rhs_p, s);
   ell_solve(c, 0, c->rhs_p, c->dp);
   const double* dT = nullptr;
   if (o.precond == JFNK_PC_SOUND_THERMAL) {
@@ -532,7 +533,7 @@ void precond_T(jfnk_ctx* c, const double* X, const double* v, int scaled, double
     t = c->dT;
   }
   ell_solve(c, 0, c->rhs_p, c->dp);
-  launch_pbpT_out(G, X, v, scaled, o.alpha2, tau, c->dp, t, 1.0 / c->prob.theta, z, s);
+  launch_pbpT_out(G, X, v, scaled, o.alpha2, tau, c->dp, t, o.pc_schur, 1.0 / c->prob.theta, z, s);
   check_launch();
 }
 
@@ -880,6 +881,7 @@ void jfnk_default_opts(jfnk_opts* o) {
   o->ell_precision = JFNK_FP64;
   o->cg_eta = 1e-4;
   o->cg_maxit = 50;
+  o->pc_schur = 0;
 }
 
 int jfnk_create(const jfnk_problem* prob, const jfnk_opts* opts, void* hip_stream, jfnk_ctx** out) {

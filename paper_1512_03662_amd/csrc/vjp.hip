@@ -557,7 +557,7 @@ __global__ void __launch_bounds__(kBlock) k_pbpT_mid(Grid G, double dt, const do
 template <int ND>
 __global__ void __launch_bounds__(kBlock) k_pbpT_out(Grid G, const double* X, const double* v, int scaled,
                                                      double alpha2, double dt, const double* sp,
-                                                     const double* t, double zs, double* z) {
+                                                     const double* t, int schur, double zs, double* z) {
   int lin = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (lin >= G.N) return;
   Pos P = make_pos<ND>(G, lin);
@@ -589,6 +589,8 @@ __global__ void __launch_bounds__(kBlock) k_pbpT_out(Grid G, const double* X, co
     int im = gidx<ND>(G, P, 0, shift(off0(), d, -1), &s);
     double rf = 0.5 * (X[im] + rho);
     double Fu_b = dt * w_face<ND>(G, X, v, scaled, alpha2, d, lin);
+    // schur: the pressure right-hand side's -dt div F_u, transposed (not on wall faces)
+    if (schur && !(G.bc[d] == 1 && P.c[d] == 0)) Fu_b -= dt * (sp[im] - sp[lin]) * G.idx[d];
     z[(2 + d) * N + lin] = zs * (Fu_b / rf);
     // the F_u row of face f reads rbar = (r_rho[f-1] + r_rho[f])/2 with coefficient -u/rho_f
     double a0 = -X[(2 + d) * N + lin] * Fu_b / rf;
@@ -599,6 +601,7 @@ __global__ void __launch_bounds__(kBlock) k_pbpT_out(Grid G, const double* X, co
       int ip = top ? lin - (G.n[d] - 1) * G.stride[d] : lin + G.stride[d];
       double rfp = 0.5 * (rho + X[ip]);
       double Fu_bp = dt * w_face<ND>(G, X, v, scaled, alpha2, d, ip);
+      if (schur) Fu_bp -= dt * (sp[lin] - sp[ip]) * G.idx[d];
       r0 += 0.5 * (-X[(2 + d) * N + ip] * Fu_bp / rfp);
     }
   }
@@ -617,10 +620,11 @@ void launch_pbpT_mid(const Grid& G, double dt, const double* t, double* rhs_p, h
   k_pbpT_mid<<<gr, kBlock, 0, s>>>(G, dt, t, rhs_p);
 }
 void launch_pbpT_out(const Grid& G, const double* X, const double* v, int scaled, double alpha2,
-                     double dt, const double* sp, const double* t, double zscale, double* z, hipStream_t s) {
+                     double dt, const double* sp, const double* t, int schur, double zscale, double* z,
+                     hipStream_t s) {
   dim3 gr((G.N + kBlock - 1) / kBlock);
-  if (G.nd == 2) k_pbpT_out<2><<<gr, kBlock, 0, s>>>(G, X, v, scaled, alpha2, dt, sp, t, zscale, z);
-  else k_pbpT_out<3><<<gr, kBlock, 0, s>>>(G, X, v, scaled, alpha2, dt, sp, t, zscale, z);
+  if (G.nd == 2) k_pbpT_out<2><<<gr, kBlock, 0, s>>>(G, X, v, scaled, alpha2, dt, sp, t, schur, zscale, z);
+  else k_pbpT_out<3><<<gr, kBlock, 0, s>>>(G, X, v, scaled, alpha2, dt, sp, t, schur, zscale, z);
 }
 
 size_t vjp_scratch_doubles(const Grid& G) {

@@ -107,6 +107,23 @@ ADJ_CASES = [
 ]
 
 
+def test_adjoint_step_parity_schur():
+    """The transposed Schur-variant preconditioner leaves the adjoint unchanged."""
+    J = _lib()
+    w_ = W.polytrope((16, 24), 10.0, mach=1e-3, seed=5, chi_model="power", steps=1, cfl=50.0)
+    pd, X0 = w_["problem"], w_["X0"]
+    P = Problem.from_dict(pd)
+    dt = cfl_dt(P, X0, 10.0)
+    Xs, _ = exact_step(P, X0, dt)
+    gbar = W.random_vector(X0, 32)
+    ref, _ = adjoint_step_exact(P, Xs, X0, dt, gbar)
+    ctx = J.Context(pd, precond="sound_thermal", pc_schur=1, gmres_eta=1e-12, cg_eta=1e-6)
+    got, st = ctx.adjoint_step(T(Xs), T(X0), dt, T(gbar))
+    got = H(got)
+    assert st["converged"] == 1
+    assert np.max(np.abs(got - ref)) <= 1e-8 * np.max(np.abs(ref)), (np.max(np.abs(got - ref)), st)
+
+
 @pytest.mark.parametrize("name,mk,prec", ADJ_CASES, ids=[c[0] for c in ADJ_CASES])
 def test_adjoint_step_parity(name, mk, prec):
     J = _lib()

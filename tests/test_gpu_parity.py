@@ -232,6 +232,49 @@ def test_precond_parity_crank_nicolson(mode):
         assert np.max(np.abs(got[k] - ref[k])) <= 1e-10 * np.max(np.abs(ref[k])), k
 
 
+@pytest.mark.parametrize("mode", ["sound", "sound_thermal"])
+def test_precond_parity_schur(mode):
+    J = _lib()
+    pd, X = W.random_state((32, 16), ("periodic", "wall"), seed=18, g=(0.0, -1.0), chi_model="power",
+                           chi0=0.02, amp=0.2)
+    P = Problem.from_dict(pd)
+    dt = 0.05
+    r = W.random_vector(X, 19)
+    ref = PBP(P, X, dt, mode, schur=True).apply(r)
+    ctx = J.Context(pd, precond=mode, pc_schur=1, cg_eta=1e-13, cg_maxit=200)
+    ctx.set_state_n(T(X), dt)
+    got = H(ctx.precond_apply(T(X), T(r)))
+    for k in range(P.nvar):
+        assert np.max(np.abs(got[k] - ref[k])) <= 1e-10 * np.max(np.abs(ref[k])), k
+
+
+def test_schur_step_one_gmres_iteration_near_rest():
+    """A small sound wave on a uniform state at rest: with the Schur variant and tight inner
+    solves the preconditioner is J^-1 up to O(amplitude), so every Newton iteration needs one
+    GMRES iteration; the paper's J~_V needs more."""
+    J = _lib()
+    n = 32
+    h = 1.0 / n
+    pd = W.make_problem((n, n), (h, h), ("periodic", "periodic"), 1.4)
+    xc = (np.arange(n) + 0.5) * h
+    Y, Xg = np.meshgrid(xc, xc, indexing="ij")
+    p = 1.0 + 1e-8 * np.cos(2 * np.pi * Xg) * np.cos(4 * np.pi * Y)
+    X0 = np.zeros((4, n, n))
+    X0[0] = p ** (1 / 1.4)
+    X0[1] = p / (0.4 * X0[0])
+    its = {}
+    for schur in (1, 0):
+        ctx = J.Context(pd, precond="sound", pc_schur=schur, cg_eta=1e-12, cg_maxit=200, jv_mode="exact")
+        Xg_ = T(X0)
+        dt = ctx.cfl_dt(Xg_, 100.0)
+        st = ctx.implicit_step(Xg_, dt)
+        assert st["converged"] == 1
+        its[schur] = (st["gmres_its"], st["newton_its"])
+        ctx.close()
+    assert its[1][0] == its[1][1], its
+    assert its[0][0] > its[0][1], its
+
+
 def test_implicit_step_unpreconditioned_small_cfl():
     w = W.acoustic_bump_2d(n=16)
     err, st = _step_parity(w["problem"], w["X0"], 1.0, precond="none", alpha1=1.0)

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle.residual import Problem
+from oracle.residual import Problem, rhs_b
 from oracle.scaling import scaling_LR
 from oracle.pbp import (PBP, EllOp, pressure_operator, thermal_operator, transform_in,
                         grad_face, face_mean, eos_derivs)
@@ -171,6 +171,53 @@ def test_pbp_transpose_dot_product(mode, theta):
     P, X = _state((8, 6), ("periodic", "wall"), seed=4)
     P = dataclasses.replace(P, theta=theta)
     pbp = PBP(P, X, 0.15, mode)
+    r = W.random_vector(X, 6)
+    w = W.random_vector(X, 7)
+    a = np.sum(w * pbp.apply(r))
+    b = np.sum(pbp.apply_T(w) * r)
+    assert abs(a - b) <= 1e-12 * (abs(a) + abs(b))
+
+
+def _rest_state(shape, bc, seed):
+    """Uniform rho, e at rest, no gravity, no conduction (a linearisation state where the
+    eliminated system is exact)."""
+    nd = len(shape)
+    pd = W.make_problem(shape, tuple(1.0 / n for n in shape), bc, 1.4)
+    rng = np.random.default_rng(seed)
+    X = np.zeros((2 + nd,) + W.grid_shape(shape))
+    X[0] = 1.0 + rng.uniform(0.5, 1.5)
+    X[1] = 2.0 + rng.uniform(0.0, 1.0)
+    return Problem.from_dict(pd), X
+
+
+@pytest.mark.parametrize("theta", [1.0, 0.5])
+@pytest.mark.parametrize("shape,bc", [((6, 5), ("periodic", "periodic")), ((5, 6), ("periodic", "wall")),
+                                      ((4, 3, 4), ("periodic", "wall", "periodic"))])
+def test_schur_pbp_is_exact_inverse_at_rest(shape, bc, theta):
+    """At a uniform state at rest without gravity or conduction, eliminating du exactly makes
+    the physics-based preconditioner the exact inverse of J (dense, complex step); the paper's
+    J~_V, which drops F_u from the pressure equation, is not."""
+    from oracle.jacobian import jacobian_dense_cs
+    P, X = _rest_state(shape, bc, seed=11)
+    P = dataclasses.replace(P, theta=theta)
+    dt = 0.3
+    b = rhs_b(P, X, dt)
+    Jd = jacobian_dense_cs(P, X, b, dt)
+    r = W.random_vector(X, 12, bc=P.bc)
+    for schur, exact in ((True, True), (False, False)):
+        z = PBP(P, X, dt, "sound", schur=schur).apply(r)
+        back = (Jd @ z.ravel()).reshape(r.shape)
+        err = np.max(np.abs(back - r)) / np.max(np.abs(r))
+        if exact:
+            assert err <= 1e-11, err
+        else:
+            assert err > 1e-3, err
+
+
+@pytest.mark.parametrize("mode", ["sound", "sound_thermal"])
+def test_schur_pbp_transpose_dot_product(mode):
+    P, X = _state((8, 6), ("periodic", "wall"), seed=4)
+    pbp = PBP(P, X, 0.15, mode, schur=True)
     r = W.random_vector(X, 6)
     w = W.random_vector(X, 7)
     a = np.sum(w * pbp.apply(r))
