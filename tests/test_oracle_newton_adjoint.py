@@ -125,9 +125,9 @@ def test_jfnk_crank_nicolson(precond):
     import oracle.pbp as pbp_mod
     st1 = Stats()
     orig = pbp_mod.PBP.__init__
-    def unweighted(self, prob, X, dt, mode="sound", solver_factory=None):
+    def unweighted(self, prob, X, dt, mode="sound", solver_factory=None, **kw):
         import dataclasses
-        orig(self, dataclasses.replace(prob, theta=1.0), X, dt, mode, solver_factory)
+        orig(self, dataclasses.replace(prob, theta=1.0), X, dt, mode, solver_factory, **kw)
     pbp_mod.PBP.__init__ = unweighted
     try:
         jfnk_step(P, X0, dt, Opts(precond=precond, elliptic="direct"), st1)
