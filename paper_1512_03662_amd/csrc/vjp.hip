@@ -6,6 +6,7 @@
 // taken with respect to a ghost-padded copy of X (3 ghost layers per side, ghost values
 // treated as independent inputs), then folded back through the ghost rules (wrap, even
 // mirror, odd mirror with zero on wall faces):
+//   stage 0: the mass flux f_d on every padded face (stored, read by the next two stages);
 //   stage A: adjoint of the mass flux f_d on every padded face, from w (R_rho, the energy
 //            flux g = f e*, the momentum fluxes through their carrying mass flux);
 //   stage B: adjoint of every padded input (rho, e, u_d) gathered from the local terms that
@@ -35,41 +36,33 @@ static PadGrid make_pad(const Grid& G) {
   return p;
 }
 
-// derivative of the upwind van Leer value w.r.t. its four arguments (qm2, qm1, q0, qp1)
+// derivative of the upwind van Leer value w.r.t. its four arguments (qm2, qm1, q0, qp1),
+// branch frozen at the value; evaluated without branches with one refined reciprocal (as
+// the forward's vl).  Left (w >= 0): value qm1 + v/2 with a = qm1 - qm2, b = q0 - qm1;
+// right: q0 - v/2 with a = q0 - qm1, b = qp1 - q0; v = 2ab/(a+b) when ab > 0, else 0, and
+// dv/da = 2b^2/(a+b)^2, dv/db = 2a^2/(a+b)^2.
 __device__ __forceinline__ double upwind_grad(double qm2, double qm1, double q0, double qp1, double w,
                                               double* g) {
-  if (w >= 0.0) {
-    double a = qm1 - qm2, b = q0 - qm1;
-    double v = 0.0, da = 0.0, db = 0.0;
-    if (a * b > 0.0) {
-      double s = a + b;
-      v = 2.0 * a * b / s;
-      da = 2.0 * b * b / (s * s);
-      db = 2.0 * a * a / (s * s);
-    }
-    g[0] = -0.5 * da;
-    g[1] = 1.0 + 0.5 * (da - db);
-    g[2] = 0.5 * db;
-    g[3] = 0.0;
-    return qm1 + 0.5 * v;
-  }
-  double a = q0 - qm1, b = qp1 - q0;
-  double v = 0.0, da = 0.0, db = 0.0;
-  if (a * b > 0.0) {
-    double s = a + b;
-    v = 2.0 * a * b / s;
-    da = 2.0 * b * b / (s * s);
-    db = 2.0 * a * a / (s * s);
-  }
-  g[0] = 0.0;
-  g[1] = 0.5 * da;
-  g[2] = 1.0 - 0.5 * (da - db);
-  g[3] = -0.5 * db;
-  return q0 - 0.5 * v;
+  const bool left = (w >= 0.0);
+  const double d0 = q0 - qm1;
+  const double a = left ? (qm1 - qm2) : d0;
+  const double b = left ? d0 : (qp1 - q0);
+  const double r = rcp_nr(a + b);
+  const bool on = a * b > 0.0;
+  const double v = on ? 2.0 * a * b * r : 0.0;
+  const double r2 = r * r;
+  const double da = on ? 2.0 * b * b * r2 : 0.0;
+  const double db = on ? 2.0 * a * a * r2 : 0.0;
+  g[0] = left ? -0.5 * da : 0.0;
+  g[1] = left ? 1.0 + 0.5 * (da - db) : 0.5 * da;
+  g[2] = left ? 0.5 * db : 1.0 - 0.5 * (da - db);
+  g[3] = left ? 0.0 : -0.5 * db;
+  return left ? qm1 + 0.5 * v : q0 - 0.5 * v;
 }
 
-// Accesses at logical (possibly ghost) positions; same ghost rules as the forward.
-template <int ND>
+// Accesses at logical (possibly ghost) positions; same ghost rules as the forward.  IN:
+// every position accessed lies inside the grid, away from wall faces (no ghost rules).
+template <int ND, bool IN = false>
 struct Acc {
   const Grid& G;
   const double* X;
@@ -78,6 +71,11 @@ struct Acc {
   __device__ Acc(const Grid& g, const double* x, const double* ww, double c) : G(g), X(x), w(ww), cR(c) {}
 
   __device__ __forceinline__ double x(int var, const int* c) const {
+    if constexpr (IN) {
+      int idx = c[0] + c[1] * G.stride[1];
+      if (ND == 3) idx += c[2] * G.stride[2];
+      return X[var * G.N + idx];
+    }
     double sign = 1.0;
     int idx = 0;
 #pragma unroll
@@ -99,6 +97,11 @@ struct Acc {
   }
   // seed of row (var, c) of the R part: zero outside the grid and on wall-normal wall faces
   __device__ __forceinline__ double W(int var, const int* c) const {
+    if constexpr (IN) {
+      int i = c[0] + c[1] * G.stride[1];
+      if (ND == 3) i += c[2] * G.stride[2];
+      return cR * w[var * G.N + i];
+    }
     int idx = 0;
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
@@ -124,8 +127,8 @@ struct Acc {
   dst[d] += (k)
 
 // mass flux f_d at the low-d face of logical cell c
-template <int ND>
-__device__ __forceinline__ double mflux(const Acc<ND>& A, int d, const int* c) {
+template <int ND, class AC>
+__device__ __forceinline__ double mflux(const AC& A, int d, const int* c) {
   SH(m2, c, d, -2);
   SH(m1, c, d, -1);
   SH(p1, c, d, 1);
@@ -133,10 +136,61 @@ __device__ __forceinline__ double mflux(const Acc<ND>& A, int d, const int* c) {
   return w * upwind(A.rho(m2), A.rho(m1), A.rho(c), A.rho(p1), w);
 }
 
-// ---- stage A: adjoint of f_d on padded faces ---------------------------------------------
+// Stages A and B walk the padded grid in tiles of kBlock cells (32 x 8 in 2D, 32 x 4 x 2 in
+// 3D, so that loads stay coalesced along x); a tile whose terms reach (at most 5 cells from
+// its cells) stays inside the grid, away from its walls, runs without ghost rules.
 template <int ND>
-__global__ void __launch_bounds__(kBlock) k_vjp_stageA(Grid G, PadGrid PG, const double* X, const double* w,
-                                                       double cR, double* fbar) {
+__host__ __device__ constexpr int vt(int d) {
+  return ND == 2 ? (d == 0 ? 32 : (d == 1 ? 8 : 1)) : (d == 0 ? 32 : (d == 1 ? 4 : 2));
+}
+
+// logical cell of this thread and its padded index; false outside the padded grid
+template <int ND>
+__device__ __forceinline__ bool vtile_cell(const Grid& G, const PadGrid& PG, int* c, int* pl, bool* interior) {
+  int nb[3], o[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) nb[d] = (PG.P[d] + vt<ND>(d) - 1) / vt<ND>(d);
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  o[0] = (b % nb[0]) * vt<ND>(0);
+  o[1] = ((b / nb[0]) % nb[1]) * vt<ND>(1);
+  o[2] = (b / (nb[0] * nb[1])) * vt<ND>(2);
+  const int t = threadIdx.x;
+  const int l[3] = {t % vt<ND>(0), (t / vt<ND>(0)) % vt<ND>(1), t / (vt<ND>(0) * vt<ND>(1))};
+  bool in = true, ok = true;
+  int idx = 0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int q = o[d] + l[d];
+    ok = ok && q < PG.P[d];
+    idx += q * PG.pstride[d];
+    c[d] = (d < ND) ? q - 3 : 0;
+    if (d < ND) in = in && (o[d] - 3 >= 6) && (o[d] - 3 + vt<ND>(d) + 6 <= G.n[d]);
+  }
+  *pl = idx;
+  *interior = in;
+  return ok;
+}
+
+template <int ND>
+static int vtile_blocks(const PadGrid& PG) {
+  int b = 1;
+  for (int d = 0; d < 3; ++d) b *= (PG.P[d] + vt<ND>(d) - 1) / vt<ND>(d);
+  return b;
+}
+
+// padded index of logical cell q (coordinates clamped to the padded grid; every term that
+// reads a stored mass flux lies inside it)
+template <int ND>
+__device__ __forceinline__ int pad_index(const PadGrid& PG, const int* q) {
+  int idx = 0;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) idx += min(max(q[d] + 3, 0), PG.P[d] - 1) * PG.pstride[d];
+  return idx;
+}
+
+// ---- stage 0: mass flux f_d on every padded face (read by stages A and B) ----------------
+template <int ND>
+__global__ void __launch_bounds__(kBlock) k_vjp_flux(Grid G, PadGrid PG, const double* X, double* mf) {
   int pl = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (pl >= PG.PN) return;
   int c[3];
@@ -144,7 +198,16 @@ __global__ void __launch_bounds__(kBlock) k_vjp_stageA(Grid G, PadGrid PG, const
   int r = pl / PG.P[0];
   c[1] = (ND >= 2) ? r % PG.P[1] - 3 : 0;
   c[2] = (ND == 3) ? r / PG.P[1] - 3 : 0;
-  Acc<ND> A(G, X, w, cR);
+  Acc<ND> A(G, X, nullptr, 0.0);
+#pragma unroll
+  for (int d = 0; d < ND; ++d) mf[(size_t)d * PG.PN + pl] = mflux<ND>(A, d, c);
+}
+
+// ---- stage A: adjoint of f_d on padded faces ---------------------------------------------
+template <int ND, class AC>
+__device__ __forceinline__ void vjp_stageA_cell(const Grid& G, const PadGrid& PG, const AC& A, const int* c, int pl,
+                                                const double* mf, double* fbar) {
+  auto MF = [&](int d, const int* q) { return mf[(size_t)d * PG.PN + pad_index<ND>(PG, q)]; };
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
     const double ih = G.idx[d];
@@ -164,7 +227,7 @@ __global__ void __launch_bounds__(kBlock) k_vjp_stageA(Grid G, PadGrid PG, const
       SH(cp, cc, d, 1);
       double Pb = (A.W(2 + d, cp) - A.W(2 + d, cc)) * ih;
       if (Pb != 0.0) {
-        double m = 0.5 * (mflux<ND>(A, d, cc) + mflux<ND>(A, d, cp));
+        double m = 0.5 * (MF(d, cc) + MF(d, cp));
         SH(um1, cc, d, -1);
         SH(up2, cc, d, 2);
         double us = upwind(A.u(d, um1), A.u(d, cc), A.u(d, cp), A.u(d, up2), m);
@@ -182,7 +245,7 @@ __global__ void __launch_bounds__(kBlock) k_vjp_stageA(Grid G, PadGrid PG, const
         double Pb = (A.W(2 + e, ce) - A.W(2 + e, ced)) * ih;
         if (Pb != 0.0) {
           SH(cee, ce, e, -1);
-          double m = 0.5 * (mflux<ND>(A, d, cee) + mflux<ND>(A, d, ce));
+          double m = 0.5 * (MF(d, cee) + MF(d, ce));
           SH(d2, ce, d, -2);
           SH(dp, ce, d, 1);
           double us = upwind(A.u(e, d2), A.u(e, ced), A.u(e, ce), A.u(e, dp), m);
@@ -194,18 +257,21 @@ __global__ void __launch_bounds__(kBlock) k_vjp_stageA(Grid G, PadGrid PG, const
   }
 }
 
-// ---- stage B: adjoint of every padded input ----------------------------------------------
 template <int ND>
-__global__ void __launch_bounds__(kBlock) k_vjp_stageB(Grid G, PadGrid PG, const double* X, const double* w,
-                                                       double cR, const double* fbar, double* xbar) {
-  int pl = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-  if (pl >= PG.PN) return;
-  int c[3];
-  c[0] = pl % PG.P[0] - 3;
-  int r = pl / PG.P[0];
-  c[1] = (ND >= 2) ? r % PG.P[1] - 3 : 0;
-  c[2] = (ND == 3) ? r / PG.P[1] - 3 : 0;
-  Acc<ND> A(G, X, w, cR);
+__global__ void __launch_bounds__(kBlock) k_vjp_stageA(Grid G, PadGrid PG, const double* X, const double* w,
+                                                       double cR, const double* mf, double* fbar) {
+  int c[3], pl;
+  bool in;
+  if (!vtile_cell<ND>(G, PG, c, &pl, &in)) return;
+  if (in) vjp_stageA_cell<ND>(G, PG, Acc<ND, true>(G, X, w, cR), c, pl, mf, fbar);
+  else vjp_stageA_cell<ND>(G, PG, Acc<ND, false>(G, X, w, cR), c, pl, mf, fbar);
+}
+
+// ---- stage B: adjoint of every padded input ----------------------------------------------
+template <int ND, class AC>
+__device__ __forceinline__ void vjp_stageB_cell(const Grid& G, const PadGrid& PG, const AC& A, const int* c, int pl,
+                                                const double* mf, const double* fbar, double* xbar) {
+  auto MF = [&](int d, const int* q) { return mf[(size_t)d * PG.PN + pad_index<ND>(PG, q)]; };
   const double gm1 = G.gamma - 1.0;
   double rb = 0.0, eb = 0.0, ub[3] = {0.0, 0.0, 0.0};
   auto padded = [&](const int* q) -> int {  // padded index or -1 outside the padded grid
@@ -272,7 +338,7 @@ __global__ void __launch_bounds__(kBlock) k_vjp_stageB(Grid G, PadGrid PG, const
       SH(m2, f, d, -2);
       SH(p1, f, d, 1);
       double wv = A.u(d, f);
-      double fl = wv * upwind(A.rho(m2), A.rho(fm), A.rho(f), A.rho(p1), wv);
+      double fl = MF(d, f);
       double g[4];
       upwind_grad(A.e(m2), A.e(fm), A.e(f), A.e(p1), wv, g);
       eb += gb * fl * g[2 - k];
@@ -330,7 +396,7 @@ __global__ void __launch_bounds__(kBlock) k_vjp_stageB(Grid G, PadGrid PG, const
       SH(cp, cc, d, 1);
       double Pb = (A.W(2 + d, cp) - A.W(2 + d, cc)) * ih;
       if (Pb == 0.0) continue;
-      double m = 0.5 * (mflux<ND>(A, d, cc) + mflux<ND>(A, d, cp));
+      double m = 0.5 * (MF(d, cc) + MF(d, cp));
       SH(um1, cc, d, -1);
       SH(up2, cc, d, 2);
       double g[4];
@@ -350,7 +416,7 @@ __global__ void __launch_bounds__(kBlock) k_vjp_stageB(Grid G, PadGrid PG, const
         double Pb = (A.W(2 + d, ce) - A.W(2 + d, cem)) * ihe;
         if (Pb == 0.0) continue;
         SH(ced, ce, d, -1);
-        double m = 0.5 * (mflux<ND>(A, e, ced) + mflux<ND>(A, e, ce));
+        double m = 0.5 * (MF(e, ced) + MF(e, ce));
         SH(em2, ce, e, -2);
         SH(ep1, ce, e, 1);
         double g[4];
@@ -363,6 +429,17 @@ __global__ void __launch_bounds__(kBlock) k_vjp_stageB(Grid G, PadGrid PG, const
   xbar[(size_t)PG.PN + pl] = eb;
 #pragma unroll
   for (int d = 0; d < ND; ++d) xbar[(size_t)(2 + d) * PG.PN + pl] = ub[d];
+}
+
+template <int ND>
+__global__ void __launch_bounds__(kBlock) k_vjp_stageB(Grid G, PadGrid PG, const double* X, const double* w,
+                                                       double cR, const double* mf, const double* fbar,
+                                                       double* xbar) {
+  int c[3], pl;
+  bool in;
+  if (!vtile_cell<ND>(G, PG, c, &pl, &in)) return;
+  if (in) vjp_stageB_cell<ND>(G, PG, Acc<ND, true>(G, X, w, cR), c, pl, mf, fbar, xbar);
+  else vjp_stageB_cell<ND>(G, PG, Acc<ND, false>(G, X, w, cR), c, pl, mf, fbar, xbar);
 }
 
 // ---- fold: interior adjoint = U part + sum of padded copies ------------------------------
@@ -629,7 +706,7 @@ void launch_pbpT_out(const Grid& G, const double* X, const double* v, int scaled
 
 size_t vjp_scratch_doubles(const Grid& G) {
   PadGrid PG = make_pad(G);
-  return (size_t)PG.PN * (G.nd + 2 + G.nd);
+  return (size_t)PG.PN * (G.nd + 2 + G.nd + G.nd);
 }
 
 void launch_vjp(const Grid& G, const double* X, const double* w, double cU, double cR, double* scratch,
@@ -637,18 +714,26 @@ void launch_vjp(const Grid& G, const double* X, const double* w, double cU, doub
   PadGrid PG = make_pad(G);
   double* fbar = scratch;
   double* xbar = scratch + (size_t)G.nd * PG.PN;
+  double* mf = xbar + (size_t)(2 + G.nd) * PG.PN;
   dim3 gp((PG.PN + kBlock - 1) / kBlock), gc((G.N + kBlock - 1) / kBlock), bl(kBlock);
+  dim3 gt(G.nd == 2 ? vtile_blocks<2>(PG) : vtile_blocks<3>(PG));
   const double nv = 2 + G.nd;
   {
-    const double by = 8.0 * (2 * nv * G.N + G.nd * (double)PG.PN);
-    if (G.nd == 2) launch_k(KF_VJP_A, by, k_vjp_stageA<2>, gp, bl, 0, s, G, PG, X, w, cR, fbar);
-    else launch_k(KF_VJP_A, by, k_vjp_stageA<3>, gp, bl, 0, s, G, PG, X, w, cR, fbar);
+    const double by = 8.0 * (3.0 * G.N + G.nd * (double)PG.PN);
+    if (G.nd == 2) launch_k(KF_VJP_A, by, k_vjp_flux<2>, gp, bl, 0, s, G, PG, X, mf);
+    else launch_k(KF_VJP_A, by, k_vjp_flux<3>, gp, bl, 0, s, G, PG, X, mf);
+  }
+  const double* mfc = mf;
+  {
+    const double by = 8.0 * (2 * nv * G.N + 2 * G.nd * (double)PG.PN);
+    if (G.nd == 2) launch_k(KF_VJP_A, by, k_vjp_stageA<2>, gt, bl, 0, s, G, PG, X, w, cR, mfc, fbar);
+    else launch_k(KF_VJP_A, by, k_vjp_stageA<3>, gt, bl, 0, s, G, PG, X, w, cR, mfc, fbar);
   }
   {
-    const double by = 8.0 * (2 * nv * G.N + (G.nd + nv) * (double)PG.PN);
+    const double by = 8.0 * (2 * nv * G.N + (2 * G.nd + nv) * (double)PG.PN);
     const double* fb = fbar;
-    if (G.nd == 2) launch_k(KF_VJP_B, by, k_vjp_stageB<2>, gp, bl, 0, s, G, PG, X, w, cR, fb, xbar);
-    else launch_k(KF_VJP_B, by, k_vjp_stageB<3>, gp, bl, 0, s, G, PG, X, w, cR, fb, xbar);
+    if (G.nd == 2) launch_k(KF_VJP_B, by, k_vjp_stageB<2>, gt, bl, 0, s, G, PG, X, w, cR, mfc, fb, xbar);
+    else launch_k(KF_VJP_B, by, k_vjp_stageB<3>, gt, bl, 0, s, G, PG, X, w, cR, mfc, fb, xbar);
   }
   {
     const double by = 8.0 * (3 * nv * G.N + nv * (double)PG.PN);
