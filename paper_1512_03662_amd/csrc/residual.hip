@@ -23,6 +23,7 @@ namespace jfnk {
 
 template <class T>
 struct LoadVal {  // T(X)
+  static constexpr bool kStage = false;
   const double* X;
   int N;
   __device__ __forceinline__ T operator()(int var, int idx, double s) const {
@@ -31,6 +32,7 @@ struct LoadVal {  // T(X)
   __device__ __forceinline__ T operator()(int var, int idx) const { return T(X[var * N + idx]); }
 };
 struct LoadDual {  // dual(X, V)
+  static constexpr bool kStage = false;
   const double* X;
   const double* V;
   int N;
@@ -42,6 +44,7 @@ struct LoadDual {  // dual(X, V)
   }
 };
 struct LoadShift {  // X + delta V
+  static constexpr bool kStage = true;
   const double* X;
   const double* V;
   double delta;
@@ -368,16 +371,43 @@ __device__ __forceinline__ void tile_axis(const Grid& G, const AT& at, const Til
   __syncthreads();
 }
 
+// box of the staged density and energy: tile-local coordinates [-3, T + 1] on every active
+// axis (the reach of the face reconstructions and of the cell terms)
+template <int ND>
+__host__ __device__ constexpr int box_n(int i) {
+  return i < ND ? tile_n<ND>(i) + 5 : 1;
+}
+template <int ND>
+__host__ __device__ constexpr int box_size() {
+  return box_n<ND>(0) * box_n<ND>(1) * box_n<ND>(2);
+}
+
+// sRE: LDS for rho and e on the box (value and finite-difference forms only; nullptr: read
+// every field from memory)
 template <int ND, bool IN, class T, class LD>
 __device__ __forceinline__ bool tile_RU_in(const Grid& G, const LD& ld, const TileIdx<ND>& ti, T* R, T* U,
-                                           int* lin_out, T* sF, T* sE, T* sP) {
+                                           int* lin_out, T* sF, T* sE, T* sP, T* sRE) {
   using TT = RTile<ND>;
+  constexpr int BX = box_n<ND>(0), BY = box_n<ND>(1), BN = box_size<ND>();
+  constexpr int BZ0 = (ND == 3) ? 3 : 0;
   const int t = threadIdx.x;
-  auto at = [&](int var, const int* q) -> T {
+  auto atg = [&](int var, const int* q) -> T {
     double s;
     const int i = ti.template at<IN>(G, var, q, &s);
     if constexpr (IN) return ld(var, i);
     else return ld(var, i, s);
+  };
+  if (sRE) {
+    for (int p = t; p < 2 * BN; p += kBlock) {
+      const int var = p / BN, b = p - var * BN;
+      const int q[3] = {b % BX - 3, (b / BX) % BY - 3, b / (BX * BY) - BZ0};
+      sRE[p] = atg(var, q);
+    }
+    __syncthreads();
+  }
+  auto at = [&](int var, const int* q) -> T {
+    if (var < 2 && sRE) return sRE[var * BN + (q[0] + 3) + (q[1] + 3) * BX + (q[2] + BZ0) * BX * BY];
+    return atg(var, q);
   };
   const int l[3] = {t % TT::X, (t / TT::X) % TT::Y, t / (TT::X * TT::Y)};
   bool own = true;
@@ -419,12 +449,18 @@ __device__ __forceinline__ bool tile_RU_in(const Grid& G, const LD& ld, const Ti
 // outside the grid.  Every thread of the block must call it (it synchronises the block).
 template <int ND, class T, class LD>
 __device__ __forceinline__ bool tile_RU(const Grid& G, const LD& ld, T* R, T* U, int* lin_out) {
+  // rho and e are staged in LDS when the loader combines two arrays per value (X + delta V);
+  // for plain values the staging costs more than it saves, and staged duals would double
+  // the LDS and halve the workgroups per CU
+  constexpr bool STAGE = LD::kStage;
   __shared__ T sF[fmaxsz<ND>()];
   __shared__ T sE[smaxsz<ND>()];
   __shared__ T sP[ND * smaxsz<ND>()];
+  __shared__ T sRE[STAGE ? 2 * box_size<ND>() : 1];
+  T* re = STAGE ? sRE : nullptr;
   const TileIdx<ND> ti = tile_setup<ND>(G);
-  if (ti.interior) return tile_RU_in<ND, true>(G, ld, ti, R, U, lin_out, sF, sE, sP);
-  return tile_RU_in<ND, false>(G, ld, ti, R, U, lin_out, sF, sE, sP);
+  if (ti.interior) return tile_RU_in<ND, true>(G, ld, ti, R, U, lin_out, sF, sE, sP, re);
+  return tile_RU_in<ND, false>(G, ld, ti, R, U, lin_out, sF, sE, sP, re);
 }
 
 // ---- kernels --------------------------------------------------------------------------
