@@ -35,6 +35,7 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
+from . import eos
 from .residual import Problem, WALL
 
 
@@ -120,16 +121,14 @@ def _zero_wall_faces(prob, w):
 
 def pressure_operator(prob: Problem, X, dt):
     """A_p = diag(1/(Gamma1 p dt)) - dt div_h(rho_f^-1 grad_h)  (Sect. 3.3, row-scaled)."""
-    g = prob.gamma
-    rho, e = X[0], X[1]
-    p = (g - 1.0) * rho * e
-    diag = 1.0 / (g * p * dt)
-    w = [dt / (face_mean(prob, rho, d) * prob.dx[d] ** 2) for d in range(prob.nd)]
+    p, _, _, _, G1, _ = eos.thermo(prob, X[0], X[1])
+    diag = 1.0 / (G1 * p * dt)
+    w = [dt / (face_mean(prob, X[0], d) * prob.dx[d] ** 2) for d in range(prob.nd)]
     return EllOp(prob, diag, _zero_wall_faces(prob, w))
 
 
 def chi_cells(prob: Problem, X):
-    T = (prob.gamma - 1.0) * X[1]
+    T = eos.temperature(prob, X[0], X[1])
     if prob.chi_model == "none":
         return np.zeros_like(T)
     if prob.chi_model == "const":
@@ -138,8 +137,9 @@ def chi_cells(prob: Problem, X):
 
 
 def thermal_operator(prob: Problem, X, dt):
-    """A_T = diag(rho c_v/dt) - div_h(chi_f grad_h)  (Sect. 3.4 with dT = de/c_v)."""
-    cv = 1.0 / (prob.gamma - 1.0)
+    """A_T = diag(rho c_v/dt) - div_h(chi_f grad_h)  (Sect. 3.4 with dT = de/c_v,
+    c_v = de/dT|_rho)."""
+    cv = eos.thermo(prob, X[0], X[1])[5]
     diag = X[0] * cv / dt
     chi = chi_cells(prob, X)
     w = [face_mean(prob, chi, d) / prob.dx[d] ** 2 for d in range(prob.nd)]
@@ -147,10 +147,9 @@ def thermal_operator(prob: Problem, X, dt):
 
 
 def eos_derivs(prob: Problem, X):
-    """Ideal gas: dp/drho|_e = (gamma-1) e, dp/de|_rho = (gamma-1) rho (App. A with
-    Gamma1 = Gamma3 = gamma)."""
-    g = prob.gamma
-    return (g - 1.0) * X[1], (g - 1.0) * X[0]
+    """dp/drho|_e and dp/de|_rho (App. A; ideal gas: (gamma-1) e and (gamma-1) rho)."""
+    _, _, dpdr, dpde, _, _ = eos.thermo(prob, X[0], X[1])
+    return dpdr, dpde
 
 
 def transform_in(prob: Problem, X, r):
@@ -270,10 +269,8 @@ class PBP:
 
     def apply(self, r):
         prob, X, dt = self.prob, self.X, self.dt
-        g = prob.gamma
-        rho, e = X[0], X[1]
-        p = (g - 1.0) * rho * e
-        dpdr, dpde = eos_derivs(prob, X)
+        rho = X[0]
+        p, _, dpdr, dpde, g, cv = eos.thermo(prob, X[0], X[1])
         Fp, Fe, Fu = transform_in(prob, X, r)
         rhs_p = Fp / (g * p)
         if self.schur:
@@ -283,7 +280,6 @@ class PBP:
         if self.mode == "sound":
             de = dt * Fe + (dp - dt * Fp) / (g * rho)
         else:
-            cv = 1.0 / (g - 1.0)
             dT = self.solve_T(rho * Fe + (dp / dt - Fp) / g)
             de = cv * dT
         z = np.empty_like(r)
@@ -296,10 +292,8 @@ class PBP:
     def apply_T(self, w):
         """Transpose of ``apply`` (the elliptic solves are self-adjoint)."""
         prob, X, dt = self.prob, self.X, self.dt
-        g = prob.gamma
-        rho, e = X[0], X[1]
-        p = (g - 1.0) * rho * e
-        dpdr, dpde = eos_derivs(prob, X)
+        rho = X[0]
+        p, _, dpdr, dpde, g, cv = eos.thermo(prob, X[0], X[1])
         # z0 = (dp - dpde de)/dpdr
         dp_b = w[0] / dpdr
         de_b = w[1] - dpde / dpdr * w[0]
@@ -312,7 +306,6 @@ class PBP:
             dp_b = dp_b + de_b / (g * rho)
             Fp_b = -dt * de_b / (g * rho)
         else:
-            cv = 1.0 / (g - 1.0)
             t = self.solve_T(cv * de_b)
             Fe_b = rho * t
             dp_b = dp_b + t / (g * dt)

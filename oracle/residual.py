@@ -16,7 +16,8 @@ out here (the same reading is used by the GPU library):
 * cells c = (i, j[, k]); rho, e at centres; u_d[c] on the low-d face of c.
 * ghosts: periodic wrap; at walls scalars and tangential velocities mirror evenly,
   the wall-normal velocity is zero on both wall faces and odd outside.
-* ideal gas, R = mu = 1: p = (gamma-1) rho e, T = (gamma-1) e.
+* equation of state (oracle/eos.py), R = mu = 1: ideal gas p = (gamma-1) rho e,
+  T = (gamma-1) e; with a_rad > 0 gas + radiation p = rho T + a T^4/3, e = c_v T + a T^4/rho.
 * van Leer harmonic slope vl(a, b) = 2ab/(a+b) if ab > 0 else 0.
 * upwind value at the low-d face of c by the sign of w (w >= 0 takes the left state):
   q_L = q[c-1] + vl(q[c-1]-q[c-2], q[c]-q[c-1])/2,  q_R = q[c] - vl(q[c]-q[c-1], q[c+1]-q[c])/2.
@@ -41,6 +42,8 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
+from . import eos
+
 PERIODIC = "periodic"
 WALL = "wall"
 GHOST = 3
@@ -59,6 +62,7 @@ class Problem:
     chi_exp: float = 3.0
     qwall: tuple = None   # per axis (lo, hi) prescribed chi dT/dx_d on wall faces
     theta: float = 1.0
+    a_rad: float = 0.0    # radiation constant of the gas + radiation equation of state
 
     @property
     def nd(self):
@@ -88,7 +92,8 @@ class Problem:
                        gamma=float(p["gamma"]), g=tuple(p.get("g") or (0.0,) * nd),
                        chi_model=p.get("chi_model", "none"), chi0=float(p.get("chi0", 0.0)),
                        chi_tref=float(p.get("chi_tref", 1.0)), chi_exp=float(p.get("chi_exp", 3.0)),
-                       qwall=tuple(tuple(q) for q in qwall), theta=float(p.get("theta", 1.0)))
+                       qwall=tuple(tuple(q) for q in qwall), theta=float(p.get("theta", 1.0)),
+                       a_rad=float(p.get("a_rad", 0.0)))
 
 
 def ghost_index(i, n, bc, odd_normal):
@@ -160,10 +165,10 @@ class Stencil:
         return self.gather(2 + d, off)
 
     def p(self, off):
-        return (self.prob.gamma - 1.0) * self.rho(off) * self.e(off)
+        return eos.pressure(self.prob, self.rho(off), self.e(off))
 
     def T(self, off):
-        return (self.prob.gamma - 1.0) * self.e(off)
+        return eos.temperature(self.prob, self.rho(off), self.e(off))
 
     def chi(self, off):
         pr = self.prob
@@ -402,5 +407,5 @@ def cfl_dt(prob: Problem, X, cfl):
     for d in range(prob.nd):
         uc = 0.5 * (st.u(d, o) + st.u(d, sh(o, d, 1)))
         u2 = u2 + uc * uc
-    cs = np.sqrt(prob.gamma * (prob.gamma - 1.0) * st.e(o))
+    cs = eos.sound_speed(prob, st.rho(o), st.e(o))
     return cfl * min(prob.dx) / float(np.max(np.sqrt(u2) + cs))

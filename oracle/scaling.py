@@ -14,6 +14,8 @@ from __future__ import annotations
 
 import numpy as np
 
+from . import eos
+
 from .residual import Problem, Stencil, sh
 
 
@@ -29,7 +31,7 @@ def scaling_LR(prob: Problem, X, alpha1=1e-5, alpha2=1.0):
     L[1] = rho * e
     R[0] = rho
     R[1] = e
-    cs = lambda off: np.sqrt(prob.gamma * (prob.gamma - 1.0) * st.e(off))
+    cs = lambda off: eos.sound_speed(prob, st.rho(off), st.e(off))
     for d in range(nd):
         csf = 0.5 * (cs(sh(o, d, -1)) + cs(o))
         rf = 0.5 * (st.rho(sh(o, d, -1)) + rho)

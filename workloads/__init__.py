@@ -27,13 +27,15 @@ WALL = "wall"
 
 
 def make_problem(shape, dx, bc, gamma, g=None, chi_model="none", chi0=0.0, chi_tref=1.0,
-                 chi_exp=3.0, qwall=None, theta=1.0):
+                 chi_exp=3.0, qwall=None, theta=1.0, a_rad=0.0):
     """Plain-dict problem description.
 
     shape: cells per axis ordered (nx, ny[, nz]); dx: spacing per axis; bc: per-axis
     'periodic' | 'wall'; g: gravity vector per axis; chi_model: 'none' | 'const' | 'power'
     (chi = chi0 * (T/chi_tref)**chi_exp); qwall: per axis (lo, hi) prescribed conductive flux
-    chi*dT/dx_d through the wall faces (only read on wall axes).
+    chi*dT/dx_d through the wall faces (only read on wall axes); theta: time-weighting of the
+    step (1 backward Euler, 1/2 Crank-Nicolson); a_rad: radiation constant of the gas +
+    radiation equation of state (0: ideal gas).
     """
     nd = len(shape)
     return dict(
@@ -49,6 +51,7 @@ def make_problem(shape, dx, bc, gamma, g=None, chi_model="none", chi0=0.0, chi_t
         chi_exp=float(chi_exp),
         qwall=tuple(tuple(float(q) for q in qw) for qw in (qwall if qwall is not None else ((0.0, 0.0),) * nd)),
         theta=float(theta),
+        a_rad=float(a_rad),
     )
 
 
@@ -131,7 +134,8 @@ def acoustic_bump_2d(n=32, seed=1001, gamma=5.0 / 3.0, amp=1e-3, width_cells=4.0
 # Stratified polytropic boxes (C2, C4 in 2D; C5 in 3D)
 # ----------------------------------------------------------------------------------------
 def polytrope(shape, contrast, poly_n=1.5, gamma=5.0 / 3.0, mach=1e-3, seed=1002, cfl=100.0,
-              cfl_rad=10.0, chi_model="const", chi_exp=3.0, steps=10, name="polytrope"):
+              cfl_rad=10.0, chi_model="const", chi_exp=3.0, steps=10, name="polytrope",
+              a_rad=0.0):
     """Discretely hydrostatic polytrope on [0,1]^nd, gravity along -(last axis), walls there.
 
     T is linear in height at cell centres with T(top boundary) = 1 and
@@ -142,6 +146,12 @@ def polytrope(shape, contrast, poly_n=1.5, gamma=5.0 / 3.0, mach=1e-3, seed=1002
     max chi*dt_ref/(rho c_v dx^2) = cfl_rad with dt_ref = cfl*dx/max(c_s) (velocity ignored).
     The prescribed wall fluxes equal the conductive flux of the initial state at the first
     interior face next to each wall.
+
+    a_rad > 0 (gas + radiation, p = rho T + a T^4/3, e = c_v T + a T^4/rho): the same T
+    profile, g scaled by p/p_gas = 1 + a T_top^3/3 of the top, and the radiation pressure
+    difference added to the balance,
+    rho_{j-1} (T_{j-1} - g h/2) = rho_j (T_j + g h/2) - a (T_{j-1}^4 - T_j^4)/3.
+    With poly_n = 3 this is the discrete form of a constant-beta (p_gas/p) polytrope.
     """
     nd = len(shape)
     vert = nd - 1
@@ -150,13 +160,16 @@ def polytrope(shape, contrast, poly_n=1.5, gamma=5.0 / 3.0, mach=1e-3, seed=1002
     hz = h[vert]
     t_bot = contrast ** (1.0 / poly_n)
     t_top = 1.0
-    gmag = (poly_n + 1.0) * (t_bot - t_top)
+    gmag = (poly_n + 1.0) * (t_bot - t_top) * (1.0 + a_rad * t_top ** 3 / 3.0)
     zc = _centres(nz, hz)
     T1 = t_top + (t_bot - t_top) * (1.0 - zc)
     rho1 = np.empty(nz)
     rho1[-1] = (T1[-1] / t_top) ** poly_n
     for j in range(nz - 1, 0, -1):
-        rho1[j - 1] = rho1[j] * (T1[j] + 0.5 * gmag * hz) / (T1[j - 1] - 0.5 * gmag * hz)
+        rho1[j - 1] = (rho1[j] * (T1[j] + 0.5 * gmag * hz)
+                       - a_rad * (T1[j - 1] ** 4 - T1[j] ** 4) / 3.0) / (T1[j - 1] - 0.5 * gmag * hz)
+    if not np.all(rho1 > 0.0):
+        raise ValueError("radiation pressure gradient exceeds gravity: lower a_rad")
     gs = grid_shape(shape)
     bshape = [1] * nd
     bshape[0] = nz  # vertical axis is numpy axis 0
@@ -165,6 +178,8 @@ def polytrope(shape, contrast, poly_n=1.5, gamma=5.0 / 3.0, mach=1e-3, seed=1002
     X = np.zeros((2 + nd,) + gs)
     X[0] = rho
     X[1] = T / (gamma - 1.0)
+    if a_rad > 0.0:
+        X[1] += a_rad * T ** 4 / rho
     bc = tuple([PERIODIC] * (nd - 1) + [WALL])
     rng = np.random.default_rng(seed)
     _velocity_noise(rng, X, nd, bc, gamma, mach)
@@ -189,7 +204,7 @@ def polytrope(shape, contrast, poly_n=1.5, gamma=5.0 / 3.0, mach=1e-3, seed=1002
     qwall = [(0.0, 0.0)] * nd
     qwall[vert] = (q_lo, q_hi)
     prob = make_problem(shape, tuple(h), bc, gamma, g=g, chi_model=chi_model, chi0=chi0,
-                        chi_tref=t_top, chi_exp=chi_exp, qwall=qwall)
+                        chi_tref=t_top, chi_exp=chi_exp, qwall=qwall, a_rad=a_rad)
     return dict(name=name, problem=prob, X0=X, cfl=cfl, steps=steps, precond="sound_thermal",
                 jv_mode="fd", cfl_rad=cfl_rad)
 
@@ -205,6 +220,15 @@ def stratified_2d_kappa(n=512, seed=1004, steps=5, cfl=50.0):
     """C4: as C2 with chi = chi0 (T/T_top)^3 (adjoint workload)."""
     return polytrope((n, n), 10.0, mach=1e-3, seed=seed, cfl=cfl, chi_model="power", steps=steps,
                      name=f"stratified_2d_kappa_{n}x{n}")
+
+
+def radiative_2d(n=256, seed=1006, steps=5, cfl=50.0, a_rad=1.0):
+    """Gas + radiation polytrope n = 3 (chi ~ T^3, density contrast 10): a_rad = 1 gives
+    p_rad/p_gas = 1/3 (beta = 3/4) throughout, Gamma1 = 1.49 and Gamma3 = 1.42 instead of 5/3.
+    n = 3 is below the adiabatic gradient of such a mixture, so the box is convectively stable
+    (n = 1.5 with radiation would be unstable)."""
+    return polytrope((n, n), 10.0, poly_n=3.0, mach=1e-3, seed=seed, cfl=cfl,
+                     chi_model="power", steps=steps, name=f"radiative_2d_{n}x{n}", a_rad=a_rad)
 
 
 def convective_box_3d(n=256, seed=1005, steps=10, cfl=500.0):
@@ -282,7 +306,7 @@ def isentropic_vortex_2d(n=64, t_inf=1.0, gamma=1.4, beta=0.75, u_inf=1.0):
 # Small random states for Jacobian / parity tests
 # ----------------------------------------------------------------------------------------
 def random_state(shape, bc, seed, gamma=1.4, amp=0.3, umag=0.3, g=None, chi_model="none",
-                 chi0=0.0, chi_tref=1.0, chi_exp=3.0, qwall=None):
+                 chi0=0.0, chi_tref=1.0, chi_exp=3.0, qwall=None, a_rad=0.0):
     """Smooth-free random state: rho, e = 1 + amp*xi; u = umag*xi (walls: normal faces 0).
 
     Random values avoid the branch ties of the upwind and limiter switches almost surely.
@@ -302,7 +326,7 @@ def random_state(shape, bc, seed, gamma=1.4, amp=0.3, umag=0.3, g=None, chi_mode
         X[2 + d] = u
     h = tuple(1.0 / n for n in shape)
     prob = make_problem(shape, h, bc, gamma, g=g, chi_model=chi_model, chi0=chi0,
-                        chi_tref=chi_tref, chi_exp=chi_exp, qwall=qwall)
+                        chi_tref=chi_tref, chi_exp=chi_exp, qwall=qwall, a_rad=a_rad)
     return prob, X
 
 
