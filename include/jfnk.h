@@ -51,19 +51,23 @@ enum { JFNK_JV_FD = 0, JFNK_JV_EXACT = 1 };
 enum { JFNK_PC_NONE = 0, JFNK_PC_SOUND = 1, JFNK_PC_SOUND_THERMAL = 2 };
 enum { JFNK_FP64 = 0, JFNK_FP32 = 1 };
 
-/* Problem: grid, ideal-gas EOS (R = mu = 1: p = (gamma-1) rho e, T = (gamma-1) e),
- * gravity and conductivity (Sect. 2, eqs. cons1-cons3, chirad).                       */
+/* Problem: grid, equation of state, gravity and conductivity (Sect. 2, eqs. cons1-cons3,
+ * chirad).  EOS with R = mu = 1 (Sect. 2, App. A): a_rad = 0 is the ideal gas
+ * p = (gamma-1) rho e, T = (gamma-1) e; a_rad > 0 adds radiation in the diffusion limit,
+ * p = rho T + a_rad T^4/3, e = T/(gamma-1) + a_rad T^4/rho (T(rho, e) by Newton's method,
+ * Gamma1 and Gamma3 from the chain rule).                                              */
 typedef struct {
   int32_t ndim;          /* 2 or 3                                                      */
   int32_t n[3];          /* cells along x, y, z (n[2] = 1 in 2D); each used axis >= 4  */
   double dx[3];          /* spacing per axis                                            */
   int32_t bc[3];         /* JFNK_BC_PERIODIC | JFNK_BC_WALL per axis                    */
-  double gamma;          /* adiabatic index (Gamma1 = Gamma3 = gamma)                  */
+  double gamma;          /* adiabatic index of the gas (Gamma1 = Gamma3 = gamma if ideal) */
   double g[3];           /* gravity vector                                              */
   int32_t chi_model;     /* NONE | CONST (chi0) | POWER (chi0 (T/chi_tref)^chi_exp)     */
   double chi0, chi_tref, chi_exp;
   double qwall[3][2];    /* prescribed conductive flux chi dT/dx_d on the low/high wall  */
   double theta;          /* time weighting: 1 = backward Euler, 1/2 = Crank-Nicolson    */
+  double a_rad;          /* radiation constant (>= 0; 0: ideal gas)                     */
 } jfnk_problem;
 
 /* Solver options; jfnk_default_opts fills the values the paper uses (Sect. 4, 5.1.1).  */
@@ -143,6 +147,12 @@ int jfnk_vjp_prev(jfnk_ctx* ctx, const double* Xn, const double* lam, double* ou
  * semi-implicit schemes of Sects. 3.3-3.4); elliptic solves by multigrid-preconditioned
  * CG to opts.cg_eta in opts.ell_precision.  Needs jfnk_set_state_n (for dt).           */
 int jfnk_precond_apply(jfnk_ctx* ctx, const double* X, const double* r, double* z);
+
+/* z = M^-T w, the transpose of jfnk_precond_apply's operator at the same X (the adjoint
+ * step's right preconditioner, unscaled): the transposed pointwise maps in reverse order
+ * around the same symmetric elliptic solves.  Same arguments, requirements and
+ * synchronisation as jfnk_precond_apply.                                                */
+int jfnk_precond_apply_transpose(jfnk_ctx* ctx, const double* X, const double* w, double* z);
 
 /* One implicit step: X holds X^n on entry and X^{n+1} on return (Sect. 4).  dt > 0 is
  * used as given.  Newton from X^n on the scaled system, FGMRES(m) with CGS2, J.v per

@@ -58,6 +58,7 @@ def _problem_struct(p):
     s.chi_tref = float(p.get("chi_tref", 1.0))
     s.chi_exp = float(p.get("chi_exp", 3.0))
     s.theta = float(p.get("theta", 1.0))
+    s.a_rad = float(p.get("a_rad", 0.0))
     return s
 
 
@@ -180,6 +181,12 @@ class Context:
         out = self._new() if out is None else self._vec(out, "out")
         self._check(self._lib.jfnk_precond_apply(self._h, _ptr(self._vec(X, "X")),
                                                  _ptr(self._vec(r, "r")), _ptr(out)))
+        return out
+
+    def precond_apply_T(self, X, w, out=None):
+        out = self._new() if out is None else self._vec(out, "out")
+        self._check(self._lib.jfnk_precond_apply_transpose(self._h, _ptr(self._vec(X, "X")),
+                                                   _ptr(self._vec(w, "w")), _ptr(out)))
         return out
 
     def implicit_step(self, X, dt, raise_on_noconv=True):

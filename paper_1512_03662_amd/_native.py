@@ -41,6 +41,7 @@ class Problem(C.Structure):
         ("chi_exp", C.c_double),
         ("qwall", (C.c_double * 2) * 3),
         ("theta", C.c_double),
+        ("a_rad", C.c_double),
     ]
 
 
@@ -95,6 +96,7 @@ SIGNATURES = {
     "jfnk_vjp": (C.c_int, [_P, _P, _P, _P]),
     "jfnk_vjp_prev": (C.c_int, [_P, _P, _P, _P]),
     "jfnk_precond_apply": (C.c_int, [_P, _P, _P, _P]),
+    "jfnk_precond_apply_transpose": (C.c_int, [_P, _P, _P, _P]),
     "jfnk_implicit_step": (C.c_int, [_P, _P, _D, C.POINTER(StepStats)]),
     "jfnk_adjoint_step": (C.c_int, [_P, _P, _P, _D, _P, _P, C.POINTER(StepStats)]),
     "jfnk_cfl_dt": (C.c_double, [_P, _P, _D]),

@@ -304,31 +304,30 @@ template void launch_fill_t<double>(size_t, double, double*, hipStream_t);
 template void launch_fill_t<float>(size_t, float, float*, hipStream_t);
 
 // ---- scaled norms (R of Sect. 4.1 recomputed from X) ------------------------------------
-template <int ND>
+template <int ND, bool RAD>
 __device__ __forceinline__ void cell_R_scale(const Grid& G, const Pos& P, const double* X, double alpha2,
                                              double* Rs) {
-  const double k = G.gamma * (G.gamma - 1.0);
   double e0 = X[G.N + P.lin];
-  double cs0 = sqrt(k * e0);
+  double cs0 = sound_speed<RAD>(G, X[P.lin], e0);
   Rs[0] = X[P.lin];
   Rs[1] = e0;
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
     double s;
     int im = gidx<ND>(G, P, 1, shift(off0(), d, -1), &s);
-    double csf = 0.5 * (sqrt(k * X[G.N + im]) + cs0);
+    double csf = 0.5 * (sound_speed<RAD>(G, X[im], X[G.N + im]) + cs0);
     Rs[2 + d] = fmax(fabs(X[(2 + d) * G.N + P.lin]), alpha2 * csf);
   }
 }
 
-template <int ND, bool MAX>
+template <int ND, bool MAX, bool RAD>
 __global__ void __launch_bounds__(kBlock) k_scaled_red(Grid G, const double* X, const double* V,
                                                        double alpha2, double* out, RedWS ws) {
   double acc = 0.0;
   for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < G.N; lin += gridDim.x * kBlock) {
     Pos P = make_pos<ND>(G, lin);
     double Rs[2 + ND];
-    cell_R_scale<ND>(G, P, X, alpha2, Rs);
+    cell_R_scale<ND, RAD>(G, P, X, alpha2, Rs);
 #pragma unroll
     for (int v = 0; v < 2 + ND; ++v) {
       double q = V[v * G.N + lin] / Rs[v];
@@ -346,18 +345,27 @@ void launch_scaled_norm2(const Grid& G, const double* X, const double* V, double
   int b = red_blocks(G.N);
   {
     const double by = 16.0 * (2 + G.nd) * G.N;
+    const bool rad = G.a_rad != 0.0;
     if (G.nd == 2)
-      launch_k(KF_SCALED, by, k_scaled_red<2, false>, dim3(b), dim3(kBlock), 0, s, G, X, V, alpha2, out, ws);
+      launch_k(KF_SCALED, by, rad ? k_scaled_red<2, false, true> : k_scaled_red<2, false, false>, dim3(b),
+               dim3(kBlock), 0, s, G, X, V, alpha2, out, ws);
     else
-      launch_k(KF_SCALED, by, k_scaled_red<3, false>, dim3(b), dim3(kBlock), 0, s, G, X, V, alpha2, out, ws);
+      launch_k(KF_SCALED, by, rad ? k_scaled_red<3, false, true> : k_scaled_red<3, false, false>, dim3(b),
+               dim3(kBlock), 0, s, G, X, V, alpha2, out, ws);
   }
   finalize<OpSum>(ws, b, 1, out, s);
 }
 void launch_scaled_maxabs(const Grid& G, const double* X, const double* V, double alpha2,
                           double* out, const RedWS& ws, hipStream_t s) {
   int b = red_blocks(G.N);
-  if (G.nd == 2) k_scaled_red<2, true><<<b, kBlock, 0, s>>>(G, X, V, alpha2, out, ws);
-  else k_scaled_red<3, true><<<b, kBlock, 0, s>>>(G, X, V, alpha2, out, ws);
+  const bool rad = G.a_rad != 0.0;
+  if (G.nd == 2) {
+    if (rad) k_scaled_red<2, true, true><<<b, kBlock, 0, s>>>(G, X, V, alpha2, out, ws);
+    else k_scaled_red<2, true, false><<<b, kBlock, 0, s>>>(G, X, V, alpha2, out, ws);
+  } else {
+    if (rad) k_scaled_red<3, true, true><<<b, kBlock, 0, s>>>(G, X, V, alpha2, out, ws);
+    else k_scaled_red<3, true, false><<<b, kBlock, 0, s>>>(G, X, V, alpha2, out, ws);
+  }
   finalize<OpMax>(ws, b, 1, out, s);
 }
 
@@ -365,7 +373,6 @@ void launch_scaled_maxabs(const Grid& G, const double* X, const double* V, doubl
 template <int ND>
 __global__ void __launch_bounds__(kBlock) k_cfl_speed(Grid G, const double* X, double* out, RedWS ws) {
   double acc = 0.0;
-  const double k = G.gamma * (G.gamma - 1.0);
   for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < G.N; lin += gridDim.x * kBlock) {
     Pos P = make_pos<ND>(G, lin);
     double u2 = 0.0;
@@ -377,7 +384,7 @@ __global__ void __launch_bounds__(kBlock) k_cfl_speed(Grid G, const double* X, d
       double uc = 0.5 * (s0 * X[(2 + d) * G.N + i0] + s1 * X[(2 + d) * G.N + i1]);
       u2 += uc * uc;
     }
-    acc = fmax(acc, sqrt(u2) + sqrt(k * X[G.N + lin]));
+    acc = fmax(acc, sqrt(u2) + sound_speed_rt(G, X[lin], X[G.N + lin]));
   }
   double a[1] = {acc};
   block_finish<OpMax, 1>(a, out, ws);

@@ -26,6 +26,7 @@ struct Grid {
   double chi0, chi_tref_inv, chi_exp;
   double qwall[3][2];
   double theta;
+  double a_rad;     // radiation constant of the equation of state (0: ideal gas)
 };
 
 // ------------------------------------------------------------------------------------
@@ -67,6 +68,115 @@ __device__ __forceinline__ dual powr(dual x, double p) {
   }
   double y = pow(x.v, p);
   return dual(y, p * y / x.v * x.d);
+}
+
+// ------------------------------------------------------------------------------------
+// Equation of state (Sect. 2, App. A), R = mu = 1.
+//   a_rad = 0: ideal gas, p = (gamma-1) rho e, T = (gamma-1) e, Gamma1 = Gamma3 = gamma.
+//   a_rad > 0: gas + radiation in the diffusion limit, p = rho T + a T^4/3 and
+//              e = c_v T + a T^4/rho with c_v = 1/(gamma-1) and a = a_rad.
+// T(rho, e) is the positive root of c_v T + (a/rho) T^4 = e.  Newton steps start from
+// min((gamma-1) e, (rho e/a)^(1/4)), which lies above the root by at most 38%; the quartic
+// is convex, so the steps decrease to the root with relative error eps' <= 1.5 eps^2 and
+// kEosNewton steps leave it at rounding (six would do).
+// Kernels on the hot path take the choice as a template argument RAD, so that their ideal-gas
+// instantiation carries no radiative code; the others branch on a_rad (uniform per launch).
+// ------------------------------------------------------------------------------------
+constexpr int kEosNewton = 8;
+
+__device__ __forceinline__ double rad_temperature(const Grid& G, double rho, double e) {
+  const double cv = 1.0 / (G.gamma - 1.0);
+  const double b = G.a_rad / rho;
+  double t = fmin((G.gamma - 1.0) * e, sqrt(sqrt(e / b)));
+#pragma unroll
+  for (int k = 0; k < kEosNewton; ++k) {
+    const double t3 = t * t * t;
+    t -= (cv * t + b * t3 * t - e) / (cv + 4.0 * b * t3);
+  }
+  return t;
+}
+
+template <bool RAD>
+__device__ __forceinline__ double eos_T(const Grid& G, double rho, double e) {
+  if constexpr (RAD) return rad_temperature(G, rho, e);
+  else return (G.gamma - 1.0) * e;
+}
+// tangent: dT = (de + (a T^4/rho^2) drho) / (c_v + 4 a T^3/rho)
+template <bool RAD>
+__device__ __forceinline__ dual eos_T(const Grid& G, dual rho, dual e) {
+  if constexpr (RAD) {
+    const double t = rad_temperature(G, rho.v, e.v);
+    const double b = G.a_rad / rho.v, t3 = t * t * t;
+    return dual(t, (e.d + b * t3 * t / rho.v * rho.d) / (1.0 / (G.gamma - 1.0) + 4.0 * b * t3));
+  } else {
+    return (G.gamma - 1.0) * e;
+  }
+}
+
+template <bool RAD, class T>
+__device__ __forceinline__ T eos_p(const Grid& G, T rho, T e) {
+  if constexpr (RAD) {
+    const T t = eos_T<true>(G, rho, e);
+    const T t2 = t * t;
+    return rho * t + (G.a_rad / 3.0) * (t2 * t2);
+  } else {
+    return (G.gamma - 1.0) * rho * e;
+  }
+}
+
+// p, T and the derivatives the preconditioner's transforms and the adjoint need:
+// dp/drho|_e, dp/de|_rho, Gamma1 = (rho/p)(dp/drho|_e + (p/rho^2) dp/de|_rho),
+// c_v = de/dT|_rho, dT/drho|_e, dT/de|_rho
+struct Thermo {
+  double p, T, dpdr, dpde, G1, cv, dTdr, dTde;
+};
+
+template <bool RAD>
+__device__ __forceinline__ Thermo thermo(const Grid& G, double rho, double e) {
+  Thermo s;
+  const double gm1 = G.gamma - 1.0;
+  if constexpr (!RAD) {
+    s.p = gm1 * rho * e;
+    s.T = gm1 * e;
+    s.dpdr = gm1 * e;
+    s.dpde = gm1 * rho;
+    s.G1 = G.gamma;
+    s.cv = 1.0 / gm1;
+    s.dTdr = 0.0;
+    s.dTde = gm1;
+  } else {
+    const double a = G.a_rad;
+    const double t = rad_temperature(G, rho, e);
+    const double t3 = t * t * t;
+    const double eT = 1.0 / gm1 + 4.0 * a * t3 / rho;  // de/dT|_rho
+    const double pT = rho + (4.0 / 3.0) * a * t3;      // dp/dT|_rho
+    s.T = t;
+    s.p = rho * t + (a / 3.0) * t3 * t;
+    s.cv = eT;
+    s.dTde = 1.0 / eT;
+    s.dTdr = a * t3 * t / (rho * rho) * s.dTde;       // -(de/drho|_T) / (de/dT|_rho)
+    s.dpde = pT * s.dTde;
+    s.dpdr = t + pT * s.dTdr;
+    s.G1 = (rho / s.p) * (s.dpdr + s.p / (rho * rho) * s.dpde);
+  }
+  return s;
+}
+__device__ __forceinline__ Thermo thermo_rt(const Grid& G, double rho, double e) {
+  return G.a_rad == 0.0 ? thermo<false>(G, rho, e) : thermo<true>(G, rho, e);
+}
+
+// adiabatic sound speed sqrt(Gamma1 p/rho)
+template <bool RAD>
+__device__ __forceinline__ double sound_speed(const Grid& G, double rho, double e) {
+  if constexpr (!RAD) {
+    return sqrt(G.gamma * (G.gamma - 1.0) * e);
+  } else {
+    const Thermo s = thermo<true>(G, rho, e);
+    return sqrt(s.dpdr + s.p / (rho * rho) * s.dpde);
+  }
+}
+__device__ __forceinline__ double sound_speed_rt(const Grid& G, double rho, double e) {
+  return G.a_rad == 0.0 ? sound_speed<false>(G, rho, e) : sound_speed<true>(G, rho, e);
 }
 
 // Reciprocal by the hardware estimate refined with two Newton steps (relative error within

@@ -107,12 +107,16 @@ __global__ void __launch_bounds__(kBlock) k_ell_coef(Grid G, const double* X, do
   if (lin >= G.N) return;
   Pos P = make_pos<ND>(G, lin);
   const double gm1 = G.gamma - 1.0;
+  const bool rad = G.a_rad != 0.0;
   const double rho = X[lin], e = X[G.N + lin];
   double* w[3] = {w0, w1, w2};
+  Thermo th;
+  if (rad) th = thermo<true>(G, rho, e);
+  // pressure: 1/(Gamma1 p dt); thermal: rho c_v/dt with c_v = de/dT|_rho
   if (op == 0) {
-    diag[lin] = 1.0 / (G.gamma * gm1 * rho * e * dt);
+    diag[lin] = rad ? 1.0 / (th.G1 * th.p * dt) : 1.0 / (G.gamma * gm1 * rho * e * dt);
   } else {
-    diag[lin] = rho / (gm1 * dt);
+    diag[lin] = rad ? rho * th.cv / dt : rho / (gm1 * dt);
   }
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
@@ -125,7 +129,8 @@ __global__ void __launch_bounds__(kBlock) k_ell_coef(Grid G, const double* X, do
       double rf = 0.5 * (X[im] + rho);
       wf = dt / (rf * G.dx[d] * G.dx[d]);
     } else {
-      double Tm = gm1 * X[G.N + im], T0 = gm1 * e;
+      double Tm = rad ? rad_temperature(G, X[im], X[G.N + im]) : gm1 * X[G.N + im];
+      double T0 = rad ? th.T : gm1 * e;
       double cm, c0;
       if (G.chi_model == 1) {
         cm = G.chi0;
@@ -1074,13 +1079,12 @@ __device__ __forceinline__ void r_cell(const Grid& G, const double* X, const dou
 // scaled
 __device__ __forceinline__ double fu_face(const Grid& G, const double* X, const double* v, int scaled,
                                           double alpha1, int d, int lf, int lm) {
-  const double k = G.gamma * (G.gamma - 1.0);
   const double rho = X[lf], rhom = X[lm];
   const double rf = 0.5 * (rhom + rho);
   const double ud = X[(2 + d) * G.N + lf];
   double rm = v[(2 + d) * G.N + lf], r0m = v[lm], r0c = v[lf];
   if (scaled) {
-    const double csf = 0.5 * (sqrt(k * X[G.N + lm]) + sqrt(k * X[G.N + lf]));
+    const double csf = 0.5 * (sound_speed_rt(G, rhom, X[G.N + lm]) + sound_speed_rt(G, rho, X[G.N + lf]));
     rm *= rf * fmax(fabs(ud), alpha1 * csf);
     r0m *= rhom;
     r0c *= rho;
@@ -1094,13 +1098,14 @@ __global__ void __launch_bounds__(kBlock) k_pbp_in(Grid G, const double* X, cons
                                                    double alpha1, double dt, int schur, double* rhs_p) {
   int lin = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (lin >= G.N) return;
-  const double gm1 = G.gamma - 1.0;
   double rho = X[lin], e = X[G.N + lin];
   double r0, rE;
   r_cell(G, X, v, scaled, lin, &r0, &rE);
-  double dpdr = gm1 * e, dpde = gm1 * rho;
+  const Thermo th = thermo_rt(G, rho, e);
+  const double dpdr = th.dpdr, dpde = th.dpde;
   double Fp = (dpdr - (e / rho) * dpde) * r0 + (dpde / rho) * rE;
-  double rhs = Fp / (G.gamma * gm1 * rho * e);
+  const double g1p = G.a_rad == 0.0 ? G.gamma * (G.gamma - 1.0) * rho * e : th.G1 * th.p;
+  double rhs = Fp / g1p;
   if (schur) {
     Pos P = make_pos<ND>(G, lin);
     double div = 0.0;
@@ -1128,14 +1133,14 @@ __global__ void __launch_bounds__(kBlock) k_pbp_rhsT(Grid G, const double* X, co
                                                      double dt, const double* dp, double* rhs_T) {
   int lin = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (lin >= G.N) return;
-  const double gm1 = G.gamma - 1.0;
   double rho = X[lin], e = X[G.N + lin];
   double r0, rE;
   r_cell(G, X, v, scaled, lin, &r0, &rE);
-  double dpdr = gm1 * e, dpde = gm1 * rho;
+  const Thermo th = thermo_rt(G, rho, e);
+  const double dpdr = th.dpdr, dpde = th.dpde;
   double Fp = (dpdr - (e / rho) * dpde) * r0 + (dpde / rho) * rE;
   double Fe = (rE - e * r0) / rho;
-  rhs_T[lin] = rho * Fe + (dp[lin] / dt - Fp) / G.gamma;
+  rhs_T[lin] = rho * Fe + (dp[lin] / dt - Fp) / th.G1;
 }
 
 template <int ND>
@@ -1146,17 +1151,18 @@ __global__ void __launch_bounds__(kBlock) k_pbp_out(Grid G, const double* X, con
   if (lin >= G.N) return;
   Pos P = make_pos<ND>(G, lin);
   const double gm1 = G.gamma - 1.0;
-  const double k = G.gamma * gm1;
+  const bool rad = G.a_rad != 0.0;
   double rho = X[lin], e = X[G.N + lin];
   double r0, rE;
   r_cell(G, X, v, scaled, lin, &r0, &rE);
-  double dpdr = gm1 * e, dpde = gm1 * rho;
+  const Thermo th = thermo_rt(G, rho, e);
+  const double dpdr = th.dpdr, dpde = th.dpde;
   double Fp = (dpdr - (e / rho) * dpde) * r0 + (dpde / rho) * rE;
   double Fe = (rE - e * r0) / rho;
   double dpc = dp[lin];
   double de;
-  if (dT) de = dT[lin] / gm1;
-  else de = dt * Fe + (dpc - dt * Fp) / (G.gamma * rho);
+  if (dT) de = rad ? th.cv * dT[lin] : dT[lin] / gm1;  // de = c_v dT
+  else de = dt * Fe + (dpc - dt * Fp) / (th.G1 * rho);
   z[lin] = zs * ((dpc - dpde * de) / dpdr);
   z[G.N + lin] = zs * de;
 #pragma unroll
@@ -1171,7 +1177,7 @@ __global__ void __launch_bounds__(kBlock) k_pbp_out(Grid G, const double* X, con
     double r0c = v[lin];
     double ud = X[(2 + d) * G.N + lin];
     if (scaled) {
-      double csf = 0.5 * (sqrt(k * X[G.N + im]) + sqrt(k * e));
+      double csf = 0.5 * (sound_speed_rt(G, rhom, X[G.N + im]) + sound_speed_rt(G, rho, e));
       rm = vm * rf * fmax(fabs(ud), alpha1 * csf);
       r0m *= rhom;
       r0c *= rho;

@@ -208,7 +208,7 @@ void launch_vjp(const Grid& G, const double* X, const double* w, double cU, doub
 // (scaled != 0: the input is v with w = v / R)
 void launch_pbpT_in(const Grid& G, const double* X, const double* v, int scaled, double alpha2,
                     double dt, int thermal, double* rhs_p, double* rhs_T, hipStream_t s);
-void launch_pbpT_mid(const Grid& G, double dt, const double* t, double* rhs_p, hipStream_t s);
+void launch_pbpT_mid(const Grid& G, const double* X, double dt, const double* t, double* rhs_p, hipStream_t s);
 void launch_pbpT_out(const Grid& G, const double* X, const double* v, int scaled, double alpha2,
                      double dt, const double* sp, const double* t, int schur, double zscale, double* z,
                      hipStream_t s);

@@ -9,7 +9,7 @@
 //   mean of f_d on both faces, Phi_de at the (low-d, low-e) edge carried by the mean of f_e
 //   of the two cells sharing it, both with upwind van Leer values of u_d;
 //   R_m,d = -ddiv Phi - (p[c]-p[c-1])/dx_d + rho_f g_d  (zero on wall-normal wall faces).
-// Ideal gas with R = mu = 1: p = (gamma-1) rho e, T = (gamma-1) e.
+// Equation of state: ideal gas, or gas + radiation (RAD), with R = mu = 1 (common.hpp).
 //
 // Every flux is evaluated once per tile (see tile_axis); each thread then produces all nvar
 // rows of its cell.  The scalar type is double for values, dual for the exact forward-mode
@@ -72,54 +72,23 @@ struct Stencil {
   __device__ __forceinline__ T rho(Off o) const { return at(0, o); }
   __device__ __forceinline__ T e(Off o) const { return at(1, o); }
   __device__ __forceinline__ T u(int d, Off o) const { return at(2 + d, o); }
-  __device__ __forceinline__ T chi(T T_) const {
-    if (G.chi_model == 1) return T(G.chi0);
-    return G.chi0 * powr(T_ * G.chi_tref_inv, G.chi_exp);
-  }
-  // mass flux f_d and optionally energy flux g_d at the low-d face of c+o
-  __device__ __forceinline__ T mass(int d, Off o) const {
-    T w = u(d, o);
-    T rs = upwind(rho(shift(o, d, -2)), rho(shift(o, d, -1)), rho(o), rho(shift(o, d, 1)), val(w));
-    return w * rs;
-  }
-  __device__ __forceinline__ void mass_energy(int d, Off o, T* f, T* g) const {
-    T w = u(d, o);
-    double wv = val(w);
-    T rs = upwind(rho(shift(o, d, -2)), rho(shift(o, d, -1)), rho(o), rho(shift(o, d, 1)), wv);
-    T es = upwind(e(shift(o, d, -2)), e(shift(o, d, -1)), e(o), e(shift(o, d, 1)), wv);
-    *f = w * rs;
-    *g = (*f) * es;
-  }
-  __device__ __forceinline__ T cond(int d, Off o) const {
-    if (G.bc[d] == 1) {
-      int fi = P.c[d] + o.o[d];
-      if (fi == 0) return T(G.qwall[d][0]);
-      if (fi == G.n[d]) return T(G.qwall[d][1]);
-    }
-    double gm1 = G.gamma - 1.0;
-    T Tm = gm1 * e(shift(o, d, -1));
-    T T0 = gm1 * e(o);
-    T chif = 0.5 * (chi(Tm) + chi(T0));
-    return chif * (T0 - Tm) * G.idx[d];
-  }
 };
 
 // L (residual scaling) of the rows of one cell, from X (Sect. 4.1).
-template <int ND>
+template <int ND, bool RAD>
 __device__ __forceinline__ void cell_L(const Grid& G, const Pos& P, const double* X, double alpha1,
                                        double* L) {
   LoadVal<double> ld{X, G.N};
   Stencil<ND, double, LoadVal<double>> S(G, P, ld);
   const Off o = off0();
   double rho0 = S.rho(o), e0 = S.e(o);
-  double k = G.gamma * (G.gamma - 1.0);
-  double cs0 = sqrt(k * e0);
+  double cs0 = sound_speed<RAD>(G, rho0, e0);
   L[0] = rho0;
   L[1] = rho0 * e0;
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
     Off m = shift(o, d, -1);
-    double csf = 0.5 * (sqrt(k * S.e(m)) + cs0);
+    double csf = 0.5 * (sound_speed<RAD>(G, S.rho(m), S.e(m)) + cs0);
     double rf = 0.5 * (S.rho(m) + rho0);
     double au = fabs(X[(2 + d) * G.N + P.lin]);
     L[2 + d] = rf * fmax(au, alpha1 * csf);
@@ -127,20 +96,20 @@ __device__ __forceinline__ void cell_L(const Grid& G, const Pos& P, const double
 }
 
 // R (unknown scaling) of the unknowns of one cell, from X (Sect. 4.1).
-template <int ND>
+template <int ND, bool RAD>
 __device__ __forceinline__ void cell_Rs(const Grid& G, const Pos& P, const double* X, double alpha2,
                                         double* Rs) {
   LoadVal<double> ld{X, G.N};
   Stencil<ND, double, LoadVal<double>> S(G, P, ld);
   const Off o = off0();
   double e0 = S.e(o);
-  double k = G.gamma * (G.gamma - 1.0);
-  double cs0 = sqrt(k * e0);
+  double cs0 = sound_speed<RAD>(G, S.rho(o), e0);
   Rs[0] = S.rho(o);
   Rs[1] = e0;
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
-    double csf = 0.5 * (sqrt(k * S.e(shift(o, d, -1))) + cs0);
+    const Off m = shift(o, d, -1);
+    double csf = 0.5 * (sound_speed<RAD>(G, S.rho(m), S.e(m)) + cs0);
     double au = fabs(X[(2 + d) * G.N + P.lin]);
     Rs[2 + d] = fmax(au, alpha2 * csf);
   }
@@ -265,7 +234,7 @@ __device__ __forceinline__ T chi_of(const Grid& G, T Tc) {
 }
 
 // contributions of the fluxes along axis D to the rows R of the thread's own cell l
-template <int ND, int D, class T, class AT>
+template <int ND, int D, bool RAD, class T, class AT>
 __device__ __forceinline__ void tile_axis(const Grid& G, const AT& at, const TileIdx<ND>& ti, const int* l,
                                           bool own, T* R, T& divu, T* sF, T* sE, T* sP) {
   constexpr int E0 = fext<ND, D>(0), E1 = fext<ND, D>(1), E2 = fext<ND, D>(2);
@@ -274,7 +243,6 @@ __device__ __forceinline__ void tile_axis(const Grid& G, const AT& at, const Til
   constexpr int NS = S0 * S1 * S2;
   constexpr int SM = smaxsz<ND>();
   const int tid = threadIdx.x;
-  const double gm1 = G.gamma - 1.0;
   const double ix = G.idx[D];
   auto fid = [&](const int* q) {
     return (q[0] - flo<ND>(0)) + (q[1] - flo<ND>(1)) * E0 + (q[2] - flo<ND>(2)) * E0 * E1;
@@ -309,7 +277,7 @@ __device__ __forceinline__ void tile_axis(const Grid& G, const AT& at, const Til
         } else if (G.bc[D] == 1 && fi == G.n[D]) {
           qc = T(G.qwall[D][1]);
         } else {
-          const T Tm = gm1 * ee[1], T0 = gm1 * ee[2];
+          const T Tm = eos_T<RAD>(G, r[1], ee[1]), T0 = eos_T<RAD>(G, r[2], ee[2]);
           const T chif = 0.5 * (chi_of(G, Tm) + chi_of(G, T0));
           qc = chif * (T0 - Tm) * ix;
         }
@@ -384,7 +352,7 @@ __host__ __device__ constexpr int box_size() {
 
 // sRE: LDS for rho and e on the box (value and finite-difference forms only; nullptr: read
 // every field from memory)
-template <int ND, bool IN, class T, class LD>
+template <int ND, bool IN, bool RAD, class T, class LD>
 __device__ __forceinline__ bool tile_RU_in(const Grid& G, const LD& ld, const TileIdx<ND>& ti, T* R, T* U,
                                            int* lin_out, T* sF, T* sE, T* sP, T* sRE) {
   using TT = RTile<ND>;
@@ -416,13 +384,12 @@ __device__ __forceinline__ bool tile_RU_in(const Grid& G, const LD& ld, const Ti
 #pragma unroll
   for (int v = 0; v < 2 + ND; ++v) R[v] = T(0.0);
   T divu = T(0.0);
-  tile_axis<ND, 0>(G, at, ti, l, own, R, divu, sF, sE, sP);
-  tile_axis<ND, 1>(G, at, ti, l, own, R, divu, sF, sE, sP);
-  if constexpr (ND == 3) tile_axis<ND, 2>(G, at, ti, l, own, R, divu, sF, sE, sP);
+  tile_axis<ND, 0, RAD>(G, at, ti, l, own, R, divu, sF, sE, sP);
+  tile_axis<ND, 1, RAD>(G, at, ti, l, own, R, divu, sF, sE, sP);
+  if constexpr (ND == 3) tile_axis<ND, 2, RAD>(G, at, ti, l, own, R, divu, sF, sE, sP);
   if (!own) return false;
-  const double gm1 = G.gamma - 1.0;
   const T rho0 = at(0, l), e0 = at(1, l);
-  const T p0 = gm1 * rho0 * e0;
+  const T p0 = eos_p<RAD>(G, rho0, e0);
   R[1] = R[1] - p0 * divu;
   const int lin = ti.base + l[0] + l[1] * G.stride[1] + ((ND == 3) ? l[2] * G.stride[2] : 0);
   U[0] = rho0;
@@ -437,7 +404,7 @@ __device__ __forceinline__ bool tile_RU_in(const Grid& G, const LD& ld, const Ti
     if (G.bc[d] == 1 && ti.o[d] + l[d] == 0) {
       R[2 + d] = T(0.0);
     } else {
-      const T pm = gm1 * rhom * at(1, lm);
+      const T pm = eos_p<RAD>(G, rhom, at(1, lm));
       R[2 + d] = R[2 + d] - (p0 - pm) * G.idx[d] + rf * G.g[d];
     }
   }
@@ -447,7 +414,7 @@ __device__ __forceinline__ bool tile_RU_in(const Grid& G, const LD& ld, const Ti
 
 // R and U of the thread's cell; returns false (outputs unset) when the thread's cell lies
 // outside the grid.  Every thread of the block must call it (it synchronises the block).
-template <int ND, class T, class LD>
+template <int ND, bool RAD, class T, class LD>
 __device__ __forceinline__ bool tile_RU(const Grid& G, const LD& ld, T* R, T* U, int* lin_out) {
   // rho and e are staged in LDS when the loader combines two arrays per value (X + delta V);
   // for plain values the staging costs more than it saves, and staged duals would double
@@ -459,18 +426,18 @@ __device__ __forceinline__ bool tile_RU(const Grid& G, const LD& ld, T* R, T* U,
   __shared__ T sRE[STAGE ? 2 * box_size<ND>() : 1];
   T* re = STAGE ? sRE : nullptr;
   const TileIdx<ND> ti = tile_setup<ND>(G);
-  if (ti.interior) return tile_RU_in<ND, true>(G, ld, ti, R, U, lin_out, sF, sE, sP, re);
-  return tile_RU_in<ND, false>(G, ld, ti, R, U, lin_out, sF, sE, sP, re);
+  if (ti.interior) return tile_RU_in<ND, true, RAD>(G, ld, ti, R, U, lin_out, sF, sE, sP, re);
+  return tile_RU_in<ND, false, RAD>(G, ld, ti, R, U, lin_out, sF, sE, sP, re);
 }
 
 // ---- kernels --------------------------------------------------------------------------
-template <int ND>
+template <int ND, bool RAD>
 __global__ void __launch_bounds__(kBlock) k_resid_value(Grid G, ResidArgs a) {
   LoadVal<double> ld{a.X, G.N};
   double R[2 + ND], U[2 + ND], L[2 + ND];
   int lin;
-  if (!tile_RU<ND>(G, ld, R, U, &lin)) return;
-  if (a.scaleL) cell_L<ND>(G, make_pos<ND>(G, lin), a.X, a.alpha1, L);
+  if (!tile_RU<ND, RAD>(G, ld, R, U, &lin)) return;
+  if (a.scaleL) cell_L<ND, RAD>(G, make_pos<ND>(G, lin), a.X, a.alpha1, L);
 #pragma unroll
   for (int v = 0; v < 2 + ND; ++v) {
     double gv = a.cU * U[v] + a.cR * R[v];
@@ -482,14 +449,14 @@ __global__ void __launch_bounds__(kBlock) k_resid_value(Grid G, ResidArgs a) {
   }
 }
 
-template <int ND>
+template <int ND, bool RAD>
 __global__ void __launch_bounds__(kBlock) k_resid_tangent(Grid G, ResidArgs a) {
   LoadDual ld{a.X, a.V, G.N};
   dual R[2 + ND], U[2 + ND];
   double L[2 + ND];
   int lin;
-  if (!tile_RU<ND>(G, ld, R, U, &lin)) return;
-  if (a.scaleL) cell_L<ND>(G, make_pos<ND>(G, lin), a.X, a.alpha1, L);
+  if (!tile_RU<ND, RAD>(G, ld, R, U, &lin)) return;
+  if (a.scaleL) cell_L<ND, RAD>(G, make_pos<ND>(G, lin), a.X, a.alpha1, L);
 #pragma unroll
   for (int v = 0; v < 2 + ND; ++v) {
     double out = a.cU * U[v].d + a.cR * R[v].d;
@@ -498,7 +465,7 @@ __global__ void __launch_bounds__(kBlock) k_resid_tangent(Grid G, ResidArgs a) {
   }
 }
 
-template <int ND>
+template <int ND, bool RAD>
 __global__ void __launch_bounds__(kBlock) k_resid_fd(Grid G, ResidArgs a) {
   const double xn2 = a.fd_norms[0], zn2 = a.fd_norms[1];
   if (!(zn2 > 0.0)) {  // the same for every thread: no block-wide work follows
@@ -519,8 +486,8 @@ __global__ void __launch_bounds__(kBlock) k_resid_fd(Grid G, ResidArgs a) {
   LoadShift ld{a.X, a.V, delta, G.N};
   double R[2 + ND], U[2 + ND], L[2 + ND];
   int lin;
-  if (!tile_RU<ND>(G, ld, R, U, &lin)) return;
-  if (a.scaleL) cell_L<ND>(G, make_pos<ND>(G, lin), a.X, a.alpha1, L);
+  if (!tile_RU<ND, RAD>(G, ld, R, U, &lin)) return;
+  if (a.scaleL) cell_L<ND, RAD>(G, make_pos<ND>(G, lin), a.X, a.alpha1, L);
 #pragma unroll
   for (int v = 0; v < 2 + ND; ++v) {
     double out = (a.cU * U[v] + a.cR * R[v] - a.B[v * G.N + lin]) / delta;
@@ -537,8 +504,13 @@ __global__ void __launch_bounds__(kBlock) k_scale_LR(Grid G, const double* X, do
   if (lin >= G.N) return;
   Pos P = make_pos<ND>(G, lin);
   double S[2 + ND];
-  if (which == 0) cell_L<ND>(G, P, X, alpha, S);
-  else cell_Rs<ND>(G, P, X, alpha, S);
+  if (G.a_rad == 0.0) {
+    if (which == 0) cell_L<ND, false>(G, P, X, alpha, S);
+    else cell_Rs<ND, false>(G, P, X, alpha, S);
+  } else {
+    if (which == 0) cell_L<ND, true>(G, P, X, alpha, S);
+    else cell_Rs<ND, true>(G, P, X, alpha, S);
+  }
 #pragma unroll
   for (int v = 0; v < 2 + ND; ++v) {
     double x = in[v * G.N + lin];
@@ -554,6 +526,20 @@ static dim3 tile_grid(const Grid& G) {
   int b = 1;
   for (int d = 0; d < ND; ++d) b *= (G.n[d] + tile_n<ND>(d) - 1) / tile_n<ND>(d);
   return dim3(b);
+}
+
+template <bool RAD>
+static void launch_resid_k(const Grid& G, const ResidArgs& a, int mode, int fam, double bytes, dim3 gr,
+                           dim3 bl, hipStream_t s) {
+  if (G.nd == 2) {
+    if (mode == 0) launch_k(fam, bytes, k_resid_value<2, RAD>, gr, bl, 0, s, G, a);
+    else if (mode == 1) launch_k(fam, bytes, k_resid_tangent<2, RAD>, gr, bl, 0, s, G, a);
+    else launch_k(fam, bytes, k_resid_fd<2, RAD>, gr, bl, 0, s, G, a);
+  } else {
+    if (mode == 0) launch_k(fam, bytes, k_resid_value<3, RAD>, gr, bl, 0, s, G, a);
+    else if (mode == 1) launch_k(fam, bytes, k_resid_tangent<3, RAD>, gr, bl, 0, s, G, a);
+    else launch_k(fam, bytes, k_resid_fd<3, RAD>, gr, bl, 0, s, G, a);
+  }
 }
 
 void launch_resid(const Grid& G, const ResidArgs& a, int mode, hipStream_t s) {
@@ -572,15 +558,8 @@ void launch_resid(const Grid& G, const ResidArgs& a, int mode, hipStream_t s) {
     fam = KF_RESID_FD;
     bytes = nvN * 4;
   }
-  if (G.nd == 2) {
-    if (mode == 0) launch_k(fam, bytes, k_resid_value<2>, gr, bl, 0, s, G, a);
-    else if (mode == 1) launch_k(fam, bytes, k_resid_tangent<2>, gr, bl, 0, s, G, a);
-    else launch_k(fam, bytes, k_resid_fd<2>, gr, bl, 0, s, G, a);
-  } else {
-    if (mode == 0) launch_k(fam, bytes, k_resid_value<3>, gr, bl, 0, s, G, a);
-    else if (mode == 1) launch_k(fam, bytes, k_resid_tangent<3>, gr, bl, 0, s, G, a);
-    else launch_k(fam, bytes, k_resid_fd<3>, gr, bl, 0, s, G, a);
-  }
+  if (G.a_rad == 0.0) launch_resid_k<false>(G, a, mode, fam, bytes, gr, bl, s);
+  else launch_resid_k<true>(G, a, mode, fam, bytes, gr, bl, s);
 }
 
 void launch_scale_LR(const Grid& G, const double* X, double alpha, int which, const double* in,

@@ -160,6 +160,7 @@ Grid make_grid(const jfnk_problem& p) {
   G.chi_tref_inv = 1.0 / p.chi_tref;
   G.chi_exp = p.chi_exp;
   G.theta = p.theta;
+  G.a_rad = p.a_rad;
   return G;
 }
 
@@ -180,6 +181,7 @@ void validate(const jfnk_problem* p, const jfnk_opts* o) {
   if (p->chi_model != JFNK_CHI_NONE && !(p->chi0 >= 0.0)) throw InvErr("chi0 must be >= 0");
   if (p->chi_model == JFNK_CHI_POWER && !(p->chi_tref > 0.0)) throw InvErr("chi_tref must be > 0");
   if (!(p->theta > 0.0 && p->theta <= 1.0)) throw InvErr("theta must be in (0, 1]");
+  if (!(p->a_rad >= 0.0 && p->a_rad < HUGE_VAL)) throw InvErr("a_rad must be finite and >= 0");
   if (o->gmres_m < 1 || o->gmres_m > kMaxK - 2) throw InvErr("gmres_m out of range");
   if (o->gmres_maxit < 1) throw InvErr("gmres_maxit must be >= 1");
   if (o->newton_max < 1 || o->newton_min < 1) throw InvErr("newton_max/newton_min must be >= 1");
@@ -529,7 +531,7 @@ void precond_T(jfnk_ctx* c, const double* X, const double* v, int scaled, double
   const double* t = nullptr;
   if (thermal) {
     ell_solve(c, 1, c->rhs_T, c->dT);
-    launch_pbpT_mid(G, tau, c->dT, c->rhs_p, s);
+    launch_pbpT_mid(G, X, tau, c->dT, c->rhs_p, s);
     t = c->dT;
   }
   ell_solve(c, 0, c->rhs_p, c->dp);
@@ -1007,6 +1009,19 @@ int jfnk_precond_apply(jfnk_ctx* c, const double* X, const double* r, double* z)
   c->cg_its = 0;
   if (c->opts.precond != JFNK_PC_NONE) ell_setup(c, X, si_dt(c));
   precond(c, X, r, 0, z);
+  sync(c);
+  return JFNK_OK;
+  ABI_END(c)
+}
+
+int jfnk_precond_apply_transpose(jfnk_ctx* c, const double* X, const double* w, double* z) {
+  if (!c) return JFNK_E_INVALID;
+  ABI_BEGIN
+  if (!X || !w || !z) throw InvErr("null array");
+  if (!c->have_state) throw InvErr("jfnk_set_state_n must be called first");
+  c->cg_its = 0;
+  if (c->opts.precond != JFNK_PC_NONE) ell_setup(c, X, si_dt(c));
+  precond_T(c, X, w, 0, z);
   sync(c);
   return JFNK_OK;
   ABI_END(c)

@@ -117,9 +117,6 @@ struct Acc {
   __device__ __forceinline__ double rho(const int* c) const { return x(0, c); }
   __device__ __forceinline__ double e(const int* c) const { return x(1, c); }
   __device__ __forceinline__ double u(int d, const int* c) const { return x(2 + d, c); }
-  __device__ __forceinline__ double p(const int* c) const {
-    return (G.gamma - 1.0) * rho(c) * e(c);
-  }
 };
 
 #define SH(dst, src, d, k)           \
@@ -268,7 +265,7 @@ __global__ void __launch_bounds__(kBlock) k_vjp_stageA(Grid G, PadGrid PG, const
 }
 
 // ---- stage B: adjoint of every padded input ----------------------------------------------
-template <int ND, class AC>
+template <int ND, bool RAD, class AC>
 __device__ __forceinline__ void vjp_stageB_cell(const Grid& G, const PadGrid& PG, const AC& A, const int* c, int pl,
                                                 const double* mf, const double* fbar, double* xbar) {
   auto MF = [&](int d, const int* q) { return mf[(size_t)d * PG.PN + pad_index<ND>(PG, q)]; };
@@ -305,7 +302,15 @@ __device__ __forceinline__ void vjp_stageB_cell(const Grid& G, const PadGrid& PG
       rb += 0.5 * G.g[d] * (A.W(2 + d, c) + A.W(2 + d, cp));
     }
   }
-  if (pbar != 0.0) {
+  // T(rho, e) at c: its derivatives carry the conduction adjoint to rho and e of c
+  double dTdr_c = 0.0, dTde_c = gm1;
+  if constexpr (RAD) {
+    const Thermo th = thermo<true>(G, A.rho(c), A.e(c));
+    dTdr_c = th.dTdr;
+    dTde_c = th.dTde;
+    rb += pbar * th.dpdr;
+    eb += pbar * th.dpde;
+  } else if (pbar != 0.0) {
     rb += pbar * gm1 * A.e(c);
     eb += pbar * gm1 * A.rho(c);
   }
@@ -352,7 +357,7 @@ __device__ __forceinline__ void vjp_stageB_cell(const Grid& G, const PadGrid& PG
         SH(fm, f, d, -1);
         double qb = (A.W(1, fm) - A.W(1, f)) * ih;
         if (qb == 0.0) continue;
-        double Tm = gm1 * A.e(fm), T0 = gm1 * A.e(f);
+        double Tm = eos_T<RAD>(G, A.rho(fm), A.e(fm)), T0 = eos_T<RAD>(G, A.rho(f), A.e(f));
         double chm, ch0, dchm, dch0;
         if (G.chi_model == 1) {
           chm = ch0 = G.chi0;
@@ -368,7 +373,8 @@ __device__ __forceinline__ void vjp_stageB_cell(const Grid& G, const PadGrid& PG
         double dT = T0 - Tm;
         // q = chif (T0 - Tm) ih; c is the face's cell (k = 0: T0) or its lower cell (k = 1: Tm)
         double dq_dT = (k == 0) ? (0.5 * dch0 * dT + chif) * ih : (0.5 * dchm * dT - chif) * ih;
-        eb += qb * dq_dT * gm1;
+        eb += qb * dq_dT * dTde_c;
+        if constexpr (RAD) rb += qb * dq_dT * dTdr_c;
       }
     }
     // u_d at face c: its own mass flux f_d[c] = u_d rho*
@@ -386,8 +392,8 @@ __device__ __forceinline__ void vjp_stageB_cell(const Grid& G, const PadGrid& PG
     {
       SH(cm, c, d, -1);
       double a0 = A.W(1, c), a1 = A.W(1, cm);
-      if (a0 != 0.0) ub[d] += a0 * A.p(c) * ih;
-      if (a1 != 0.0) ub[d] -= a1 * A.p(cm) * ih;
+      if (a0 != 0.0) ub[d] += a0 * eos_p<RAD>(G, A.rho(c), A.e(c)) * ih;
+      if (a1 != 0.0) ub[d] -= a1 * eos_p<RAD>(G, A.rho(cm), A.e(cm)) * ih;
     }
     // Phi_dd at centres cc = c - k e_d (k = -1..2): u* reads u_d[cc-1..cc+2]
 #pragma unroll
@@ -431,15 +437,15 @@ __device__ __forceinline__ void vjp_stageB_cell(const Grid& G, const PadGrid& PG
   for (int d = 0; d < ND; ++d) xbar[(size_t)(2 + d) * PG.PN + pl] = ub[d];
 }
 
-template <int ND>
+template <int ND, bool RAD>
 __global__ void __launch_bounds__(kBlock) k_vjp_stageB(Grid G, PadGrid PG, const double* X, const double* w,
                                                        double cR, const double* mf, const double* fbar,
                                                        double* xbar) {
   int c[3], pl;
   bool in;
   if (!vtile_cell<ND>(G, PG, c, &pl, &in)) return;
-  if (in) vjp_stageB_cell<ND>(G, PG, Acc<ND, true>(G, X, w, cR), c, pl, mf, fbar, xbar);
-  else vjp_stageB_cell<ND>(G, PG, Acc<ND, false>(G, X, w, cR), c, pl, mf, fbar, xbar);
+  if (in) vjp_stageB_cell<ND, RAD>(G, PG, Acc<ND, true>(G, X, w, cR), c, pl, mf, fbar, xbar);
+  else vjp_stageB_cell<ND, RAD>(G, PG, Acc<ND, false>(G, X, w, cR), c, pl, mf, fbar, xbar);
 }
 
 // ---- fold: interior adjoint = U part + sum of padded copies ------------------------------
@@ -520,16 +526,15 @@ __global__ void __launch_bounds__(kBlock) k_vjp_fold(Grid G, PadGrid PG, const d
     res[var] += acc;
   }
   if (scaleR) {
-    const double k = G.gamma * (G.gamma - 1.0);
     const double e0 = X[N + lin];
-    const double cs0 = sqrt(k * e0);
+    const double cs0 = sound_speed_rt(G, X[lin], e0);
     res[0] *= X[lin];
     res[1] *= e0;
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
       double s;
       int im = gidx<ND>(G, P, 1, shift(off0(), d, -1), &s);
-      double csf = 0.5 * (sqrt(k * X[N + im]) + cs0);
+      double csf = 0.5 * (sound_speed_rt(G, X[im], X[N + im]) + cs0);
       res[2 + d] *= fmax(fabs(X[(2 + d) * N + lin]), alpha2 * csf);
     }
   }
@@ -552,10 +557,9 @@ struct CellT {
 template <int ND>
 __device__ __forceinline__ double rscale_u(const Grid& G, const Pos& P, const double* X, int d,
                                            double alpha2) {
-  const double k = G.gamma * (G.gamma - 1.0);
   double s;
   int im = gidx<ND>(G, P, 1, shift(off0(), d, -1), &s);
-  double csf = 0.5 * (sqrt(k * X[G.N + im]) + sqrt(k * X[G.N + P.lin]));
+  double csf = 0.5 * (sound_speed_rt(G, X[im], X[G.N + im]) + sound_speed_rt(G, X[P.lin], X[G.N + P.lin]));
   return fmax(fabs(X[(2 + d) * G.N + P.lin]), alpha2 * csf);
 }
 
@@ -613,22 +617,25 @@ __global__ void __launch_bounds__(kBlock) k_pbpT_in(Grid G, const double* X, con
     wr /= rho;
     we /= e;
   }
-  double dpdr = gm1 * e, dpde = gm1 * rho;
+  const Thermo th = thermo_rt(G, rho, e);
+  const double dpdr = th.dpdr, dpde = th.dpde;
   double dp_b = wr / dpdr;
   double de_b = we - dpde / dpdr * wr;
   dp_b -= dt * gradT<ND>(G, P, X, v, scaled, alpha2);
   if (!thermal) {
-    rhs_p[lin] = dp_b + de_b / (G.gamma * rho);
+    rhs_p[lin] = dp_b + de_b / (th.G1 * rho);
   } else {
     rhs_p[lin] = dp_b;  // completed by k_pbpT_mid after the thermal solve
-    rhs_T[lin] = de_b / gm1;
+    rhs_T[lin] = G.a_rad == 0.0 ? de_b / gm1 : th.cv * de_b;  // c_v de_b
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_pbpT_mid(Grid G, double dt, const double* t, double* rhs_p) {
+__global__ void __launch_bounds__(kBlock) k_pbpT_mid(Grid G, const double* X, double dt, const double* t,
+                                                     double* rhs_p) {
   int lin = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (lin >= G.N) return;
-  rhs_p[lin] += t[lin] / (G.gamma * dt);
+  const double g1 = G.a_rad == 0.0 ? G.gamma : thermo<true>(G, X[lin], X[G.N + lin]).G1;
+  rhs_p[lin] += t[lin] / (g1 * dt);
 }
 
 template <int ND>
@@ -638,7 +645,6 @@ __global__ void __launch_bounds__(kBlock) k_pbpT_out(Grid G, const double* X, co
   int lin = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (lin >= G.N) return;
   Pos P = make_pos<ND>(G, lin);
-  const double gm1 = G.gamma - 1.0;
   const int N = G.N;
   double rho = X[lin], e = X[N + lin];
   double wr = v[lin], we = v[N + lin];
@@ -646,18 +652,18 @@ __global__ void __launch_bounds__(kBlock) k_pbpT_out(Grid G, const double* X, co
     wr /= rho;
     we /= e;
   }
-  double dpdr = gm1 * e, dpde = gm1 * rho;
+  const Thermo th = thermo_rt(G, rho, e);
+  const double dpdr = th.dpdr, dpde = th.dpde;
   double de_b = we - dpde / dpdr * wr;
-  double p = gm1 * rho * e;
   double Fe_b, Fp_b;
   if (t) {
     Fe_b = rho * t[lin];
-    Fp_b = -t[lin] / G.gamma;
+    Fp_b = -t[lin] / th.G1;
   } else {
     Fe_b = dt * de_b;
-    Fp_b = -dt * de_b / (G.gamma * rho);
+    Fp_b = -dt * de_b / (th.G1 * rho);
   }
-  Fp_b += sp[lin] / (G.gamma * p);
+  Fp_b += sp[lin] / (th.G1 * th.p);
   double r0 = (dpdr - (e / rho) * dpde) * Fp_b - (e / rho) * Fe_b;
   double r1 = (dpde / rho) * Fp_b + Fe_b / rho;
 #pragma unroll
@@ -692,9 +698,10 @@ void launch_pbpT_in(const Grid& G, const double* X, const double* v, int scaled,
   if (G.nd == 2) k_pbpT_in<2><<<gr, kBlock, 0, s>>>(G, X, v, scaled, alpha2, dt, thermal, rhs_p, rhs_T);
   else k_pbpT_in<3><<<gr, kBlock, 0, s>>>(G, X, v, scaled, alpha2, dt, thermal, rhs_p, rhs_T);
 }
-void launch_pbpT_mid(const Grid& G, double dt, const double* t, double* rhs_p, hipStream_t s) {
+void launch_pbpT_mid(const Grid& G, const double* X, double dt, const double* t, double* rhs_p,
+                     hipStream_t s) {
   dim3 gr((G.N + kBlock - 1) / kBlock);
-  k_pbpT_mid<<<gr, kBlock, 0, s>>>(G, dt, t, rhs_p);
+  k_pbpT_mid<<<gr, kBlock, 0, s>>>(G, X, dt, t, rhs_p);
 }
 void launch_pbpT_out(const Grid& G, const double* X, const double* v, int scaled, double alpha2,
                      double dt, const double* sp, const double* t, int schur, double zscale, double* z,
@@ -732,8 +739,13 @@ void launch_vjp(const Grid& G, const double* X, const double* w, double cU, doub
   {
     const double by = 8.0 * (2 * nv * G.N + (2 * G.nd + nv) * (double)PG.PN);
     const double* fb = fbar;
-    if (G.nd == 2) launch_k(KF_VJP_B, by, k_vjp_stageB<2>, gt, bl, 0, s, G, PG, X, w, cR, mfc, fb, xbar);
-    else launch_k(KF_VJP_B, by, k_vjp_stageB<3>, gt, bl, 0, s, G, PG, X, w, cR, mfc, fb, xbar);
+    const bool rad = G.a_rad != 0.0;
+    if (G.nd == 2)
+      launch_k(KF_VJP_B, by, rad ? k_vjp_stageB<2, true> : k_vjp_stageB<2, false>, gt, bl, 0, s, G, PG, X, w,
+               cR, mfc, fb, xbar);
+    else
+      launch_k(KF_VJP_B, by, rad ? k_vjp_stageB<3, true> : k_vjp_stageB<3, false>, gt, bl, 0, s, G, PG, X, w,
+               cR, mfc, fb, xbar);
   }
   {
     const double by = 8.0 * (3 * nv * G.N + nv * (double)PG.PN);
