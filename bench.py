@@ -34,7 +34,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "rad"])
     ap.add_argument("--jv", default=None, choices=["fd", "exact"])
     ap.add_argument("--ell", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--kernel-reps", type=int, default=20)

@@ -350,4 +350,5 @@ CONFIGS = {
     "c3": taylor_green_3d,
     "c4": stratified_2d_kappa,
     "c5": convective_box_3d,
+    "rad": radiative_2d,
 }
