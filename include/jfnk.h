@@ -160,6 +160,16 @@ int jfnk_precond_apply_transpose(jfnk_ctx* ctx, const double* X, const double* w
  * JFNK_E_NEWTON_NOCONV otherwise (X then holds the last iterate).  stats may be NULL.   */
 int jfnk_implicit_step(jfnk_ctx* ctx, double* X, double dt, jfnk_step_stats* stats);
 
+/* One step of the semi-implicit scheme used as a time stepper (Sect. 3.6): X holds X^n on
+ * entry and X^{n+1} = X^n - M^-1 F(X^n) on return, F(X^n) = -R(X^n), M^-1 the physics-based
+ * preconditioner of opts.precond (SOUND or SOUND_THERMAL; NONE is an error) frozen at X^n
+ * with elliptic solves to opts.cg_eta.  opts.pc_schur = 1 gives the scheme derived in
+ * Sect. 3.3 (Laplacian on p^{n+1}: implicit acoustics); 0 the delta-form J~_V applied to
+ * (dV/dU) F.  Linear (no Newton), first order in time for theta = 1, stable only while the
+ * advective CFL number stays small (the advection terms are explicit).  stats (may be NULL):
+ * f0_norm = ||F(X^n)||_2, last_dx_norm = ||R^-1 dX||_inf, cg_its, converged = 1.         */
+int jfnk_si_step(jfnk_ctx* ctx, double* X, double dt, jfnk_step_stats* stats);
+
 /* Adjoint of one implicit step: given gbar_n1 = dL/dX^{n+1} at the converged X^{n+1} = Xn1
  * of the step from Xn with dt, solve J^T lam = gbar_n1 (FGMRES(m) on the scaled transposed
  * system R J^T L^-1, right preconditioner L M^-T R^-1 with the transposed physics-based

@@ -196,6 +196,12 @@ class Context:
         self._check(rc, allow)
         return st.as_dict()
 
+    def si_step(self, X, dt):
+        """One semi-implicit step in place (X^n -> X^{n+1}); returns the step statistics."""
+        st = N.StepStats()
+        self._check(self._lib.jfnk_si_step(self._h, _ptr(self._vec(X, "X")), float(dt), C.byref(st)))
+        return st.as_dict()
+
     def adjoint_step(self, Xn1, Xn, dt, gbar_n1, out=None):
         out = self._new() if out is None else self._vec(out, "out")
         st = N.StepStats()

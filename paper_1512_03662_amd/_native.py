@@ -98,6 +98,7 @@ SIGNATURES = {
     "jfnk_precond_apply": (C.c_int, [_P, _P, _P, _P]),
     "jfnk_precond_apply_transpose": (C.c_int, [_P, _P, _P, _P]),
     "jfnk_implicit_step": (C.c_int, [_P, _P, _D, C.POINTER(StepStats)]),
+    "jfnk_si_step": (C.c_int, [_P, _P, _D, C.POINTER(StepStats)]),
     "jfnk_adjoint_step": (C.c_int, [_P, _P, _P, _D, _P, _P, C.POINTER(StepStats)]),
     "jfnk_cfl_dt": (C.c_double, [_P, _P, _D]),
     "jfnk_probe_enable": (C.c_int, [C.c_int32]),

@@ -740,6 +740,43 @@ int implicit_step(jfnk_ctx* c, double* X, double dt, jfnk_step_stats* st) {
   return status;
 }
 
+// One step of the semi-implicit scheme used as a time stepper (Sect. 3.6):
+// X^{n+1} = X^n - M^-1 F(X^n) with F(X^n) = -R(X^n), M^-1 the physics-based preconditioner
+// frozen at X^n (opts.pc_schur = 1: the scheme of Sect. 3.3 with the Laplacian on p^{n+1};
+// 0: the delta-form J~_V with F~_V = (dV/dU) F_U).
+int si_step(jfnk_ctx* c, double* X, double dt, jfnk_step_stats* st) {
+  const jfnk_opts& o = c->opts;
+  const Grid& G = c->G;
+  hipStream_t s = c->stream;
+  if (o.precond == JFNK_PC_NONE) throw InvErr("the semi-implicit step needs a physics-based preconditioner");
+  jfnk_step_stats S{};
+  S.dt = dt;
+  set_state(c, X, dt);
+  c->cg_its = 0;
+  ResidArgs a;
+  a.X = X;
+  a.B = c->bn;
+  a.out = c->W;
+  a.cU = 1.0 / dt;
+  a.cR = -c->prob.theta;
+  launch_resid(G, a, 0, s);
+  launch_dot<double>(c->n, c->W, c->W, c->scal + S_FN2, c->red, s);
+  pull(c, S_FN2, 1);
+  S.f0_norm = S.f_norm = std::sqrt(c->hscal[S_FN2]);
+  if (!std::isfinite(S.f0_norm)) throw FiniteErr("non-finite residual norm");
+  ell_setup(c, X, si_dt(c));
+  precond(c, X, c->W, 0, c->dX);
+  launch_scaled_maxabs(G, X, c->dX, o.alpha2, c->scal + S_DXMAX, c->red, s);
+  launch_axpy(c->n, -1.0, c->dX, X, s);
+  pull(c, S_DXMAX, 1);
+  S.last_dx_norm = c->hscal[S_DXMAX];
+  if (!std::isfinite(S.last_dx_norm)) throw FiniteErr("non-finite semi-implicit update");
+  S.cg_its = c->cg_its;
+  S.converged = 1;
+  if (st) *st = S;
+  return JFNK_OK;
+}
+
 // Adjoint of one implicit step: lam solves J^T lam = gbar at X^{n+1}; returns
 // dL/dX^n = (dU/dX|_{X^n})^T lam / dt + (1 - theta) (dR/dX|_{X^n})^T lam.
 struct AdjGuard {
@@ -1024,6 +1061,16 @@ int jfnk_precond_apply_transpose(jfnk_ctx* c, const double* X, const double* w, 
   precond_T(c, X, w, 0, z);
   sync(c);
   return JFNK_OK;
+  ABI_END(c)
+}
+
+int jfnk_si_step(jfnk_ctx* c, double* X, double dt, jfnk_step_stats* st) {
+  if (!c) return JFNK_E_INVALID;
+  ABI_BEGIN
+  if (!X) throw InvErr("null X");
+  int r = si_step(c, X, dt, st);
+  sync(c);
+  return r;
   ABI_END(c)
 }
 

@@ -2,6 +2,7 @@
 
     python -m paper_1512_03662_amd.studies tgv [--steps 10]
     python -m paper_1512_03662_amd.studies vortex [--steps 5]
+    python -m paper_1512_03662_amd.studies si_vortex [--schemes si_schur,jfnk_be]
 
 tgv:    the 3D Taylor-Green vortex at 64^3 for the Mach numbers and hydrodynamic CFL numbers
         of the paper's timing table (Results section, Taylor-Green vortex): average Newton
@@ -11,6 +12,10 @@ vortex: the 2D isentropic vortex at 64^2 (T_inf = 1, 1e2, 1e6, 1e10, i.e. Mach 1
         over a range of advective CFL numbers, with and without the physics-based
         preconditioner: GMRES iterations per Newton iteration (the paper shows these as a
         figure; no numbers are printed there, so only the trend can be compared).
+si_vortex: the semi-implicit stepper's temporal convergence on the same vortex at 64^2
+        advected to t = 0.4 (Sect. 3.7): L1, L2 and Linf errors of u against the translated
+        initial profile for CFL_adv 0.01 .. 3 and the four Mach numbers, beside the implicit
+        JFNK step (backward Euler and Crank-Nicolson) on the same cases.
 
 The paper's runs used its own code (MUSIC with Trilinos), Newton tolerance 1e-6 and an
 algebraic-multigrid preconditioned parabolic solver; here Newton tolerance 1e-8, FGMRES(30)
@@ -115,12 +120,83 @@ def vortex(args):
                 print(json.dumps(r), flush=True)
 
 
+SI_SCHEMES = {
+    # name: (stepper, Context options)
+    "si_schur": ("si", dict(precond="sound", pc_schur=1)),
+    "si_deltaform": ("si", dict(precond="sound", pc_schur=0)),
+    "jfnk_be": ("jfnk", dict(precond="sound", jv_mode="fd")),
+    "jfnk_cn": ("jfnk", dict(precond="sound", jv_mode="fd", theta=0.5)),
+}
+
+
+def si_vortex(args):
+    """Temporal convergence of the isentropic vortex advected to t = 0.4 (Sect. 3.7): errors of
+    u against the translated initial profile for the semi-implicit stepper (both readings of
+    its system) and for the implicit JFNK step (backward Euler, Crank-Nicolson)."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    import paper_1512_03662_amd as J
+    dev = torch.device("cuda:0")
+    n, t_end = 64, args.t_end
+    u_ex = W.isentropic_vortex_u_exact(n=n, t=t_end)
+    schemes = args.schemes.split(",")
+    for t_inf in (1.0, 1e2, 1e6, 1e10):
+        w = W.isentropic_vortex_2d(n=n, t_inf=t_inf)
+        mach = 0.75 / (2 * math.pi * math.sqrt(1.4 * t_inf))
+        h = w["problem"]["dx"][0]
+        for name in schemes:
+            kind, kw = SI_SCHEMES[name]
+            kw = dict(kw)
+            pd = dict(w["problem"], theta=kw.pop("theta", 1.0))
+            cfls = tuple(float(c) for c in args.cfls.split(","))
+            if kind == "jfnk":
+                cfls = tuple(c for c in cfls if c >= 0.05)  # the small steps only repeat the SI's plateau
+            for cfl_adv in cfls:
+                steps = max(1, int(math.ceil(t_end / (cfl_adv * h) - 1e-9)))
+                dt = t_end / steps
+                ctx = J.Context(pd, gmres_maxit=300, **kw)
+                X = torch.tensor(w["X0"], dtype=torch.float64, device=dev)
+                err = None
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                try:
+                    for _ in range(steps):
+                        if kind == "si":
+                            ctx.si_step(X, dt)
+                        else:
+                            ctx.implicit_step(X, dt)
+                except Exception as e:  # an unstable or failed run is reported, not hidden
+                    err = str(e)
+                torch.cuda.synchronize()
+                sec = time.perf_counter() - t0
+                ctx.close()
+                r = {"study": f"isentropic_vortex_2d_64^2_t{t_end:g}", "scheme": name, "t_inf": t_inf,
+                     "mach": mach, "cfl_adv": dt / h, "steps": steps, "ms_per_step": 1e3 * sec / steps,
+                     "error": err}
+                if err is None:
+                    d = X[2].cpu().numpy() - u_ex
+                    if np.all(np.isfinite(d)):
+                        r.update(L1=float(np.mean(np.abs(d))), L2=float(np.sqrt(np.mean(d * d))),
+                                 Linf=float(np.max(np.abs(d))))
+                    else:
+                        r["error"] = "non-finite state"
+                print(json.dumps(r), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["tgv", "vortex"])
+    ap.add_argument("study", choices=["tgv", "vortex", "si_vortex"])
     ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--schemes", default=",".join(SI_SCHEMES),
+                    help="si_vortex: comma-separated subset of " + ",".join(SI_SCHEMES))
+    ap.add_argument("--t-end", type=float, default=0.4,
+                    help="si_vortex: final time (0.4 in the paper; 8 is one domain crossing)")
+    ap.add_argument("--cfls", default="0.01,0.02,0.05,0.1,0.2,0.4,0.8,1.6",
+                    help="si_vortex: advective CFL numbers (rounded so that t_end is reached)")
     args = ap.parse_args()
-    {"tgv": tgv, "vortex": vortex}[args.study](args)
+    {"tgv": tgv, "vortex": vortex, "si_vortex": si_vortex}[args.study](args)
 
 
 if __name__ == "__main__":
