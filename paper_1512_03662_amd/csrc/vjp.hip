@@ -9,8 +9,8 @@
 //   stage 0: the mass flux f_d on every padded face (stored, read by the next two stages);
 //   stage A: adjoint of the mass flux f_d on every padded face, from w (R_rho, the energy
 //            flux g = f e*, the momentum fluxes through their carrying mass flux);
-//   stage B: adjoint of every padded input (rho, e, u_d) gathered from the local terms that
-//            read it, re-evaluating their partial derivatives (upwind choices frozen);
+//   stage B: adjoint of every padded input (rho, e, u_d): per tile, each reconstruction term
+//            is differentiated once and its four partials reach their cells through LDS;
 //   fold:    X_bar = cU (dU/dX)^T w + sum over the padded copies of each stored value.
 // Terms whose adjoint weight is exactly zero are skipped, so only terms that the forward
 // evaluates for some interior row are evaluated, with the same (in-range) ghost accesses.
@@ -264,173 +264,301 @@ __global__ void __launch_bounds__(kBlock) k_vjp_stageA(Grid G, PadGrid PG, const
   else vjp_stageA_cell<ND>(G, PG, Acc<ND, false>(G, X, w, cR), c, pl, mf, fbar);
 }
 
-// ---- stage B: adjoint of every padded input ----------------------------------------------
-template <int ND, bool RAD, class AC>
-__device__ __forceinline__ void vjp_stageB_cell(const Grid& G, const PadGrid& PG, const AC& A, const int* c, int pl,
-                                                const double* mf, const double* fbar, double* xbar) {
-  auto MF = [&](int d, const int* q) { return mf[(size_t)d * PG.PN + pad_index<ND>(PG, q)]; };
+// ---- stage B: adjoint of every padded input, tiled -----------------------------------------
+// Every term of R that reads a field through a four-point upwind reconstruction along an axis
+// A (the mass and energy fluxes along A, the momentum fluxes carried along A) is evaluated
+// once per point of the tile's face grid along A: its four partial derivatives times the
+// term's adjoint weight go to LDS, and each cell of the tile then adds the four entries that
+// reach it (point q feeds the cells q - 2 .. q + 1 along A).  A tile of padded cells is
+// 32 x 8 (2D) or 16 x 4 x 4 (3D); its face grid along A spans [-1, T_A + 2) (tile-local) along
+// A and the tile along the other axes.  Terms local to a cell (pressure, gravity, the cell's
+// own mass flux, div u) are added by the cell's thread.  Partial derivatives are taken with
+// the upwind choices and limiter branches frozen, as in the forward.
+template <int ND>
+__host__ __device__ constexpr int bt(int d) {
+  return ND == 2 ? (d == 0 ? 32 : (d == 1 ? 8 : 1)) : (d == 0 ? 16 : 4);
+}
+template <int ND, int A>
+__host__ __device__ constexpr int bext(int i) {
+  return i >= ND ? 1 : (i == A ? bt<ND>(i) + 3 : bt<ND>(i));
+}
+template <int ND, int A>
+__host__ __device__ constexpr int bfaces() {
+  return bext<ND, A>(0) * bext<ND, A>(1) * bext<ND, A>(2);
+}
+__host__ __device__ constexpr int bmax(int a, int b) { return a > b ? a : b; }
+template <int ND>
+__host__ __device__ constexpr int bfaces_max() {
+  return ND == 2 ? bmax(bfaces<2, 0>(), bfaces<2, 1>())
+                 : bmax(bfaces<3, 0>(), bmax(bfaces<3, 1>(), bfaces<3, 2>()));
+}
+static_assert(bt<2>(0) * bt<2>(1) == kBlock && bt<3>(0) * bt<3>(1) * bt<3>(2) == kBlock,
+              "one padded cell per thread");
+
+template <int ND>
+static int btile_blocks(const PadGrid& PG) {
+  int b = 1;
+  for (int d = 0; d < 3; ++d) b *= (PG.P[d] + bt<ND>(d) - 1) / bt<ND>(d);
+  return b;
+}
+
+// o: logical coordinates of the tile's first cell; interior: every access of the tile's
+// terms (at most 5 cells beyond it) lies inside the grid, away from its walls
+template <int ND>
+struct BTile {
+  int o[3];
+  bool interior;
+};
+template <int ND>
+__device__ __forceinline__ BTile<ND> btile_setup(const Grid& G, const PadGrid& PG) {
+  int nb[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) nb[d] = (PG.P[d] + bt<ND>(d) - 1) / bt<ND>(d);
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  BTile<ND> t;
+  t.o[0] = (b % nb[0]) * bt<ND>(0) - 3;
+  t.o[1] = ((b / nb[0]) % nb[1]) * bt<ND>(1) - 3;
+  t.o[2] = (ND == 3) ? (b / (nb[0] * nb[1])) * bt<ND>(2) - 3 : 0;
+  bool in = true;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) in = in && (t.o[d] >= 6) && (t.o[d] + bt<ND>(d) + 6 <= G.n[d]);
+  t.interior = in;
+  return t;
+}
+
+// one scatter pass along A with NS independent term sets: coef(f, g) fills g[s * 4 + j],
+// the contribution of face point f (logical) to cell f + (j - 2) e_A of set s; acc[s] of the
+// thread's own cell l receives the sum of what reaches it
+template <int ND, int A, int NS, class CF>
+__device__ __forceinline__ void bscatter(const BTile<ND>& T, const int* l, bool own, double* sC, const CF& coef,
+                                         double* acc) {
+  constexpr int E0 = bext<ND, A>(0), E1 = bext<ND, A>(1), E2 = bext<ND, A>(2);
+  constexpr int NF = E0 * E1 * E2;
+  constexpr int M = bfaces_max<ND>();
+  for (int p = threadIdx.x; p < NF; p += kBlock) {
+    int f[3] = {p % E0, (p / E0) % E1, p / (E0 * E1)};
+    f[A] -= 1;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) f[d] += T.o[d];
+    double g[NS * 4];
+    coef(f, g);
+#pragma unroll
+    for (int i = 0; i < NS * 4; ++i) sC[i * M + p] = g[i];
+  }
+  __syncthreads();
+  if (own) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      int q[3] = {l[0], l[1], l[2]};
+      q[A] += 3 - j;  // face l + (2 - j) e_A, shifted by the face grid's origin -1
+      const int p = q[0] + q[1] * E0 + q[2] * E0 * E1;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) acc[s] += sC[(s * 4 + j) * M + p];
+    }
+  }
+  __syncthreads();
+}
+
+// the passes along axis A: mass and energy fluxes (to rho, e), Phi_AA (to u_A), and Phi_dA
+// for d != A (u_d carried along A, to u_d)
+template <int ND, int A, bool RAD, class AC>
+__device__ __forceinline__ void vjp_axisB(const Grid& G, const PadGrid& PG, const AC& Ac, const BTile<ND>& T,
+                                          const int* l, bool own, const double* mf, const double* fbar,
+                                          double* sC, double& rb, double& eb, double* ub) {
+  const double ih = G.idx[A];
   const double gm1 = G.gamma - 1.0;
-  double rb = 0.0, eb = 0.0, ub[3] = {0.0, 0.0, 0.0};
-  auto padded = [&](const int* q) -> int {  // padded index or -1 outside the padded grid
+  auto MF = [&](int d, const int* q) { return mf[(size_t)d * PG.PN + pad_index<ND>(PG, q)]; };
+  auto padded = [&](const int* q) -> int {
     int idx = 0;
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
-      int pq = q[d] + 3;
+      const int pq = q[d] + 3;
       if (pq < 0 || pq >= PG.P[d]) return -1;
       idx += pq * PG.pstride[d];
     }
     return idx;
   };
-  double pbar = 0.0;
-  // pressure: p in -p div u (row E at c) and in the momentum pressure gradients
   {
-    double WE = A.W(1, c);
-    if (WE != 0.0) {
-      double D = 0.0;
+    auto coef = [&](const int* f, double* g) {
 #pragma unroll
-      for (int d = 0; d < ND; ++d) {
-        SH(cp, c, d, 1);
-        D += (A.u(d, cp) - A.u(d, c)) * G.idx[d];
+      for (int i = 0; i < 8; ++i) g[i] = 0.0;
+      SH(m2, f, A, -2);
+      SH(m1, f, A, -1);
+      SH(p1, f, A, 1);
+      const double wv = Ac.u(A, f);
+      double gg[4];
+      // mass flux f_A = u_A rho*: rho at f - 2 .. f + 1
+      const int pf = padded(f);
+      const double fb = (pf >= 0) ? fbar[(size_t)A * PG.PN + pf] : 0.0;
+      if (fb != 0.0) {
+        upwind_grad(Ac.rho(m2), Ac.rho(m1), Ac.rho(f), Ac.rho(p1), wv, gg);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) g[j] = fb * wv * gg[j];
       }
-      pbar -= WE * D;
-    }
+      // energy flux g_A = f_A e*: e at f - 2 .. f + 1
+      const double gb = (Ac.W(1, f) - Ac.W(1, m1)) * ih;
+      if (gb != 0.0) {
+        const double fl = MF(A, f);
+        upwind_grad(Ac.e(m2), Ac.e(m1), Ac.e(f), Ac.e(p1), wv, gg);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) g[4 + j] = gb * fl * gg[j];
+      }
+      // conduction q = chi_f (T0 - Tm) ih with Tm at f - e_A, T0 at f (not on wall faces)
+      if (G.chi_model != 0 && !(G.bc[A] == 1 && (f[A] == 0 || f[A] == G.n[A]))) {
+        const double qb = (Ac.W(1, m1) - Ac.W(1, f)) * ih;
+        if (qb != 0.0) {
+          const double Tm = eos_T<RAD>(G, Ac.rho(m1), Ac.e(m1)), T0 = eos_T<RAD>(G, Ac.rho(f), Ac.e(f));
+          double chm, ch0, dchm, dch0;
+          if (G.chi_model == 1) {
+            chm = ch0 = G.chi0;
+            dchm = dch0 = 0.0;
+          } else {
+            const double pe = G.chi_exp;
+            chm = G.chi0 * powr(Tm * G.chi_tref_inv, pe);
+            ch0 = G.chi0 * powr(T0 * G.chi_tref_inv, pe);
+            dchm = pe * chm / Tm;
+            dch0 = pe * ch0 / T0;
+          }
+          const double chif = 0.5 * (chm + ch0);
+          const double dT = T0 - Tm;
+          const double qm = qb * (0.5 * dchm * dT - chif) * ih;  // times dT/dX of cell f - e_A
+          const double q0 = qb * (0.5 * dch0 * dT + chif) * ih;  // times dT/dX of cell f
+          if constexpr (RAD) {
+            const Thermo tm = thermo<true>(G, Ac.rho(m1), Ac.e(m1));
+            const Thermo t0 = thermo<true>(G, Ac.rho(f), Ac.e(f));
+            g[1] += qm * tm.dTdr;
+            g[2] += q0 * t0.dTdr;
+            g[5] += qm * tm.dTde;
+            g[6] += q0 * t0.dTde;
+          } else {
+            g[5] += qm * gm1;
+            g[6] += q0 * gm1;
+          }
+        }
+      }
+    };
+    double acc[2] = {0.0, 0.0};
+    bscatter<ND, A, 2>(T, l, own, sC, coef, acc);
+    rb += acc[0];
+    eb += acc[1];
+  }
+  // Phi_AA: point q stands for the centre between faces q - e_A and q; u_A at q - 2 .. q + 1
+  {
+    auto coef = [&](const int* q, double* g) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) g[j] = 0.0;
+      SH(qm, q, A, -1);
+      const double Pb = (Ac.W(2 + A, q) - Ac.W(2 + A, qm)) * ih;
+      if (Pb != 0.0) {
+        const double m = 0.5 * (MF(A, qm) + MF(A, q));
+        SH(qm2, q, A, -2);
+        SH(qp1, q, A, 1);
+        double gg[4];
+        upwind_grad(Ac.u(A, qm2), Ac.u(A, qm), Ac.u(A, q), Ac.u(A, qp1), m, gg);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) g[j] = Pb * m * gg[j];
+      }
+    };
+    double acc[1] = {0.0};
+    bscatter<ND, A, 1>(T, l, own, sC, coef, acc);
+    ub[A] += acc[0];
+  }
+  // Phi_dA, d != A: the edge at point q carries u_d along A with the mass flux mean of f_A at
+  // q - e_d and q; u_d at q - 2 .. q + 1 along A
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    if (d == A) continue;
+    auto coef = [&](const int* q, double* g) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) g[j] = 0.0;
+      SH(qm, q, A, -1);
+      const double Pb = (Ac.W(2 + d, q) - Ac.W(2 + d, qm)) * ih;
+      if (Pb != 0.0) {
+        SH(qd, q, d, -1);
+        const double m = 0.5 * (MF(A, qd) + MF(A, q));
+        SH(qm2, q, A, -2);
+        SH(qp1, q, A, 1);
+        double gg[4];
+        upwind_grad(Ac.u(d, qm2), Ac.u(d, qm), Ac.u(d, q), Ac.u(d, qp1), m, gg);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) g[j] = Pb * m * gg[j];
+      }
+    };
+    double acc[1] = {0.0};
+    bscatter<ND, A, 1>(T, l, own, sC, coef, acc);
+    ub[d] += acc[0];
+  }
+}
+
+// terms local to the padded cell c: pressure in -p div u and in the momentum gradients,
+// gravity, the cell's own mass flux (u_d times rho*), u_d in div u
+template <int ND, bool RAD, class AC>
+__device__ __forceinline__ void vjp_localB(const Grid& G, const PadGrid& PG, const AC& Ac, const int* c, int pl,
+                                           const double* fbar, double& rb, double& eb, double* ub) {
+  const double gm1 = G.gamma - 1.0;
+  double pbar = 0.0;
+  const double WE = Ac.W(1, c);
+  if (WE != 0.0) {
+    double D = 0.0;
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
       SH(cp, c, d, 1);
-      pbar += (A.W(2 + d, cp) - A.W(2 + d, c)) * G.idx[d];
-      // gravity: rho_f g_d on the faces c and c + e_d
-      rb += 0.5 * G.g[d] * (A.W(2 + d, c) + A.W(2 + d, cp));
+      D += (Ac.u(d, cp) - Ac.u(d, c)) * G.idx[d];
     }
+    pbar -= WE * D;
   }
-  // T(rho, e) at c: its derivatives carry the conduction adjoint to rho and e of c
-  double dTdr_c = 0.0, dTde_c = gm1;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    SH(cp, c, d, 1);
+    pbar += (Ac.W(2 + d, cp) - Ac.W(2 + d, c)) * G.idx[d];
+    rb += 0.5 * G.g[d] * (Ac.W(2 + d, c) + Ac.W(2 + d, cp));
+  }
   if constexpr (RAD) {
-    const Thermo th = thermo<true>(G, A.rho(c), A.e(c));
-    dTdr_c = th.dTdr;
-    dTde_c = th.dTde;
+    const Thermo th = thermo<true>(G, Ac.rho(c), Ac.e(c));
     rb += pbar * th.dpdr;
     eb += pbar * th.dpde;
   } else if (pbar != 0.0) {
-    rb += pbar * gm1 * A.e(c);
-    eb += pbar * gm1 * A.rho(c);
+    rb += pbar * gm1 * Ac.e(c);
+    eb += pbar * gm1 * Ac.rho(c);
   }
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
     const double ih = G.idx[d];
-    // mass flux faces f = p + k e_d (k = -1..2) read rho at c through the reconstruction
-#pragma unroll
-    for (int k = -1; k <= 2; ++k) {
-      SH(f, c, d, k);
-      int pf = padded(f);
-      if (pf < 0) continue;
-      double fb = fbar[(size_t)d * PG.PN + pf];
-      if (fb == 0.0) continue;
-      SH(m2, f, d, -2);
-      SH(m1, f, d, -1);
-      SH(p1, f, d, 1);
-      double wv = A.u(d, f);
-      double g[4];
-      upwind_grad(A.rho(m2), A.rho(m1), A.rho(f), A.rho(p1), wv, g);
-      rb += fb * wv * g[2 - k];  // c = f - k is argument (c - (f - 2)) = 2 - k
+    const double fb = fbar[(size_t)d * PG.PN + pl];
+    if (fb != 0.0) {
+      SH(m2, c, d, -2);
+      SH(m1, c, d, -1);
+      SH(p1, c, d, 1);
+      ub[d] += fb * upwind(Ac.rho(m2), Ac.rho(m1), Ac.rho(c), Ac.rho(p1), Ac.u(d, c));
     }
-    // energy flux g = f e*: e* reads e at c from faces f = c + k e_d
+    SH(cm, c, d, -1);
+    const double a0 = Ac.W(1, c), a1 = Ac.W(1, cm);
+    if (a0 != 0.0) ub[d] += a0 * eos_p<RAD>(G, Ac.rho(c), Ac.e(c)) * ih;
+    if (a1 != 0.0) ub[d] -= a1 * eos_p<RAD>(G, Ac.rho(cm), Ac.e(cm)) * ih;
+  }
+}
+
+template <int ND, bool RAD, class AC>
+__device__ __forceinline__ void vjp_tileB(const Grid& G, const PadGrid& PG, const AC& Ac, const BTile<ND>& T,
+                                          const double* mf, const double* fbar, double* xbar, double* sC) {
+  const int t = threadIdx.x;
+  const int l[3] = {t % bt<ND>(0), (t / bt<ND>(0)) % bt<ND>(1), t / (bt<ND>(0) * bt<ND>(1))};
+  int c[3], pl = 0;
+  bool own = true;
 #pragma unroll
-    for (int k = -1; k <= 2; ++k) {
-      SH(f, c, d, k);
-      SH(fm, f, d, -1);
-      double gb = (A.W(1, f) - A.W(1, fm)) * ih;
-      if (gb == 0.0) continue;
-      SH(m2, f, d, -2);
-      SH(p1, f, d, 1);
-      double wv = A.u(d, f);
-      double fl = MF(d, f);
-      double g[4];
-      upwind_grad(A.e(m2), A.e(fm), A.e(f), A.e(p1), wv, g);
-      eb += gb * fl * g[2 - k];
-    }
-    // conduction q_d on faces c and c + e_d (not on wall faces)
-    if (G.chi_model != 0) {
-#pragma unroll
-      for (int k = 0; k < 2; ++k) {
-        SH(f, c, d, k);
-        if (G.bc[d] == 1 && (f[d] == 0 || f[d] == G.n[d])) continue;
-        SH(fm, f, d, -1);
-        double qb = (A.W(1, fm) - A.W(1, f)) * ih;
-        if (qb == 0.0) continue;
-        double Tm = eos_T<RAD>(G, A.rho(fm), A.e(fm)), T0 = eos_T<RAD>(G, A.rho(f), A.e(f));
-        double chm, ch0, dchm, dch0;
-        if (G.chi_model == 1) {
-          chm = ch0 = G.chi0;
-          dchm = dch0 = 0.0;
-        } else {
-          double p = G.chi_exp;
-          chm = G.chi0 * powr(Tm * G.chi_tref_inv, p);
-          ch0 = G.chi0 * powr(T0 * G.chi_tref_inv, p);
-          dchm = p * chm / Tm;
-          dch0 = p * ch0 / T0;
-        }
-        double chif = 0.5 * (chm + ch0);
-        double dT = T0 - Tm;
-        // q = chif (T0 - Tm) ih; c is the face's cell (k = 0: T0) or its lower cell (k = 1: Tm)
-        double dq_dT = (k == 0) ? (0.5 * dch0 * dT + chif) * ih : (0.5 * dchm * dT - chif) * ih;
-        eb += qb * dq_dT * dTde_c;
-        if constexpr (RAD) rb += qb * dq_dT * dTdr_c;
-      }
-    }
-    // u_d at face c: its own mass flux f_d[c] = u_d rho*
-    {
-      int pc = padded(c);
-      double fb = fbar[(size_t)d * PG.PN + pc];
-      if (fb != 0.0) {
-        SH(m2, c, d, -2);
-        SH(m1, c, d, -1);
-        SH(p1, c, d, 1);
-        ub[d] += fb * upwind(A.rho(m2), A.rho(m1), A.rho(c), A.rho(p1), A.u(d, c));
-      }
-    }
-    // u_d in div u of rows E at c and c - e_d
-    {
-      SH(cm, c, d, -1);
-      double a0 = A.W(1, c), a1 = A.W(1, cm);
-      if (a0 != 0.0) ub[d] += a0 * eos_p<RAD>(G, A.rho(c), A.e(c)) * ih;
-      if (a1 != 0.0) ub[d] -= a1 * eos_p<RAD>(G, A.rho(cm), A.e(cm)) * ih;
-    }
-    // Phi_dd at centres cc = c - k e_d (k = -1..2): u* reads u_d[cc-1..cc+2]
-#pragma unroll
-    for (int k = -1; k <= 2; ++k) {
-      SH(cc, c, d, -k);
-      SH(cp, cc, d, 1);
-      double Pb = (A.W(2 + d, cp) - A.W(2 + d, cc)) * ih;
-      if (Pb == 0.0) continue;
-      double m = 0.5 * (MF(d, cc) + MF(d, cp));
-      SH(um1, cc, d, -1);
-      SH(up2, cc, d, 2);
-      double g[4];
-      upwind_grad(A.u(d, um1), A.u(d, cc), A.u(d, cp), A.u(d, up2), m, g);
-      ub[d] += Pb * m * g[k + 1];  // c = cc + k: argument index k + 1
-    }
-    // Phi_de (u_d carried along e) at edges ce = c - k e_e (k = -2..1): u* reads
-    // u_d[ce - 2e_e .. ce + e_e]
-#pragma unroll
-    for (int e = 0; e < ND; ++e) {
-      if (e == d) continue;
-      const double ihe = G.idx[e];
-#pragma unroll
-      for (int k = -2; k <= 1; ++k) {
-        SH(ce, c, e, -k);
-        SH(cem, ce, e, -1);
-        double Pb = (A.W(2 + d, ce) - A.W(2 + d, cem)) * ihe;
-        if (Pb == 0.0) continue;
-        SH(ced, ce, d, -1);
-        double m = 0.5 * (MF(e, ced) + MF(e, ce));
-        SH(em2, ce, e, -2);
-        SH(ep1, ce, e, 1);
-        double g[4];
-        upwind_grad(A.u(d, em2), A.u(d, cem), A.u(d, ce), A.u(d, ep1), m, g);
-        ub[d] += Pb * m * g[k + 2];  // c = ce + k: argument index k + 2
-      }
+  for (int d = 0; d < 3; ++d) {
+    c[d] = T.o[d] + l[d];
+    if (d < ND) {
+      own = own && (c[d] + 3 < PG.P[d]);
+      pl += (c[d] + 3) * PG.pstride[d];
     }
   }
+  double rb = 0.0, eb = 0.0, ub[3] = {0.0, 0.0, 0.0};
+  vjp_axisB<ND, 0, RAD>(G, PG, Ac, T, l, own, mf, fbar, sC, rb, eb, ub);
+  vjp_axisB<ND, 1, RAD>(G, PG, Ac, T, l, own, mf, fbar, sC, rb, eb, ub);
+  if constexpr (ND == 3) vjp_axisB<ND, 2, RAD>(G, PG, Ac, T, l, own, mf, fbar, sC, rb, eb, ub);
+  if (!own) return;
+  vjp_localB<ND, RAD>(G, PG, Ac, c, pl, fbar, rb, eb, ub);
   xbar[pl] = rb;
   xbar[(size_t)PG.PN + pl] = eb;
 #pragma unroll
@@ -441,11 +569,10 @@ template <int ND, bool RAD>
 __global__ void __launch_bounds__(kBlock) k_vjp_stageB(Grid G, PadGrid PG, const double* X, const double* w,
                                                        double cR, const double* mf, const double* fbar,
                                                        double* xbar) {
-  int c[3], pl;
-  bool in;
-  if (!vtile_cell<ND>(G, PG, c, &pl, &in)) return;
-  if (in) vjp_stageB_cell<ND, RAD>(G, PG, Acc<ND, true>(G, X, w, cR), c, pl, mf, fbar, xbar);
-  else vjp_stageB_cell<ND, RAD>(G, PG, Acc<ND, false>(G, X, w, cR), c, pl, mf, fbar, xbar);
+  __shared__ double sC[8 * bfaces_max<ND>()];
+  const BTile<ND> T = btile_setup<ND>(G, PG);
+  if (T.interior) vjp_tileB<ND, RAD>(G, PG, Acc<ND, true>(G, X, w, cR), T, mf, fbar, xbar, sC);
+  else vjp_tileB<ND, RAD>(G, PG, Acc<ND, false>(G, X, w, cR), T, mf, fbar, xbar, sC);
 }
 
 // ---- fold: interior adjoint = U part + sum of padded copies ------------------------------
@@ -740,11 +867,12 @@ void launch_vjp(const Grid& G, const double* X, const double* w, double cU, doub
     const double by = 8.0 * (2 * nv * G.N + (2 * G.nd + nv) * (double)PG.PN);
     const double* fb = fbar;
     const bool rad = G.a_rad != 0.0;
+    const dim3 gb(G.nd == 2 ? btile_blocks<2>(PG) : btile_blocks<3>(PG));
     if (G.nd == 2)
-      launch_k(KF_VJP_B, by, rad ? k_vjp_stageB<2, true> : k_vjp_stageB<2, false>, gt, bl, 0, s, G, PG, X, w,
+      launch_k(KF_VJP_B, by, rad ? k_vjp_stageB<2, true> : k_vjp_stageB<2, false>, gb, bl, 0, s, G, PG, X, w,
                cR, mfc, fb, xbar);
     else
-      launch_k(KF_VJP_B, by, rad ? k_vjp_stageB<3, true> : k_vjp_stageB<3, false>, gt, bl, 0, s, G, PG, X, w,
+      launch_k(KF_VJP_B, by, rad ? k_vjp_stageB<3, true> : k_vjp_stageB<3, false>, gb, bl, 0, s, G, PG, X, w,
                cR, mfc, fb, xbar);
   }
   {
