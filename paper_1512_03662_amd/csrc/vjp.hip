@@ -577,24 +577,32 @@ __global__ void __launch_bounds__(kBlock) k_vjp_stageB(Grid G, PadGrid PG, const
 
 // ---- fold: interior adjoint = U part + sum of padded copies ------------------------------
 // padded logical positions that hold a copy of stored index i on an axis, with signs
-__device__ __forceinline__ int preimages(int i, int n, int bc, bool normal, int* pos, double* sg) {
-  int k = 0;
+// padded logical positions that hold a copy of stored index i on an axis: slot 0 the index
+// itself, slots 1 and 2 its images below and above the grid, with the sign of the copy (0: no
+// copy in that slot)
+__device__ __forceinline__ void preimages(int i, int n, int bc, bool normal, int* pos, double* sg) {
   if (bc == 0) {
-    pos[k] = i; sg[k++] = 1.0;
-    if (i - n >= -3) { pos[k] = i - n; sg[k++] = 1.0; }
-    if (i + n <= n + 2) { pos[k] = i + n; sg[k++] = 1.0; }
-    return k;
+    pos[0] = i;
+    sg[0] = 1.0;
+    pos[1] = i - n;
+    sg[1] = (i - n >= -3) ? 1.0 : 0.0;
+    pos[2] = i + n;
+    sg[2] = (i + n <= n + 2) ? 1.0 : 0.0;
+  } else if (!normal) {
+    pos[0] = i;
+    sg[0] = 1.0;
+    pos[1] = -1 - i;
+    sg[1] = (-1 - i >= -3) ? 1.0 : 0.0;
+    pos[2] = 2 * n - 1 - i;
+    sg[2] = (2 * n - 1 - i <= n + 2) ? 1.0 : 0.0;
+  } else {
+    pos[0] = i;
+    sg[0] = (i >= 1) ? 1.0 : 0.0;
+    pos[1] = -i;
+    sg[1] = (i >= 1 && -i >= -3) ? -1.0 : 0.0;
+    pos[2] = 2 * n - i;
+    sg[2] = (i >= 1 && 2 * n - i <= n + 2) ? -1.0 : 0.0;
   }
-  if (!normal) {
-    pos[k] = i; sg[k++] = 1.0;
-    if (-1 - i >= -3) { pos[k] = -1 - i; sg[k++] = 1.0; }
-    if (2 * n - 1 - i <= n + 2) { pos[k] = 2 * n - 1 - i; sg[k++] = 1.0; }
-    return k;
-  }
-  if (i >= 1) { pos[k] = i; sg[k++] = 1.0; }
-  if (i >= 1 && -i >= -3) { pos[k] = -i; sg[k++] = -1.0; }
-  if (i >= 1 && 2 * n - i <= n + 2) { pos[k] = 2 * n - i; sg[k++] = -1.0; }
-  return k;
 }
 
 template <int ND>
@@ -634,21 +642,22 @@ __global__ void __launch_bounds__(kBlock) k_vjp_fold(Grid G, PadGrid PG, const d
   // R part: sum over padded copies
 #pragma unroll
   for (int var = 0; var < 2 + ND; ++var) {
-    int pos[3][3];
-    double sg[3][3];
-    int cnt[3] = {1, 1, 1};
-    pos[1][0] = pos[2][0] = 0;
-    sg[1][0] = sg[2][0] = 1.0;
+    int pos[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    double sg[3][3] = {{1.0, 0.0, 0.0}, {1.0, 0.0, 0.0}, {1.0, 0.0, 0.0}};
 #pragma unroll
-    for (int d = 0; d < ND; ++d) cnt[d] = preimages(P.c[d], G.n[d], G.bc[d], var == 2 + d, pos[d], sg[d]);
+    for (int d = 0; d < ND; ++d) preimages(P.c[d], G.n[d], G.bc[d], var == 2 + d, pos[d], sg[d]);
     double acc = 0.0;
-    for (int a = 0; a < cnt[0]; ++a)
-      for (int b = 0; b < cnt[1]; ++b)
-        for (int cc = 0; cc < cnt[2]; ++cc) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+          const double sgn = sg[0][a] * sg[1][b] * sg[2][cc];
+          if (sgn == 0.0) continue;  // no copy there (the position may lie off the padded grid)
           int pl = (pos[0][a] + 3) + (pos[1][b] + (ND >= 2 ? 3 : 0)) * PG.pstride[1];
           if (ND == 3) pl += (pos[2][cc] + 3) * PG.pstride[2];
-          double s = sg[0][a] * sg[1][b] * sg[2][cc];
-          acc += s * xbar[(size_t)var * PG.PN + pl];
+          acc += sgn * xbar[(size_t)var * PG.PN + pl];
         }
     res[var] += acc;
   }
