@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--ell", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="c4: skip the adjoint run (gradient through the steps, FD-checked)")
     ap.add_argument("--no-kernels-3d", dest="kernels_3d", action="store_false",
                     help="skip the kernel rates at the 256^3 production size")
     ap.add_argument("--only-kernels-3d", action="store_true",
@@ -241,9 +243,80 @@ def main():
         "compare": compare,
         "probe_ms": {k: round(v[0], 3) for k, v in sorted(probes.items(), key=lambda kv: -kv[1][0])},
     }
+    if args.workload == "c4" and not args.no_adjoint:
+        print("# adjoint run", file=sys.stderr, flush=True)
+        rec["adjoint"] = adjoint_run(J, w)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"], rec["error_vs_oracle"] = cpu_baseline(w, args, Xk_first=first_step(ctx, X0, cfl))
     print(json.dumps(rec), flush=True)
+
+
+def kinetic_energy(Xt, pd):
+    """Sum over faces of rho_f u_d^2 / 2 (rho_f the mean of the two cells, mirrored at walls)."""
+    import torch
+    nd = len(pd["shape"])
+    tot = 0.0
+    for d in range(nd):
+        ax = nd - 1 - d
+        rho = Xt[0]
+        lower = torch.roll(rho, 1, dims=ax)
+        if pd["bc"][d] == "wall":
+            idx = [slice(None)] * nd
+            idx[ax] = 0
+            lower[tuple(idx)] = rho[tuple(idx)]
+        tot = tot + 0.5 * torch.sum(0.5 * (lower + rho) * Xt[2 + d] ** 2)
+    return tot
+
+
+def adjoint_run(J, w, directions=8):
+    """The adjoint form of the workload: the gradient of the total kinetic energy after the
+    workload's implicit steps (fixed time step from X^0) w.r.t. the initial temperature,
+    through ImplicitSteps (per-step checkpoints; each backward step is a transposed FGMRES
+    solve with the hand-written J^T w and transposed preconditioner), checked against central
+    differences of the forward steps along seeded directions (T -> T (1 + eps d) at fixed rho,
+    eps = 1e-7).  Tight solver tolerances (Newton 1e-13, GMRES 1e-11, CG 1e-8) make the
+    converged steps, and so the difference quotients, accurate enough for the check."""
+    import numpy as np
+    import torch
+    import workloads as Wl
+    dev = torch.device("cuda:0")
+    pd = w["problem"]
+    ctx = J.Context(pd, precond="sound_thermal", jv_mode="exact", newton_tol=1e-13, newton_max=30,
+                    gmres_eta=1e-11, gmres_maxit=600, cg_eta=1e-8)
+    X0 = torch.tensor(w["X0"], dtype=torch.float64, device=dev)
+    dt = ctx.cfl_dt(X0, w["cfl"])
+    dts = [dt] * int(w["steps"])
+    Xg = X0.clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = kinetic_energy(J.ImplicitSteps.apply(Xg, ctx, dts), pd)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    grad_e = Xg.grad[1]
+    errs = []
+    eps = 1e-7
+    for k in range(directions):
+        d = torch.tensor(Wl.random_vector(w["X0"][1:2], 2001 + k)[0], dtype=torch.float64, device=dev)
+        an = float(torch.sum(grad_e * X0[1] * d))  # dL/deps for e -> e (1 + eps d)
+        vals = []
+        for sgn in (1.0, -1.0):
+            Xp = X0.clone()
+            Xp[1] = X0[1] * (1.0 + sgn * eps * d)
+            for dtk in dts:
+                ctx.implicit_step(Xp, dtk)
+            vals.append(float(kinetic_energy(Xp, pd)))
+        fd = (vals[0] - vals[1]) / (2 * eps)
+        errs.append(abs(fd - an) / abs(an))
+    ctx.close()
+    return {"form": "gradient of total kinetic energy w.r.t. the initial temperature",
+            "steps": len(dts), "dt": dt, "forward_ms": 1e3 * (t1 - t0),
+            "backward_ms": 1e3 * (t2 - t1), "loss": float(loss.detach()),
+            "fd_directions": directions, "fd_eps": eps,
+            "fd_max_rel_err": float(np.max(errs)), "fd_rel_errs": [float(e) for e in errs],
+            "solver": "exact J.v, sound+thermal preconditioner, Newton 1e-13, GMRES 1e-11, CG 1e-8"}
 
 
 def first_step(ctx, X0, cfl):

@@ -132,3 +132,50 @@ def test_fullsize_vjp_sampled(name):
             ref = float(np.sum(col * wb))
             scale = float(np.sum(np.abs(col * wb)))
             assert abs(JTw[idx] - ref) <= 1e-12 * scale + 1e-300, (c, var, JTw[idx], ref)
+
+
+def test_fullsize_gradient_through_steps_fd():
+    """The 512^2 adjoint workload (stratified box, chi ~ T^3, CFL 50, 5 steps): the gradient
+    of the total kinetic energy w.r.t. the initial temperature through ImplicitSteps, against
+    central differences of the forward steps along 8 seeded directions.  eps = 1e-7 and a bar
+    of 3e-4: on 512^2 the difference quotient straddles a few upwind switches (measured
+    errors 5e-6 .. 1e-4), which the exact gradient of the frozen branches does not see."""
+    J = _lib()
+    w = W.stratified_2d_kappa(n=512)
+    pd, X0np = w["problem"], w["X0"]
+    ctx = J.Context(pd, precond="sound_thermal", jv_mode="exact", newton_tol=1e-13, newton_max=30,
+                    gmres_eta=1e-11, gmres_maxit=600, cg_eta=1e-8)
+    X0 = torch.tensor(X0np, dtype=torch.float64, device=DEV)
+    dt = ctx.cfl_dt(X0, w["cfl"])
+    dts = [dt] * int(w["steps"])
+
+    def ke(Xt):
+        rho = Xt[0]
+        tot = 0.0
+        for d in range(2):
+            ax = 1 - d
+            lower = torch.roll(rho, 1, dims=ax)
+            if pd["bc"][d] == "wall":
+                idx = [slice(None)] * 2
+                idx[ax] = 0
+                lower[tuple(idx)] = rho[tuple(idx)]
+            tot = tot + 0.5 * torch.sum(0.5 * (lower + rho) * Xt[2 + d] ** 2)
+        return tot
+
+    Xg = X0.clone().requires_grad_(True)
+    ke(J.ImplicitSteps.apply(Xg, ctx, dts)).backward()
+    grad_e = Xg.grad[1]
+    eps = 1e-7
+    for k in range(8):
+        d = torch.tensor(W.random_vector(X0np[1:2], 2001 + k)[0], dtype=torch.float64, device=DEV)
+        an = float(torch.sum(grad_e * X0[1] * d))
+        vals = []
+        for sgn in (1.0, -1.0):
+            Xp = X0.clone()
+            Xp[1] = X0[1] * (1.0 + sgn * eps * d)
+            for dtk in dts:
+                ctx.implicit_step(Xp, dtk)
+            vals.append(float(ke(Xp)))
+        fd = (vals[0] - vals[1]) / (2 * eps)
+        assert abs(fd - an) <= 3e-4 * abs(an), (k, fd, an)
+    ctx.close()
