@@ -20,7 +20,8 @@
  *   rho_f u / dt - b (no flux acts on them) so J, M and J^T act there as the diagonal.
  * Streams: all work is ordered on the stream given to jfnk_create.  jfnk_residual,
  *   jfnk_jvp, jfnk_vjp and jfnk_vjp_prev are asynchronous; jfnk_precond_apply,
- *   jfnk_implicit_step, jfnk_adjoint_step and jfnk_cfl_dt synchronise the stream.
+ *   jfnk_precond_apply_transpose, jfnk_implicit_step, jfnk_si_step, jfnk_adjoint_step and
+ *   jfnk_cfl_dt synchronise the stream.
  * Errors: negative status codes; jfnk_last_error() gives the message.  Nothing throws
  *   across this boundary.  A context is not thread-safe; use one context per stream.
  */

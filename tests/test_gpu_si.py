@@ -88,3 +88,24 @@ def test_si_step_needs_a_preconditioner():
     ctx = J.Context(pd, precond="none")
     with pytest.raises(J.JfnkError):
         ctx.si_step(T(X), 0.01)
+
+
+def test_si_schur_long_run_is_mach_independent():
+    """One domain crossing (t = 8) of the isentropic vortex (Sect. 3.7) at CFL_adv = 0.2 with
+    the Schur-form stepper: stable at Mach 8.5e-3 and 8.5e-5, and the L2 error of u against
+    the (periodically) translated initial profile is the same for both within 2 %."""
+    J = _lib()
+    errs = []
+    for t_inf in (1e2, 1e6):
+        w = W.isentropic_vortex_2d(n=64, t_inf=t_inf)
+        pd = w["problem"]
+        ctx = J.Context(pd, precond="sound", pc_schur=1)
+        X = T(w["X0"])
+        steps = 320
+        dt = 8.0 / steps
+        for _ in range(steps):
+            ctx.si_step(X, dt)
+        ctx.close()
+        d = H(X)[2] - W.isentropic_vortex_u_exact(n=64, t=8.0)
+        errs.append(float(np.sqrt(np.mean(d * d))))
+    assert max(errs) < 5e-3 and abs(errs[0] - errs[1]) <= 0.02 * errs[1], errs
