@@ -3,6 +3,7 @@
     python -m paper_1512_03662_amd.studies tgv [--steps 10]
     python -m paper_1512_03662_amd.studies vortex [--steps 5]
     python -m paper_1512_03662_amd.studies si_vortex [--schemes si_schur,jfnk_be]
+    python -m paper_1512_03662_amd.studies eta [--steps 10]
 
 tgv:    the 3D Taylor-Green vortex at 64^3 for the Mach numbers and hydrodynamic CFL numbers
         of the paper's timing table (Results section, Taylor-Green vortex): average Newton
@@ -185,9 +186,34 @@ def si_vortex(args):
                 print(json.dumps(r), flush=True)
 
 
+def eta(args):
+    """The parabolic-solve tolerance eta' (the paper fixes 1e-4 and leaves larger values to
+    future work): the stratified 2D box 256x256 (bench's default workload, 10 steps at
+    CFL_hydro 100, sound + thermal preconditioner, FD J.v) for eta' = 1e-4 .. 1 and for a
+    single multigrid-preconditioned CG iteration per elliptic solve."""
+    import torch
+
+    import workloads as W
+    import paper_1512_03662_amd as J
+    dev = torch.device("cuda:0")
+    w = W.stratified_2d(n=256)
+    X0 = torch.tensor(w["X0"], dtype=torch.float64, device=dev)
+    cases = [(1e-4, 50), (1e-3, 50), (1e-2, 50), (1e-1, 50), (1.0, 50), (1e-4, 1), (1e-4, 2)]
+    for prec in ("fp64", "fp32"):
+        for cg_eta, cg_maxit in cases:
+            ctx = J.Context(w["problem"], precond=w["precond"], jv_mode=w["jv_mode"], ell_precision=prec,
+                            cg_eta=cg_eta, cg_maxit=cg_maxit)
+            r = _run(ctx, X0, w["cfl"], 1, torch)  # warm-up
+            r = _run(ctx, X0, w["cfl"], args.steps, torch)
+            ctx.close()
+            r.update({"study": "stratified_2d_256x256_cg_eta", "ell_precision": prec, "cg_eta": cg_eta,
+                      "cg_maxit": cg_maxit, "steps_per_s": 1e3 / r["ms_per_step"]})
+            print(json.dumps(r), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["tgv", "vortex", "si_vortex"])
+    ap.add_argument("study", choices=["tgv", "vortex", "si_vortex", "eta"])
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--schemes", default=",".join(SI_SCHEMES),
                     help="si_vortex: comma-separated subset of " + ",".join(SI_SCHEMES))
@@ -196,7 +222,7 @@ def main():
     ap.add_argument("--cfls", default="0.01,0.02,0.05,0.1,0.2,0.4,0.8,1.6",
                     help="si_vortex: advective CFL numbers (rounded so that t_end is reached)")
     args = ap.parse_args()
-    {"tgv": tgv, "vortex": vortex, "si_vortex": si_vortex}[args.study](args)
+    {"tgv": tgv, "vortex": vortex, "si_vortex": si_vortex, "eta": eta}[args.study](args)
 
 
 if __name__ == "__main__":
