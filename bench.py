@@ -1,6 +1,6 @@
 """Benchmark: implicit steps/s of the JFNK + physics-based-preconditioner step on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload c2] [--gpus 1]
+    python bench.py [--steps K] [--warmup W] [--workload stratified_2d] [--gpus 1]
 
 A step is one implicit time step X^n -> X^{n+1} (CFL time step from X^n, Newton to
 ||R^-1 dX||_inf < 1e-8, FGMRES(30) with CGS2, finite-difference J.v, physics-based
@@ -29,12 +29,16 @@ METRIC = "implicit steps/s and J·v cell-updates/s at fixed Newton tol; % HBM pe
 HBM_PEAK_GBS = 8000.0
 
 
+WORKLOADS = ("acoustic_bump_2d", "stratified_2d", "taylor_green_3d", "stratified_2d_kappa",
+             "convective_box_3d", "radiative_2d")
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "rad"])
+    ap.add_argument("--workload", default="stratified_2d", choices=sorted(WORKLOADS))
     ap.add_argument("--jv", default=None, choices=["fd", "exact"])
     ap.add_argument("--ell", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--kernel-reps", type=int, default=20)
@@ -42,7 +46,7 @@ def parse():
     ap.add_argument("--no-tuned", action="store_true",
                     help="skip the second timing with one CG iteration per elliptic solve")
     ap.add_argument("--no-adjoint", action="store_true",
-                    help="c4: skip the adjoint run (gradient through the steps, FD-checked)")
+                    help="stratified_2d_kappa: skip the adjoint run (gradient through the steps, FD-checked)")
     ap.add_argument("--no-kernels-3d", dest="kernels_3d", action="store_false",
                     help="skip the kernel rates at the 256^3 production size")
     ap.add_argument("--only-kernels-3d", action="store_true",
@@ -277,7 +281,7 @@ def main():
         "tuned": tuned,
         "probe_ms": {k: round(v[0], 3) for k, v in sorted(probes.items(), key=lambda kv: -kv[1][0])},
     }
-    if args.workload == "c4" and not args.no_adjoint:
+    if args.workload == "stratified_2d_kappa" and not args.no_adjoint:
         print("# adjoint run", file=sys.stderr, flush=True)
         rec["adjoint"] = adjoint_run(J, w)
     if not args.no_cpu_baseline:

@@ -50,12 +50,12 @@ def test_vjp_parity_small(case):
     assert np.all(np.abs(got - ref) <= 1e-12 * scale + 1e-300)
 
 
-@pytest.mark.parametrize("name", ["c2", "c3_64", "c5_64"])
+@pytest.mark.parametrize("name", ["stratified_2d_256", "taylor_green_3d_64", "convective_3d_64"])
 def test_vjp_dot_product_large(name):
     J = _lib()
-    if name == "c2":
+    if name == "stratified_2d_256":
         w_ = W.stratified_2d(n=256)
-    elif name == "c3_64":
+    elif name == "taylor_green_3d_64":
         w_ = W.taylor_green_3d(n=64, mach=1e-2)
     else:
         w_ = W.polytrope((64, 64, 64), 20.0, mach=1e-4, seed=1005, chi_model="power", cfl=500.0)

@@ -45,12 +45,12 @@ def _at(A, P, cells):
 
 
 def _workload(name):
-    if name == "c5_256":
+    if name == "convective_3d_256":
         return W.convective_box_3d(n=256)
     return W.taylor_green_3d(n=128)
 
 
-@pytest.mark.parametrize("name", ["c5_256", "c3_128"])
+@pytest.mark.parametrize("name", ["convective_3d_256", "taylor_green_3d_128"])
 def test_fullsize_residual_and_jv_sampled(name):
     J = _lib()
     w = _workload(name)
@@ -105,7 +105,7 @@ def _box_cells(P, c, r=3):
     return tuple(g.ravel() for g in grids)
 
 
-@pytest.mark.parametrize("name", ["c5_256"])
+@pytest.mark.parametrize("name", ["convective_3d_256"])
 def test_fullsize_vjp_sampled(name):
     J = _lib()
     w = _workload(name)

@@ -102,7 +102,7 @@ def _velocity_noise(rng, X, nd, bc, gamma, mach):
 
 
 # ----------------------------------------------------------------------------------------
-# C1: 2D acoustic pulse in a periodic box
+# 2D acoustic pulse in a periodic box
 # ----------------------------------------------------------------------------------------
 def acoustic_bump_2d(n=32, seed=1001, gamma=5.0 / 3.0, amp=1e-3, width_cells=4.0, cfl=10.0):
     """Gaussian density bump on a uniform periodic box, isentropic pressure p = rho**gamma.
@@ -131,7 +131,7 @@ def acoustic_bump_2d(n=32, seed=1001, gamma=5.0 / 3.0, amp=1e-3, width_cells=4.0
 
 
 # ----------------------------------------------------------------------------------------
-# Stratified polytropic boxes (C2, C4 in 2D; C5 in 3D)
+# Stratified polytropic boxes (2D 256^2 and 512^2, 3D 256^3)
 # ----------------------------------------------------------------------------------------
 def polytrope(shape, contrast, poly_n=1.5, gamma=5.0 / 3.0, mach=1e-3, seed=1002, cfl=100.0,
               cfl_rad=10.0, chi_model="const", chi_exp=3.0, steps=10, name="polytrope",
@@ -210,14 +210,14 @@ def polytrope(shape, contrast, poly_n=1.5, gamma=5.0 / 3.0, mach=1e-3, seed=1002
 
 
 def stratified_2d(n=256, seed=1002, steps=10, cfl=100.0):
-    """C2: 2D polytrope n=1.5, density contrast 10, constant conductivity, Mach 1e-3 noise."""
+    """2D polytrope n=1.5, density contrast 10, constant conductivity, Mach 1e-3 noise."""
     w = polytrope((n, n), 10.0, mach=1e-3, seed=seed, cfl=cfl, chi_model="const", steps=steps,
                   name=f"stratified_2d_{n}x{n}")
     return w
 
 
 def stratified_2d_kappa(n=512, seed=1004, steps=5, cfl=50.0):
-    """C4: as C2 with chi = chi0 (T/T_top)^3 (adjoint workload)."""
+    """As stratified_2d (at 512^2) with chi = chi0 (T/T_top)^3 (the adjoint workload)."""
     return polytrope((n, n), 10.0, mach=1e-3, seed=seed, cfl=cfl, chi_model="power", steps=steps,
                      name=f"stratified_2d_kappa_{n}x{n}")
 
@@ -232,13 +232,13 @@ def radiative_2d(n=256, seed=1006, steps=5, cfl=50.0, a_rad=1.0):
 
 
 def convective_box_3d(n=256, seed=1005, steps=10, cfl=500.0):
-    """C5: 3D polytrope n=1.5, density contrast 20, chi ~ T^3, Mach 1e-4 noise."""
+    """3D polytrope n=1.5, density contrast 20, chi ~ T^3, Mach 1e-4 noise."""
     return polytrope((n, n, n), 20.0, mach=1e-4, seed=seed, cfl=cfl, chi_model="power",
                      steps=steps, name=f"convective_box_3d_{n}^3")
 
 
 # ----------------------------------------------------------------------------------------
-# C3: 3D Taylor-Green vortex at low Mach
+# 3D Taylor-Green vortex at low Mach
 # ----------------------------------------------------------------------------------------
 def taylor_green_3d(n=128, seed=1003, mach=1e-6, gamma=1.4, noise=1e-8, cfl=1000.0, steps=5):
     """Taylor-Green velocity on [0, 2pi)^3 with the divergence-preserving pressure.
@@ -362,10 +362,10 @@ def random_vector(X, seed, amp=1.0, bc=None):
 
 
 CONFIGS = {
-    "c1": acoustic_bump_2d,
-    "c2": stratified_2d,
-    "c3": taylor_green_3d,
-    "c4": stratified_2d_kappa,
-    "c5": convective_box_3d,
-    "rad": radiative_2d,
+    "acoustic_bump_2d": acoustic_bump_2d,
+    "stratified_2d": stratified_2d,
+    "taylor_green_3d": taylor_green_3d,
+    "stratified_2d_kappa": stratified_2d_kappa,
+    "convective_box_3d": convective_box_3d,
+    "radiative_2d": radiative_2d,
 }
