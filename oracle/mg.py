@@ -141,7 +141,8 @@ def pcg(op: EllOp, b, eta=1e-4, maxit=50, dtype=np.float64, mg=None, stats=None)
     """CG on A x = b preconditioned by one V-cycle; stop when ||r||_2 < eta ||b||_2.
 
     Returns x in float64.  With dtype=float32, b is divided by ||b||_2 (FP64) before the
-    cast and the result multiplied back.
+    cast and the result multiplied back.  maxit = 0: the solve is the preconditioning
+    V-cycle alone, x = M b (a fixed, symmetric linear operator; no CG step).
     """
     if mg is None:
         mg = Multigrid(op, dtype)
@@ -160,6 +161,8 @@ def pcg(op: EllOp, b, eta=1e-4, maxit=50, dtype=np.float64, mg=None, stats=None)
     r = bb.copy()
     bn = np.sqrt(dot(bb, bb))
     z = mg.vcycle(r)
+    if maxit == 0:
+        x = z
     p = z.copy()
     rz = dot(r, z)
     it = 0

@@ -115,3 +115,23 @@ def test_fgmres_restart_and_residual_estimates():
     x, info = fgmres(lambda z: A @ z, prec, b, eta=1e-8, m=10, maxit=300)
     assert info["converged"]
     assert np.linalg.norm(b - A @ x) < 1e-8 * np.linalg.norm(b) * 1.0001
+
+
+def test_single_vcycle_solve_is_a_symmetric_contraction():
+    """maxit = 0 makes the elliptic solve the preconditioning V-cycle alone (x = M b): a fixed,
+    symmetric operator whose error propagation I - M A is a contraction (spectral radius
+    below 1, so M is a usable approximate inverse of A)."""
+    P, X = _state((16, 8), ("periodic", "wall"), seed=5)
+    op = pressure_operator(P, X, _stiff_dt(P, 30.0))
+    N = P.ncell
+    M = np.empty((N, N))
+    for k in range(N):
+        e = np.zeros(N)
+        e[k] = 1.0
+        M[:, k] = pcg(op, e.reshape(P.field_shape), maxit=0).ravel()
+    assert np.max(np.abs(M - M.T)) <= 1e-12 * np.max(np.abs(M))
+    A = op.to_sparse().toarray()
+    rho = np.max(np.abs(np.linalg.eigvals(np.eye(N) - M @ A)))
+    assert rho < 0.5, rho
+    b = np.random.default_rng(6).uniform(-1, 1, P.field_shape)
+    assert np.array_equal(pcg(op, b, maxit=0), Multigrid(op).vcycle(b.astype(np.float64)))
