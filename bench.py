@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tuned", action="store_true",
-                    help="skip the second timing with one CG iteration per elliptic solve")
+                    help="skip the second timing with one V-cycle per elliptic solve")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="stratified_2d_kappa: skip the adjoint run (gradient through the steps, FD-checked)")
     ap.add_argument("--no-kernels-3d", dest="kernels_3d", action="store_false",
@@ -195,13 +195,13 @@ def main():
         ctx5.close()
         del X5
 
-    # ---- the same steps with one multigrid-preconditioned CG iteration per elliptic solve
-    # (the paper fixes eta' = 1e-4 and leaves looser inner solves to future work; FGMRES
-    # tolerates the variable preconditioner and needs the same iterations here) ------------
+    # ---- the same steps with each elliptic solve replaced by its preconditioning V-cycle
+    # (cg_maxit = 0: the paper fixes eta' = 1e-4 and leaves looser inner solves to future
+    # work; FGMRES needs the same iterations here) ----------------------------------------
     tuned = None
     if not args.no_tuned:
-        print("# tuned: one CG iteration per elliptic solve", file=sys.stderr, flush=True)
-        ctx_t = J.Context(pd, precond=precond, jv_mode=jv, ell_precision=args.ell, cg_maxit=1)
+        print("# tuned: one V-cycle per elliptic solve", file=sys.stderr, flush=True)
+        ctx_t = J.Context(pd, precond=precond, jv_mode=jv, ell_precision=args.ell, cg_maxit=0)
         ctx_save = ctx
         ctx = ctx_t
         run_steps(args.warmup)
@@ -215,7 +215,7 @@ def main():
         rel = [float(np.max(np.abs(Xt_np[v] - Xk_np[v])) / max(np.max(np.abs(Xk_np[v])), 1e-300))
                for v in range(nvar)]
         tuned = {
-            "form": "cg_maxit = 1 (one multigrid-preconditioned CG iteration per elliptic solve)",
+            "form": "cg_maxit = 0 (each elliptic solve is one symmetric multigrid V-cycle)",
             "value": args.steps / sec_t, "unit": "implicit steps/s", "ms_per_step": 1e3 * sec_t / args.steps,
             "speedup_vs_plain": sec / sec_t,
             "solver": {"newton_its": sum(s["newton_its"] for s in stats_t),

@@ -85,7 +85,9 @@ typedef struct {
   int32_t precond;       /* JFNK_PC_NONE | JFNK_PC_SOUND | JFNK_PC_SOUND_THERMAL        */
   int32_t ell_precision; /* JFNK_FP64 | JFNK_FP32 elliptic solves                       */
   double cg_eta;         /* parabolic-solve tolerance eta' (eq. forcing_term2)          */
-  int32_t cg_maxit;      /* maximum CG iterations per elliptic solve                    */
+  int32_t cg_maxit;      /* maximum CG iterations per elliptic solve; 0: the solve is    *
+                          * one symmetric V-cycle, x = M b (a fixed linear operator, no   *
+                          * CG step and no host synchronisation)                          */
   int32_t pc_schur;      /* 0: the paper's J~_V, which drops the velocity residual from  *
                           * the pressure equation (Sect. 3.3, delta form); 1: eliminate   *
                           * du exactly, keeping -dt div F~_u in the pressure right-hand  *

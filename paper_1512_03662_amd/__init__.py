@@ -183,7 +183,7 @@ class Context:
                                                  _ptr(self._vec(r, "r")), _ptr(out)))
         return out
 
-    def precond_apply_T(self, X, w, out=None):
+    def precond_apply_transpose(self, X, w, out=None):
         out = self._new() if out is None else self._vec(out, "out")
         self._check(self._lib.jfnk_precond_apply_transpose(self._h, _ptr(self._vec(X, "X")),
                                                    _ptr(self._vec(w, "w")), _ptr(out)))

@@ -188,7 +188,7 @@ void validate(const jfnk_problem* p, const jfnk_opts* o) {
   if (o->jv_mode != JFNK_JV_FD && o->jv_mode != JFNK_JV_EXACT) throw InvErr("bad jv_mode");
   if (o->precond < 0 || o->precond > 2) throw InvErr("bad precond");
   if (o->ell_precision != JFNK_FP64 && o->ell_precision != JFNK_FP32) throw InvErr("bad ell_precision");
-  if (o->cg_maxit < 1) throw InvErr("cg_maxit must be >= 1");
+  if (o->cg_maxit < 0) throw InvErr("cg_maxit must be >= 0");
   if (o->pc_schur != 0 && o->pc_schur != 1) throw InvErr("pc_schur must be 0 or 1");
 }
 
@@ -422,6 +422,9 @@ int pcg(jfnk_ctx* c, std::vector<Level>& lv, const double* Ainv, const T* b, T* 
   bool fused;
   const int l0 = first_fused(lv, &fused);
   const int nl = (int)lv.size();
+  // cg_maxit = 0: the solve is one V-cycle, x = M b (a fixed symmetric linear operator); no
+  // CG step and no host synchronisation
+  if (g.maxit == 0) z = x;
   // z = M b with the (b, b) and (b, z) partials
   if (l0 >= 1) {
     launch_mg_presmooth<T>(G, lv[0], b, z, g, true, s);
@@ -433,6 +436,7 @@ int pcg(jfnk_ctx* c, std::vector<Level>& lv, const double* Ainv, const T* b, T* 
     launch_dense_matvec<T>(N, Ainv, b, z, g, s);
     launch_cg_dot_rz<T>(N, b, z, g, s);
   }
+  if (g.maxit == 0) return 0;
   const T* rold = b;
   T* rnew = r1;
   const T* pold = z;
@@ -442,9 +446,13 @@ int pcg(jfnk_ctx* c, std::vector<Level>& lv, const double* Ainv, const T* b, T* 
   for (;;) {
     for (int k = 0; k < batch && enq < g.maxit; ++k) {
       const int it = ++enq;
+      // after the last allowed iteration only the decision is needed, not the next V-cycle
+      const bool last = (enq == g.maxit);
       launch_cg_apply<T>(G, lv[0], z, pold, pnew, q, x, g, it, s);
-      launch_cg_update<T>(G, lv[0], rold, q, pnew, x, rnew, l0 >= 1 ? z : nullptr, g, it, s);
-      if (l0 >= 1) {
+      launch_cg_update<T>(G, lv[0], rold, q, pnew, x, rnew, (l0 >= 1 && !last) ? z : nullptr, g, it, s);
+      if (last) {
+        launch_cg_decide(g, it, s);
+      } else if (l0 >= 1) {
         vcycle_rest<T>(c, lv, Ainv, rnew, z, g, it);
       } else if (fused) {
         launch_vcycle_coarse<T>(G, &lv[0], nl, Ainv, rnew, z, g, kCoarseConv | kCoarseRZ, it, s);

@@ -189,8 +189,9 @@ def si_vortex(args):
 def eta(args):
     """The parabolic-solve tolerance eta' (the paper fixes 1e-4 and leaves larger values to
     future work): the stratified 2D box 256x256 (bench's default workload, 10 steps at
-    CFL_hydro 100, sound + thermal preconditioner, FD J.v) for eta' = 1e-4 .. 1 and for a
-    single multigrid-preconditioned CG iteration per elliptic solve."""
+    CFL_hydro 100, sound + thermal preconditioner, FD J.v) for eta' = 1e-4 .. 1, for one or
+    two multigrid-preconditioned CG iterations per elliptic solve, and for the V-cycle alone
+    (cg_maxit = 0)."""
     import torch
 
     import workloads as W
@@ -198,7 +199,7 @@ def eta(args):
     dev = torch.device("cuda:0")
     w = W.stratified_2d(n=256)
     X0 = torch.tensor(w["X0"], dtype=torch.float64, device=dev)
-    cases = [(1e-4, 50), (1e-3, 50), (1e-2, 50), (1e-1, 50), (1.0, 50), (1e-4, 1), (1e-4, 2)]
+    cases = [(1e-4, 50), (1e-3, 50), (1e-2, 50), (1e-1, 50), (1.0, 50), (1e-4, 1), (1e-4, 2), (1e-4, 0)]
     for prec in ("fp64", "fp32"):
         for cg_eta, cg_maxit in cases:
             ctx = J.Context(w["problem"], precond=w["precond"], jv_mode=w["jv_mode"], ell_precision=prec,

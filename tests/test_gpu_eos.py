@@ -125,7 +125,7 @@ def test_precond_and_transpose_parity(mode, schur, shape, bc, a_rad):
     for k in range(P.nvar):
         assert np.max(np.abs(got[k] - ref[k])) <= 1e-10 * np.max(np.abs(ref[k])), k
     refT = pbp.apply_T(r)
-    gotT = H(ctx.precond_apply_T(T(X), T(r)))
+    gotT = H(ctx.precond_apply_transpose(T(X), T(r)))
     for k in range(P.nvar):
         assert np.max(np.abs(gotT[k] - refT[k])) <= 1e-10 * np.max(np.abs(refT[k])), k
 

@@ -279,3 +279,37 @@ def test_implicit_step_unpreconditioned_small_cfl():
     w = W.acoustic_bump_2d(n=16)
     err, st = _step_parity(w["problem"], w["X0"], 1.0, precond="none", alpha1=1.0)
     assert err <= 1e-8, (err, st)
+
+
+@pytest.mark.parametrize("maxit", [0, 1, 2])
+@pytest.mark.parametrize("mode", ["sound", "sound_thermal"])
+@pytest.mark.parametrize("shape,bc", [((64, 32), ("periodic", "wall")), ((16, 16, 16), ("periodic", "periodic", "wall")),
+                                      ((1024, 512), ("periodic", "wall"))])
+def test_precond_parity_few_cg_iterations(mode, shape, bc, maxit):
+    """cg_maxit = 0: each elliptic solve is one V-cycle (x = M b); 1, 2: that many CG
+    iterations (the run stops at the limit without a further V-cycle).  The preconditioner
+    and its transpose against the oracle's with the same solves (1024 x 512: the fused and
+    single-level kernels of the large levels)."""
+    from oracle.mg import PCGSolver
+    J = _lib()
+    nd = len(shape)
+    pd, X = W.random_state(shape, bc, seed=18, g=tuple([0.0] * (nd - 1) + [-1.0]), chi_model="power",
+                           chi0=0.02, amp=0.2)
+    P = Problem.from_dict(pd)
+    dt = 0.05
+    r = W.random_vector(X, 19)
+    pbp = PBP(P, X, dt, mode, solver_factory=PCGSolver.factory(1e-4, maxit))
+    ctx = J.Context(pd, precond=mode, cg_maxit=maxit)
+    ctx.set_state_n(T(X), dt)
+    ref, got = pbp.apply(r), H(ctx.precond_apply(T(X), T(r)))
+    refT, gotT = pbp.apply_T(r), H(ctx.precond_apply_transpose(T(X), T(r)))
+    for k in range(P.nvar):
+        assert np.max(np.abs(got[k] - ref[k])) <= 1e-10 * np.max(np.abs(ref[k])), k
+        assert np.max(np.abs(gotT[k] - refT[k])) <= 1e-10 * np.max(np.abs(refT[k])), k
+
+
+def test_implicit_step_single_vcycle_solves():
+    """FGMRES with the one-V-cycle preconditioner reaches the same root."""
+    w = W.polytrope((32, 32), 10.0, mach=1e-3, seed=5, chi_model="power", steps=1, cfl=50.0)
+    err, st = _step_parity(w["problem"], w["X0"], 50.0, precond="sound_thermal", cg_maxit=0)
+    assert err <= 1e-8, (err, st)
