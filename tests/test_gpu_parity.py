@@ -50,6 +50,10 @@ TINY = [
                              chi_model="power", chi0=0.05, qwall=((0, 0), (0.1, 0.2)))),
     ("3d_ragged_19x11x13", dict(shape=(19, 11, 13), bc=("wall", "periodic", "wall"), g=(0.3, 0, -1.0),
                                 chi_model="const", chi0=0.05, qwall=((0.1, -0.1), (0, 0), (0.2, 0.1)))),
+    ("2d_all_walls_7x6", dict(shape=(7, 6), bc=("wall", "wall"), g=(0.4, -1.0), chi_model="power",
+                              chi0=0.05, qwall=((0.05, -0.1), (0.1, 0.2)))),
+    ("3d_all_walls_6x5x7", dict(shape=(6, 5, 7), bc=("wall", "wall", "wall"), g=(0.2, -0.3, -1.0),
+                                chi_model="power", chi0=0.05, qwall=((0.1, 0.0), (-0.1, 0.05), (0.2, 0.1)))),
 ]
 
 
