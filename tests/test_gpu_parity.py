@@ -119,7 +119,8 @@ def test_fd_jvp_parity_small(case):
 
 @pytest.mark.parametrize("mode", ["sound", "sound_thermal"])
 @pytest.mark.parametrize("shape,bc", [((32, 16), ("periodic", "wall")), ((8, 8, 16), ("periodic", "periodic", "wall")),
-                                      ((96, 20), ("periodic", "wall"))])
+                                      ((96, 20), ("periodic", "wall")), ((24, 16), ("wall", "wall")),
+                                      ((8, 12, 8), ("wall", "wall", "wall"))])
 def test_precond_parity(mode, shape, bc):
     """(96, 20): two multigrid levels, the coarser solved exactly right below a grid level."""
     J = _lib()
