@@ -204,7 +204,7 @@ def test_pbp_transpose_radiation(mode, schur):
 
 
 def test_jfnk_radiative_thermal():
-    w = W.radiative_2d(n=12, seed=5, cfl=50.0)
+    w = W.radiative_2d(n=8, seed=5, cfl=50.0)
     P = Problem.from_dict(w["problem"])
     X0 = w["X0"]
     dt = cfl_dt(P, X0, 50.0)
@@ -218,7 +218,7 @@ def test_jfnk_radiative_thermal():
 
 @pytest.mark.parametrize("theta", [1.0, 0.5])
 def test_adjoint_step_radiation(theta):
-    P, X = _rad_case(seed=2, theta=theta)
+    P, X = _rad_case(seed=2, theta=theta, shape=(4, 6))
     dt = 0.02
     Xn1, _ = exact_step(P, X, dt)
 
