@@ -133,48 +133,6 @@ __device__ __forceinline__ double mflux(const AC& A, int d, const int* c) {
   return w * upwind(A.rho(m2), A.rho(m1), A.rho(c), A.rho(p1), w);
 }
 
-// Stages A and B walk the padded grid in tiles of kBlock cells (32 x 8 in 2D, 32 x 4 x 2 in
-// 3D, so that loads stay coalesced along x); a tile whose terms reach (at most 5 cells from
-// its cells) stays inside the grid, away from its walls, runs without ghost rules.
-template <int ND>
-__host__ __device__ constexpr int vt(int d) {
-  return ND == 2 ? (d == 0 ? 32 : (d == 1 ? 8 : 1)) : (d == 0 ? 32 : (d == 1 ? 4 : 2));
-}
-
-// logical cell of this thread and its padded index; false outside the padded grid
-template <int ND>
-__device__ __forceinline__ bool vtile_cell(const Grid& G, const PadGrid& PG, int* c, int* pl, bool* interior) {
-  int nb[3], o[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) nb[d] = (PG.P[d] + vt<ND>(d) - 1) / vt<ND>(d);
-  const int b = xcd_block(blockIdx.x, gridDim.x);
-  o[0] = (b % nb[0]) * vt<ND>(0);
-  o[1] = ((b / nb[0]) % nb[1]) * vt<ND>(1);
-  o[2] = (b / (nb[0] * nb[1])) * vt<ND>(2);
-  const int t = threadIdx.x;
-  const int l[3] = {t % vt<ND>(0), (t / vt<ND>(0)) % vt<ND>(1), t / (vt<ND>(0) * vt<ND>(1))};
-  bool in = true, ok = true;
-  int idx = 0;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const int q = o[d] + l[d];
-    ok = ok && q < PG.P[d];
-    idx += q * PG.pstride[d];
-    c[d] = (d < ND) ? q - 3 : 0;
-    if (d < ND) in = in && (o[d] - 3 >= 6) && (o[d] - 3 + vt<ND>(d) + 6 <= G.n[d]);
-  }
-  *pl = idx;
-  *interior = in;
-  return ok;
-}
-
-template <int ND>
-static int vtile_blocks(const PadGrid& PG) {
-  int b = 1;
-  for (int d = 0; d < 3; ++d) b *= (PG.P[d] + vt<ND>(d) - 1) / vt<ND>(d);
-  return b;
-}
-
 // padded index of logical cell q (coordinates clamped to the padded grid; every term that
 // reads a stored mass flux lies inside it)
 template <int ND>
@@ -198,70 +156,6 @@ __global__ void __launch_bounds__(kBlock) k_vjp_flux(Grid G, PadGrid PG, const d
   Acc<ND> A(G, X, nullptr, 0.0);
 #pragma unroll
   for (int d = 0; d < ND; ++d) mf[(size_t)d * PG.PN + pl] = mflux<ND>(A, d, c);
-}
-
-// ---- stage A: adjoint of f_d on padded faces ---------------------------------------------
-template <int ND, class AC>
-__device__ __forceinline__ void vjp_stageA_cell(const Grid& G, const PadGrid& PG, const AC& A, const int* c, int pl,
-                                                const double* mf, double* fbar) {
-  auto MF = [&](int d, const int* q) { return mf[(size_t)d * PG.PN + pad_index<ND>(PG, q)]; };
-#pragma unroll
-  for (int d = 0; d < ND; ++d) {
-    const double ih = G.idx[d];
-    SH(cm, c, d, -1);
-    double fb = (A.W(0, c) - A.W(0, cm)) * ih;  // from R_rho
-    double gb = (A.W(1, c) - A.W(1, cm)) * ih;  // energy flux g_d = f_d e*
-    if (gb != 0.0) {
-      SH(m2, c, d, -2);
-      SH(p1, c, d, 1);
-      double es = upwind(A.e(m2), A.e(cm), A.e(c), A.e(p1), A.u(d, c));
-      fb += gb * es;
-    }
-    // Phi_dd at the centres of c and c - e_d (u_d carried along d)
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      SH(cc, c, d, -k);  // centre cc lies between faces cc and cc + e_d
-      SH(cp, cc, d, 1);
-      double Pb = (A.W(2 + d, cp) - A.W(2 + d, cc)) * ih;
-      if (Pb != 0.0) {
-        double m = 0.5 * (MF(d, cc) + MF(d, cp));
-        SH(um1, cc, d, -1);
-        SH(up2, cc, d, 2);
-        double us = upwind(A.u(d, um1), A.u(d, cc), A.u(d, cp), A.u(d, up2), m);
-        fb += 0.5 * Pb * us;
-      }
-    }
-    // Phi_ed (u_e carried along d, mass flux mean of f_d[c' - e_e] and f_d[c']) at c' = c, c + e_e
-#pragma unroll
-    for (int e = 0; e < ND; ++e) {
-      if (e == d) continue;
-#pragma unroll
-      for (int k = 0; k < 2; ++k) {
-        SH(ce, c, e, k);
-        SH(ced, ce, d, -1);
-        double Pb = (A.W(2 + e, ce) - A.W(2 + e, ced)) * ih;
-        if (Pb != 0.0) {
-          SH(cee, ce, e, -1);
-          double m = 0.5 * (MF(d, cee) + MF(d, ce));
-          SH(d2, ce, d, -2);
-          SH(dp, ce, d, 1);
-          double us = upwind(A.u(e, d2), A.u(e, ced), A.u(e, ce), A.u(e, dp), m);
-          fb += 0.5 * Pb * us;
-        }
-      }
-    }
-    fbar[(size_t)d * PG.PN + pl] = fb;
-  }
-}
-
-template <int ND>
-__global__ void __launch_bounds__(kBlock) k_vjp_stageA(Grid G, PadGrid PG, const double* X, const double* w,
-                                                       double cR, const double* mf, double* fbar) {
-  int c[3], pl;
-  bool in;
-  if (!vtile_cell<ND>(G, PG, c, &pl, &in)) return;
-  if (in) vjp_stageA_cell<ND>(G, PG, Acc<ND, true>(G, X, w, cR), c, pl, mf, fbar);
-  else vjp_stageA_cell<ND>(G, PG, Acc<ND, false>(G, X, w, cR), c, pl, mf, fbar);
 }
 
 // ---- stage B: adjoint of every padded input, tiled -----------------------------------------
@@ -357,6 +251,131 @@ __device__ __forceinline__ void bscatter(const BTile<ND>& T, const int* l, bool 
     }
   }
   __syncthreads();
+}
+
+// ---- stage A: adjoint of the mass flux f_d on every padded face, tiled ------------------
+// fbar_d at face c takes R_rho's difference, the energy flux's e*, and half of each momentum
+// flux term whose carrying mass flux averages f_d at c: Phi_dd at the centres c - e_d and c,
+// Phi_ed (e != d) at the edges c and c + e_e.  Each of those terms is evaluated once per
+// tile point into LDS; a face adds the two that reach it.
+template <int ND, int B>
+__host__ __device__ constexpr int pext(int i) {
+  return i >= ND ? 1 : (i == B ? bt<ND>(i) + 1 : bt<ND>(i));
+}
+template <int ND, int B>
+__host__ __device__ constexpr int ppoints() {
+  return pext<ND, B>(0) * pext<ND, B>(1) * pext<ND, B>(2);
+}
+template <int ND>
+__host__ __device__ constexpr int ppoints_max() {
+  return ND == 2 ? bmax(ppoints<2, 0>(), ppoints<2, 1>())
+                 : bmax(ppoints<3, 0>(), bmax(ppoints<3, 1>(), ppoints<3, 2>()));
+}
+// term values at points [LO, LO + T_B + 1) along B (tile-local; LO = -1 or 0); the thread's
+// own cell l gets the sum of the entries at l and at l - e_B (LO = -1) or l + e_B (LO = 0)
+template <int ND, int B, int LO, class VF>
+__device__ __forceinline__ double bpair(const BTile<ND>& T, const int* l, bool own, double* sV, const VF& val) {
+  constexpr int E0 = pext<ND, B>(0), E1 = pext<ND, B>(1), E2 = pext<ND, B>(2);
+  constexpr int NP = E0 * E1 * E2;
+  for (int p = threadIdx.x; p < NP; p += kBlock) {
+    int f[3] = {p % E0, (p / E0) % E1, p / (E0 * E1)};
+    f[B] += LO;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) f[d] += T.o[d];
+    sV[p] = val(f);
+  }
+  __syncthreads();
+  double r = 0.0;
+  if (own) {
+    int q[3] = {l[0], l[1], l[2]};
+    q[B] -= LO;
+    const int i1 = q[0] + q[1] * E0 + q[2] * E0 * E1;
+    q[B] += (LO == -1) ? -1 : 1;
+    const int i2 = q[0] + q[1] * E0 + q[2] * E0 * E1;
+    r = sV[i1] + sV[i2];
+  }
+  __syncthreads();
+  return r;
+}
+
+template <int ND, int D, class AC>
+__device__ __forceinline__ double vjp_faceA(const Grid& G, const PadGrid& PG, const AC& Ac, const BTile<ND>& T,
+                                            const int* l, const int* c, bool own, const double* mf, double* sV) {
+  const double ih = G.idx[D];
+  auto MF = [&](int d, const int* q) { return mf[(size_t)d * PG.PN + pad_index<ND>(PG, q)]; };
+  // Phi_DD at the centre between faces cc and cc + e_D, for cc = c - e_D and c
+  double fb = bpair<ND, D, -1>(T, l, own, sV, [&](const int* cc) -> double {
+    SH(cp, cc, D, 1);
+    const double Pb = (Ac.W(2 + D, cp) - Ac.W(2 + D, cc)) * ih;
+    if (Pb == 0.0) return 0.0;
+    const double m = 0.5 * (MF(D, cc) + MF(D, cp));
+    SH(um1, cc, D, -1);
+    SH(up2, cc, D, 2);
+    return 0.5 * Pb * upwind(Ac.u(D, um1), Ac.u(D, cc), Ac.u(D, cp), Ac.u(D, up2), m);
+  });
+  // Phi_eD (u_e carried along D) at the edges ce = c and c + e_e
+#pragma unroll
+  for (int e = 0; e < ND; ++e) {
+    if (e == D) continue;
+    auto val = [&](const int* ce) -> double {
+      SH(ced, ce, D, -1);
+      const double Pb = (Ac.W(2 + e, ce) - Ac.W(2 + e, ced)) * ih;
+      if (Pb == 0.0) return 0.0;
+      SH(cee, ce, e, -1);
+      const double m = 0.5 * (MF(D, cee) + MF(D, ce));
+      SH(d2, ce, D, -2);
+      SH(dp, ce, D, 1);
+      return 0.5 * Pb * upwind(Ac.u(e, d2), Ac.u(e, ced), Ac.u(e, ce), Ac.u(e, dp), m);
+    };
+    if (e == 0) fb += bpair<ND, 0, 0>(T, l, own, sV, val);
+    else if (e == 1) fb += bpair<ND, 1, 0>(T, l, own, sV, val);
+    else fb += bpair<ND, (ND == 3 ? 2 : 1), 0>(T, l, own, sV, val);
+  }
+  if (!own) return 0.0;
+  // R_rho's difference and the energy flux g_D = f_D e*
+  SH(cm, c, D, -1);
+  fb += (Ac.W(0, c) - Ac.W(0, cm)) * ih;
+  const double gb = (Ac.W(1, c) - Ac.W(1, cm)) * ih;
+  if (gb != 0.0) {
+    SH(m2, c, D, -2);
+    SH(p1, c, D, 1);
+    fb += gb * upwind(Ac.e(m2), Ac.e(cm), Ac.e(c), Ac.e(p1), Ac.u(D, c));
+  }
+  return fb;
+}
+
+template <int ND, class AC>
+__device__ __forceinline__ void vjp_tileA(const Grid& G, const PadGrid& PG, const AC& Ac, const BTile<ND>& T,
+                                          const double* mf, double* fbar, double* sV) {
+  const int t = threadIdx.x;
+  const int l[3] = {t % bt<ND>(0), (t / bt<ND>(0)) % bt<ND>(1), t / (bt<ND>(0) * bt<ND>(1))};
+  int c[3], pl = 0;
+  bool own = true;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    c[d] = T.o[d] + l[d];
+    if (d < ND) {
+      own = own && (c[d] + 3 < PG.P[d]);
+      pl += (c[d] + 3) * PG.pstride[d];
+    }
+  }
+  const double f0 = vjp_faceA<ND, 0>(G, PG, Ac, T, l, c, own, mf, sV);
+  const double f1 = vjp_faceA<ND, 1>(G, PG, Ac, T, l, c, own, mf, sV);
+  double f2 = 0.0;
+  if constexpr (ND == 3) f2 = vjp_faceA<ND, 2>(G, PG, Ac, T, l, c, own, mf, sV);
+  if (!own) return;
+  fbar[pl] = f0;
+  fbar[(size_t)PG.PN + pl] = f1;
+  if constexpr (ND == 3) fbar[(size_t)2 * PG.PN + pl] = f2;
+}
+
+template <int ND>
+__global__ void __launch_bounds__(kBlock) k_vjp_stageA(Grid G, PadGrid PG, const double* X, const double* w,
+                                                       double cR, const double* mf, double* fbar) {
+  __shared__ double sV[ppoints_max<ND>()];
+  const BTile<ND> T = btile_setup<ND>(G, PG);
+  if (T.interior) vjp_tileA<ND>(G, PG, Acc<ND, true>(G, X, w, cR), T, mf, fbar, sV);
+  else vjp_tileA<ND>(G, PG, Acc<ND, false>(G, X, w, cR), T, mf, fbar, sV);
 }
 
 // the passes along axis A: mass and energy fluxes (to rho, e), Phi_AA (to u_A), and Phi_dA
@@ -859,7 +878,6 @@ void launch_vjp(const Grid& G, const double* X, const double* w, double cU, doub
   double* xbar = scratch + (size_t)G.nd * PG.PN;
   double* mf = xbar + (size_t)(2 + G.nd) * PG.PN;
   dim3 gp((PG.PN + kBlock - 1) / kBlock), gc((G.N + kBlock - 1) / kBlock), bl(kBlock);
-  dim3 gt(G.nd == 2 ? vtile_blocks<2>(PG) : vtile_blocks<3>(PG));
   const double nv = 2 + G.nd;
   {
     const double by = 8.0 * (3.0 * G.N + G.nd * (double)PG.PN);
@@ -869,8 +887,9 @@ void launch_vjp(const Grid& G, const double* X, const double* w, double cU, doub
   const double* mfc = mf;
   {
     const double by = 8.0 * (2 * nv * G.N + 2 * G.nd * (double)PG.PN);
-    if (G.nd == 2) launch_k(KF_VJP_A, by, k_vjp_stageA<2>, gt, bl, 0, s, G, PG, X, w, cR, mfc, fbar);
-    else launch_k(KF_VJP_A, by, k_vjp_stageA<3>, gt, bl, 0, s, G, PG, X, w, cR, mfc, fbar);
+    const dim3 ga(G.nd == 2 ? btile_blocks<2>(PG) : btile_blocks<3>(PG));
+    if (G.nd == 2) launch_k(KF_VJP_A, by, k_vjp_stageA<2>, ga, bl, 0, s, G, PG, X, w, cR, mfc, fbar);
+    else launch_k(KF_VJP_A, by, k_vjp_stageA<3>, ga, bl, 0, s, G, PG, X, w, cR, mfc, fbar);
   }
   {
     const double by = 8.0 * (2 * nv * G.N + (2 * G.nd + nv) * (double)PG.PN);
