@@ -446,8 +446,9 @@ int pcg(jfnk_ctx* c, std::vector<Level>& lv, const double* Ainv, const T* b, T* 
   for (;;) {
     for (int k = 0; k < batch && enq < g.maxit; ++k) {
       const int it = ++enq;
-      // after the last allowed iteration only the decision is needed, not the next V-cycle
-      const bool last = (enq == g.maxit);
+      // the last iteration of a batch (or the last allowed one) only takes the decision: the
+      // next V-cycle is enqueued after the host has read it, and only if the solve goes on
+      const bool last = (enq == g.maxit) || (k == batch - 1);
       launch_cg_apply<T>(G, lv[0], z, pold, pnew, q, x, g, it, s);
       launch_cg_update<T>(G, lv[0], rold, q, pnew, x, rnew, (l0 >= 1 && !last) ? z : nullptr, g, it, s);
       if (last) {
@@ -470,6 +471,17 @@ int pcg(jfnk_ctx* c, std::vector<Level>& lv, const double* Ainv, const T* b, T* 
     HIPX(hipMemcpyAsync(c->hctl, c->ctl, sizeof(CGCtl), hipMemcpyDeviceToHost, s));
     sync(c);
     if (c->hctl->flag != 0 || enq >= g.maxit) break;
+    // the solve goes on: z = M r for the last residual (with the first level-0 smoothing that
+    // the update kernel skipped); the repeated decision in the V-cycle finds "go on" again
+    if (l0 >= 1) {
+      launch_mg_presmooth<T>(G, lv[0], rold, z, g, false, s);
+      vcycle_rest<T>(c, lv, Ainv, rold, z, g, enq);
+    } else if (fused) {
+      launch_vcycle_coarse<T>(G, &lv[0], nl, Ainv, rold, z, g, kCoarseConv | kCoarseRZ, enq, s);
+    } else {
+      launch_dense_matvec<T>(N, Ainv, rold, z, g, s);
+      launch_cg_dot_rz<T>(N, rold, z, g, s);
+    }
     batch = 1;
   }
   if (c->hctl->flag < 0) throw FiniteErr("non-finite residual in an elliptic solve");
