@@ -110,7 +110,7 @@ __global__ void __launch_bounds__(kBlock) k_ell_coef(Grid G, const double* X, do
   const bool rad = G.a_rad != 0.0;
   const double rho = X[lin], e = X[G.N + lin];
   double* w[3] = {w0, w1, w2};
-  Thermo th;
+  Thermo th{};
   if (rad) th = thermo<true>(G, rho, e);
   // pressure: 1/(Gamma1 p dt); thermal: rho c_v/dt with c_v = de/dT|_rho
   if (op == 0) {
