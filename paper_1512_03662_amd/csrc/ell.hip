@@ -80,6 +80,36 @@ __device__ __forceinline__ T apply_at(const LV<T>& L, const int* c, int lin, con
   return apply_nb<T, ND>(L, c, lin, [&](int, int, int k) { return phi(k); }, phic);
 }
 
+// A's row at one cell (diagonal, face weights, neighbour indices), loaded ahead of a kernel's
+// LDS phase so that its memory latency overlaps that phase; apply_row then evaluates the row
+// exactly as apply_nb does
+template <class T, int ND>
+struct RowCoef {
+  T diag, wl[3], wu[3];
+  int cm[3], cp[3];
+};
+template <class T, int ND>
+__device__ __forceinline__ RowCoef<T, ND> row_coef(const LV<T>& L, const int* c, int lin) {
+  RowCoef<T, ND> r;
+  r.diag = L.diag[lin];
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    const int n = L.n[d], st = L.stride[d];
+    r.cm[d] = (c[d] == 0) ? lin + (n - 1) * st : lin - st;
+    r.cp[d] = (c[d] == n - 1) ? lin - (n - 1) * st : lin + st;
+    r.wl[d] = L.w[d][lin];
+    r.wu[d] = (L.bc[d] == 1 && c[d] == n - 1) ? T(0) : L.w[d][r.cp[d]];
+  }
+  return r;
+}
+template <class T, int ND, class F>
+__device__ __forceinline__ T apply_row(const RowCoef<T, ND>& r, const F& nb, T phic) {
+  T out = r.diag * phic;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) out -= r.wu[d] * (nb(d, 1, r.cp[d]) - phic) - r.wl[d] * (phic - nb(d, -1, r.cm[d]));
+  return out;
+}
+
 // restricted residual (mean over the 2^ND children of b - A x) of coarse cell cc
 template <class T, int ND>
 __device__ __forceinline__ T restrict_at(const LV<T>& F, const T* b, const T* x, const int* cc) {
@@ -463,6 +493,23 @@ __global__ void __launch_bounds__(kBlock) k_mg_down(LV<T> F, const T* bf, const 
   }
   int o[3];
   tile_origin<ND>(C.n, o);
+  const int t = threadIdx.x;
+  const int l[3] = {t % TD::X, (t / TD::X) % TD::Y, t / (TD::X * TD::Y)};
+  int c[3] = {o[0] + l[0], o[1] + l[1], (ND == 3) ? o[2] + l[2] : 0};
+  const bool own = c[0] < C.n[0] && c[1] < C.n[1] && (ND < 3 || c[2] < C.n[2]);
+  const int lin = own ? c[0] * C.stride[0] + c[1] * C.stride[1] + c[2] * C.stride[2] : 0;
+  // the coarse row and the smoother's diagonal around it, ahead of the restriction phase
+  RowCoef<T, ND> rc{};
+  T dv = T(0), dvm[3] = {T(0), T(0), T(0)}, dvp[3] = {T(0), T(0), T(0)};
+  if (own) {
+    rc = row_coef<T, ND>(C, c, lin);
+    dv = C.dinv[lin];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      dvm[d] = C.dinv[rc.cm[d]];
+      dvp[d] = C.dinv[rc.cp[d]];
+    }
+  }
   for (int h = threadIdx.x; h < HN; h += kBlock) {
     const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
     int cc[3] = {wrapc(o[0] + hx - 1, C.n[0]), wrapc(o[1] + hy - 1, C.n[1]),
@@ -470,20 +517,16 @@ __global__ void __launch_bounds__(kBlock) k_mg_down(LV<T> F, const T* bf, const 
     sb[h] = restrict_at<T, ND>(F, bf, xf, cc);
   }
   __syncthreads();
-  const int t = threadIdx.x;
-  const int l[3] = {t % TD::X, (t / TD::X) % TD::Y, t / (TD::X * TD::Y)};
-  int c[3] = {o[0] + l[0], o[1] + l[1], (ND == 3) ? o[2] + l[2] : 0};
-  if (c[0] >= C.n[0] || c[1] >= C.n[1] || (ND == 3 && c[2] >= C.n[2])) return;
-  const int lin = c[0] * C.stride[0] + c[1] * C.stride[1] + c[2] * C.stride[2];
+  if (!own) return;
   const int hs[3] = {1, HX, HX * HY};
   const int hc = (l[0] + 1) + (l[1] + 1) * HX + ((ND == 3) ? (l[2] + 1) * HX * HY : 0);
   const T bcen = sb[hc];
   bc[lin] = bcen;
   const T th = T(1.0 / kChebTheta);
-  auto x1 = [&](int d, int s, int k) { return C.dinv[k] * sb[hc + s * hs[d]] * th; };
-  const T x1c = C.dinv[lin] * bcen * th;
-  const T Ax = apply_nb<T, ND>(C, c, lin, x1, x1c);
-  xc[lin] = (T(1.0) + T(kChebC1)) * x1c + T(kChebC2) * C.dinv[lin] * (bcen - Ax);
+  auto x1 = [&](int d, int s, int) { return (s < 0 ? dvm[d] : dvp[d]) * sb[hc + s * hs[d]] * th; };
+  const T x1c = dv * bcen * th;
+  const T Ax = apply_row<T, ND>(rc, x1, x1c);
+  xc[lin] = (T(1.0) + T(kChebC1)) * x1c + T(kChebC2) * dv * (bcen - Ax);
 }
 
 // second smoothing step of level C on the parents of F's tile and their halo (in LDS), then
@@ -499,6 +542,25 @@ __global__ void __launch_bounds__(kBlock) k_mg_up(LV<T> C, const T* bc, const T*
   int o[3];
   tile_origin<ND>(F.n, o);
   const int p0[3] = {o[0] / 2, o[1] / 2, o[2] / 2};
+  const int t = threadIdx.x;
+  const int l[3] = {t % TD::X, (t / TD::X) % TD::Y, t / (TD::X * TD::Y)};
+  int c[3] = {o[0] + l[0], o[1] + l[1], (ND == 3) ? o[2] + l[2] : 0};
+  const bool own = c[0] < F.n[0] && c[1] < F.n[1] && (ND < 3 || c[2] < F.n[2]);
+  const int lin = own ? c[0] * F.stride[0] + c[1] * F.stride[1] + c[2] * F.stride[2] : 0;
+  // the fine row, the fine iterate around it, b and the diagonal, ahead of the LDS phase
+  RowCoef<T, ND> rf{};
+  T x2c = T(0), x2m[3] = {T(0), T(0), T(0)}, x2p[3] = {T(0), T(0), T(0)}, bfc = T(0), dvf = T(0);
+  if (own) {
+    rf = row_coef<T, ND>(F, c, lin);
+    x2c = x2f[lin];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      x2m[d] = x2f[rf.cm[d]];
+      x2p[d] = x2f[rf.cp[d]];
+    }
+    bfc = bf[lin];
+    dvf = F.dinv[lin];
+  }
   auto t1 = [&](int k) { return t1c[k]; };
   for (int h = threadIdx.x; h < PN; h += kBlock) {
     const int hx = h % PX, hy = (h / PX) % PY, hz = h / (PX * PY);
@@ -510,25 +572,21 @@ __global__ void __launch_bounds__(kBlock) k_mg_up(LV<T> C, const T* bc, const T*
     sx[h] = x1c + T(kChebC1) * t2c[k] + T(kChebC2) * C.dinv[k] * r1;
   }
   __syncthreads();
-  const int t = threadIdx.x;
-  const int l[3] = {t % TD::X, (t / TD::X) % TD::Y, t / (TD::X * TD::Y)};
-  int c[3] = {o[0] + l[0], o[1] + l[1], (ND == 3) ? o[2] + l[2] : 0};
-  if (c[0] >= F.n[0] || c[1] >= F.n[1] || (ND == 3 && c[2] >= F.n[2])) return;
-  const int lin = c[0] * F.stride[0] + c[1] * F.stride[1] + c[2] * F.stride[2];
+  if (!own) return;
   // LDS position of the parent of the fine cell f (unwrapped, at most one step from the tile)
   auto ppos = [&](const int* f) {
     int p = ((f[0] >> 1) - p0[0] + 1) + ((f[1] >> 1) - p0[1] + 1) * PX;
     if (ND == 3) p += ((f[2] >> 1) - p0[2] + 1) * PX * PY;
     return p;
   };
-  const T xpc = x2f[lin] + sx[ppos(c)];
-  auto xp = [&](int d, int s, int k) {
+  const T xpc = x2c + sx[ppos(c)];
+  auto xp = [&](int d, int s, int) {
     int f[3] = {c[0], c[1], c[2]};
     f[d] += s;
-    return x2f[k] + sx[ppos(f)];
+    return (s < 0 ? x2m[d] : x2p[d]) + sx[ppos(f)];
   };
-  const T r0 = bf[lin] - apply_nb<T, ND>(F, c, lin, xp, xpc);
-  const T dd = F.dinv[lin] * r0 * T(1.0 / kChebTheta);
+  const T r0 = bfc - apply_row<T, ND>(rf, xp, xpc);
+  const T dd = dvf * r0 * T(1.0 / kChebTheta);
   t1f[lin] = xpc + dd;
   t2f[lin] = dd;
 }
