@@ -450,7 +450,7 @@ __global__ void __launch_bounds__(kBlock) k_resid_value(Grid G, ResidArgs a) {
 }
 
 template <int ND, bool RAD>
-__global__ void __launch_bounds__(kBlock) k_resid_tangent(Grid G, ResidArgs a) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) k_resid_tangent(Grid G, ResidArgs a) {
   LoadDual ld{a.X, a.V, G.N};
   dual R[2 + ND], U[2 + ND];
   double L[2 + ND];

@@ -585,7 +585,7 @@ __device__ __forceinline__ void vjp_tileB(const Grid& G, const PadGrid& PG, cons
 }
 
 template <int ND, bool RAD>
-__global__ void __launch_bounds__(kBlock) k_vjp_stageB(Grid G, PadGrid PG, const double* X, const double* w,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) k_vjp_stageB(Grid G, PadGrid PG, const double* X, const double* w,
                                                        double cR, const double* mf, const double* fbar,
                                                        double* xbar) {
   __shared__ double sC[8 * bfaces_max<ND>()];
