@@ -437,6 +437,234 @@ __global__ void __launch_bounds__(kBlock) k_mg_smooth2(LV<T> L, const T* b, cons
   if (RZ) block_partial((double)acc, g.part + kPartRZ * kRedBlocks);
 }
 
+// ---- z-marching forms of the single-level kernels on 3D grids ---------------------------
+// A block owns kZX x kZY columns of cells (x contiguous) and walks them along z through a
+// chunk of planes.  The state a cell's stencil needs from its z neighbours is carried in
+// registers from one plane to the next, so no plane is fetched a second time for the z+1 or
+// z-1 neighbour of another cell (the grid-stride forms above read those planes again, from
+// another XCD's L2 or from memory).  The launch has exactly cg_partials(N) blocks (one
+// partial each where the kernel writes partials); blocks past the last chunk have no cells.
+constexpr int kZX = 64, kZY = 4;
+static_assert(kZX * kZY == kBlock, "one cell column per thread");
+
+struct ZChunk {
+  int cx, cy, z0, z1;  // the thread's column and its planes [z0, z1); z0 >= z1: no cells
+};
+__device__ __forceinline__ ZChunk zchunk(const int* n, int zc) {
+  const int nbx = (n[0] + kZX - 1) / kZX, nby = (n[1] + kZY - 1) / kZY;
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int tile = b % (nbx * nby), chunk = b / (nbx * nby);
+  ZChunk z;
+  z.cx = (tile % nbx) * kZX + (int)threadIdx.x % kZX;
+  z.cy = (tile / nbx) * kZY + (int)threadIdx.x / kZX;
+  z.z0 = chunk * zc;
+  z.z1 = min(z.z0 + zc, n[2]);
+  if (z.cx >= n[0] || z.cy >= n[1]) z.z1 = z.z0;
+  return z;
+}
+
+// Walks the thread's column: st(i, x, y, z) is the per-cell state at cell i (coordinates
+// x, y, z), val(state) the value the stencil applies A to; emit(lin, z, state, A val) is
+// called for every cell of the chunk in increasing z.  The row is evaluated in apply_nb's
+// order, with the z neighbours' values and the upper z face weight taken from the carried
+// planes.
+template <class T, class St, class Val, class Emit>
+__device__ __forceinline__ void zmarch(const LV<T>& L, const ZChunk& zc, const St& st, const Val& val,
+                                       const Emit& emit) {
+  if (zc.z0 >= zc.z1) return;
+  const int nz = L.n[2], sz = L.stride[2];
+  const int col = zc.cx + zc.cy * L.stride[1];
+  const int c[2] = {zc.cx, zc.cy};
+  int lin = col + zc.z0 * sz;
+  const int zm0 = (zc.z0 == 0) ? nz - 1 : zc.z0 - 1;
+  auto vm = val(st(col + zm0 * sz, zc.cx, zc.cy, zm0));
+  auto sc = st(lin, zc.cx, zc.cy, zc.z0);
+  T w2c = L.w[2][lin];
+  for (int z = zc.z0; z < zc.z1; ++z, lin += sz) {
+    const int zn = (z == nz - 1) ? 0 : z + 1;
+    const int ln = col + zn * sz;
+    const auto sn = st(ln, zc.cx, zc.cy, zn);
+    const T w2n = L.w[2][ln];
+    const T pc = val(sc);
+    T out = L.diag[lin] * pc;
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      const int n = L.n[d], s = L.stride[d];
+      const int cm = (c[d] == 0) ? lin + (n - 1) * s : lin - s;
+      const int cp = (c[d] == n - 1) ? lin - (n - 1) * s : lin + s;
+      int qm[2] = {c[0], c[1]}, qp[2] = {c[0], c[1]};
+      qm[d] = (c[d] == 0) ? n - 1 : c[d] - 1;
+      qp[d] = (c[d] == n - 1) ? 0 : c[d] + 1;
+      const T wl = L.w[d][lin];
+      const T wu = (L.bc[d] == 1 && c[d] == n - 1) ? T(0) : L.w[d][cp];
+      out -= wu * (val(st(cp, qp[0], qp[1], z)) - pc) - wl * (pc - val(st(cm, qm[0], qm[1], z)));
+    }
+    {
+      const T wu = (L.bc[2] == 1 && z == nz - 1) ? T(0) : w2n;
+      out -= wu * (val(sn) - pc) - w2c * (pc - vm);
+    }
+    emit(lin, z, sc, out);
+    vm = pc;
+    sc = sn;
+    w2c = w2n;
+  }
+}
+
+template <class T>
+struct UpdSt {
+  T r, dv, x1;  // new residual, inverse diagonal, first smoothing iterate
+};
+
+// k_cg_update<T, 3, true> in z-marching form
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_cg_update_zm(LV<T> L, const T* rold, const T* q, const T* p, T* x,
+                                                         T* rnew, T* xm, CGArgs g, int it, int zc) {
+  CGCtl* S = g.ctl;
+  if (S->flag) return;
+  if (it == 1 && S->bb == 0.0) {  // b = 0: x = 0 was written by the apply kernel
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      S->its = 0;
+      S->flag = 1;
+    }
+    return;
+  }
+  const double pq = block_sum_parts(g.part + kPartPQ * kRedBlocks, g.np);
+  const T al = (T)(S->rz[(it - 1) & 1] / pq);
+  const T th = T(1.0 / kChebTheta);
+  auto st = [&](int i, int, int, int) {
+    UpdSt<T> u;
+    u.r = rold[i] - al * q[i];
+    u.dv = L.dinv[i];
+    u.x1 = u.dv * u.r * th;
+    return u;
+  };
+  auto val = [](const UpdSt<T>& u) { return u.x1; };
+  T acc = T(0);
+  auto emit = [&](int lin, int, const UpdSt<T>& u, T Ax) {
+    const T xo = (it == 1) ? T(0) : x[lin];
+    x[lin] = xo + al * p[lin];
+    rnew[lin] = u.r;
+    acc += u.r * u.r;
+    xm[lin] = (T(1.0) + T(kChebC1)) * u.x1 + T(kChebC2) * u.dv * (u.r - Ax);
+  };
+  zmarch<T>(L, zchunk(L.n, zc), st, val, emit);
+  block_partial((double)acc, g.part + kPartRR * kRedBlocks);
+}
+
+// k_cg_apply<T, 3> in z-marching form
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_cg_apply_zm(LV<T> L, const T* z, const T* pold, T* pnew, T* q, T* x,
+                                                        CGArgs g, int it, int zc) {
+  CGCtl* S = g.ctl;
+  if (S->flag) return;
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  const double rz = block_sum_parts(g.part + kPartRZ * kRedBlocks, g.np);
+  double beta = 0.0;
+  if (it == 1) {
+    const double bb = block_sum_parts(g.part + kPartBB * kRedBlocks, g.np);
+    if (lead) S->bb = bb;
+    if (bb == 0.0) {  // the update kernel of this iteration ends the solve
+      FOR_CELLS(lin, L.N) x[lin] = T(0);
+      return;
+    }
+  } else {
+    beta = rz / S->rz[it & 1];
+  }
+  if (lead) S->rz[(it - 1) & 1] = rz;
+  const T bt = (T)beta;
+  const T* po = (it == 1) ? z : pold;
+  auto st = [&](int i, int, int, int) { return z[i] + bt * po[i]; };
+  auto val = [](T v) { return v; };
+  T acc = T(0);
+  auto emit = [&](int lin, int, T pc, T qv) {
+    pnew[lin] = pc;
+    q[lin] = qv;
+    acc += pc * qv;
+  };
+  zmarch<T>(L, zchunk(L.n, zc), st, val, emit);
+  block_partial((double)acc, g.part + kPartPQ * kRedBlocks);
+}
+
+template <class T>
+struct PreSt {
+  T b, dv, x1;  // right-hand side, inverse diagonal, first smoothing iterate
+};
+
+// k_mg_presmooth<T, 3, INIT> in z-marching form
+template <class T, bool INIT>
+__global__ void __launch_bounds__(kBlock) k_mg_presmooth_zm(LV<T> L, const T* b, T* x, CGArgs g, int zc) {
+  if (INIT) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      g.ctl->flag = 0;
+      g.ctl->its = 0;
+    }
+  } else if (g.ctl->flag) {
+    return;
+  }
+  const T th = T(1.0 / kChebTheta);
+  auto st = [&](int i, int, int, int) {
+    PreSt<T> u;
+    u.b = b[i];
+    u.dv = L.dinv[i];
+    u.x1 = u.dv * u.b * th;
+    return u;
+  };
+  auto val = [](const PreSt<T>& u) { return u.x1; };
+  T acc = T(0);
+  auto emit = [&](int lin, int, const PreSt<T>& u, T Ax) {
+    x[lin] = (T(1.0) + T(kChebC1)) * u.x1 + T(kChebC2) * u.dv * (u.b - Ax);
+    if (INIT) acc += u.b * u.b;
+  };
+  zmarch<T>(L, zchunk(L.n, zc), st, val, emit);
+  if (INIT) block_partial((double)acc, g.part + kPartBB * kRedBlocks);
+}
+
+// k_mg_smooth2<T, 3, RZ> in z-marching form
+template <class T, bool RZ>
+__global__ void __launch_bounds__(kBlock) k_mg_smooth2_zm(LV<T> L, const T* b, const T* x1, const T* d0, T* x,
+                                                          CGArgs g, int zc) {
+  if (g.ctl->flag) return;
+  auto st = [&](int i, int, int, int) { return x1[i]; };
+  auto val = [](T v) { return v; };
+  T acc = T(0);
+  auto emit = [&](int lin, int, T x1c, T Ax) {
+    const T r1 = b[lin] - Ax;
+    const T xn = x1c + T(kChebC1) * d0[lin] + T(kChebC2) * L.dinv[lin] * r1;
+    x[lin] = xn;
+    if (RZ) acc += b[lin] * xn;
+  };
+  zmarch<T>(L, zchunk(L.n, zc), st, val, emit);
+  if (RZ) block_partial((double)acc, g.part + kPartRZ * kRedBlocks);
+}
+
+// k_mg_prolong_smooth1<T, 3> in z-marching form
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_mg_prolong_smooth1_zm(LV<T> L, const T* b, const T* x2, const T* xc,
+                                                                  int cs0, int cs1, int cs2, T* x1, T* d0,
+                                                                  CGArgs g, int zc) {
+  if (g.ctl->flag) return;
+  auto st = [&](int i, int cx, int cy, int cz) {
+    return x2[i] + xc[(cx >> 1) * cs0 + (cy >> 1) * cs1 + (cz >> 1) * cs2];
+  };
+  auto val = [](T v) { return v; };
+  auto emit = [&](int lin, int, T xpc, T Ax) {
+    const T r0 = b[lin] - Ax;
+    const T dd = L.dinv[lin] * r0 * T(1.0 / kChebTheta);
+    x1[lin] = xpc + dd;
+    d0[lin] = dd;
+  };
+  zmarch<T>(L, zchunk(L.n, zc), st, val, emit);
+}
+
+// planes per chunk of the z-marching forms on level L, or 0 when its columns outnumber the
+// partials (the grid-stride forms are used then)
+static int zm_chunk(const Level& L) {
+  const int nbx = (L.n[0] + kZX - 1) / kZX, nby = (L.n[1] + kZY - 1) / kZY;
+  const int per = cg_partials((size_t)L.N) / (nbx * nby);
+  if (per < 1) return 0;
+  return (L.n[2] + per - 1) / per;
+}
+
 // ---- fused level pairs on LDS tiles ----------------------------------------------------
 // One workgroup owns a tile of kBlock cells (16 x 16 in 2D, 8 x 8 x 4 in 3D) of the level it
 // writes; the intermediate coarse vector lives in LDS with a halo of one cell, recomputed by
@@ -634,6 +862,14 @@ void launch_mg_presmooth(const Grid& G, const Level& L, const T* b, T* x, const 
                          hipStream_t s) {
   LV<T> v = view<T>(G, L);
   const double by = (4.0 + G.nd) * L.N * (double)sizeof(T);
+  if (G.nd == 3) {
+    if (const int zc = zm_chunk(L)) {
+      dim3 gr(red_grid(L.N)), bl(kBlock);
+      if (init) launch_k(KF_MG_PRE, by, k_mg_presmooth_zm<T, true>, gr, bl, 0, s, v, b, x, g, zc);
+      else launch_k(KF_MG_PRE, by, k_mg_presmooth_zm<T, false>, gr, bl, 0, s, v, b, x, g, zc);
+      return;
+    }
+  }
   if (init) {
     dim3 gr(red_grid(L.N)), bl(kBlock);
     if (G.nd == 2) launch_k(KF_MG_PRE, by, k_mg_presmooth<T, 2, true>, gr, bl, 0, s, v, b, x, g);
@@ -669,6 +905,13 @@ void launch_mg_prolong_smooth1(const Grid& G, const Level& f, const T* b, const 
                                const Level& c, T* x1, T* d0, const CGArgs& g, hipStream_t s) {
   LV<T> v = view<T>(G, f);
   const double by = ((6.0 + G.nd) * f.N + c.N) * (double)sizeof(T);
+  if (G.nd == 3) {
+    if (const int zc = zm_chunk(f)) {
+      launch_k(KF_MG_PROLONG, by, k_mg_prolong_smooth1_zm<T>, dim3(red_grid(f.N)), dim3(kBlock), 0, s, v, b, x2,
+               xc, c.stride[0], c.stride[1], c.stride[2], x1, d0, g, zc);
+      return;
+    }
+  }
   if (G.nd == 2)
     launch_k(KF_MG_PROLONG, by, k_mg_prolong_smooth1<T, 2>, CELLS(f.N), 0, s, v, b, x2, xc, c.stride[0],
              c.stride[1], c.stride[2], x1, d0, g);
@@ -681,6 +924,14 @@ void launch_mg_smooth2(const Grid& G, const Level& L, const T* b, const T* x1, c
                        const CGArgs& g, bool rz, hipStream_t s) {
   LV<T> v = view<T>(G, L);
   const double by = (6.0 + G.nd) * L.N * (double)sizeof(T);
+  if (G.nd == 3) {
+    if (const int zc = zm_chunk(L)) {
+      dim3 gr(red_grid(L.N)), bl(kBlock);
+      if (rz) launch_k(KF_MG_SMOOTH2, by, k_mg_smooth2_zm<T, true>, gr, bl, 0, s, v, b, x1, d0, x, g, zc);
+      else launch_k(KF_MG_SMOOTH2, by, k_mg_smooth2_zm<T, false>, gr, bl, 0, s, v, b, x1, d0, x, g, zc);
+      return;
+    }
+  }
   if (rz) {
     dim3 gr(red_grid(L.N)), bl(kBlock);
     if (G.nd == 2) launch_k(KF_MG_SMOOTH2, by, k_mg_smooth2<T, 2, true>, gr, bl, 0, s, v, b, x1, d0, x, g);
@@ -1031,157 +1282,6 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(LV<T> L, const T* rold, co
     }
   }
   block_partial((double)acc, g.part + kPartRR * kRedBlocks);
-}
-
-// ---- z-marching forms of the level-0 CG kernels on 3D grids ------------------------------
-// A block owns kZX x kZY columns of cells (x contiguous) and walks them along z through a
-// chunk of planes.  The state a cell's stencil needs from its z neighbours is carried in
-// registers from one plane to the next, so no plane is fetched a second time for the z+1 or
-// z-1 neighbour of another cell (the grid-stride forms above read those planes again, from
-// another XCD's L2 or from memory).  The launch has exactly cg_partials(N) blocks (one
-// partial each); blocks past the last chunk only write a zero partial.
-constexpr int kZX = 64, kZY = 4;
-static_assert(kZX * kZY == kBlock, "one cell column per thread");
-
-struct ZChunk {
-  int cx, cy, z0, z1;  // the thread's column and its planes [z0, z1); z0 >= z1: no cells
-};
-__device__ __forceinline__ ZChunk zchunk(const int* n, int zc) {
-  const int nbx = (n[0] + kZX - 1) / kZX, nby = (n[1] + kZY - 1) / kZY;
-  const int b = xcd_block(blockIdx.x, gridDim.x);
-  const int tile = b % (nbx * nby), chunk = b / (nbx * nby);
-  ZChunk z;
-  z.cx = (tile % nbx) * kZX + (int)threadIdx.x % kZX;
-  z.cy = (tile / nbx) * kZY + (int)threadIdx.x / kZX;
-  z.z0 = chunk * zc;
-  z.z1 = min(z.z0 + zc, n[2]);
-  if (z.cx >= n[0] || z.cy >= n[1]) z.z1 = z.z0;
-  return z;
-}
-
-// Walks the thread's column: st(i) is the per-cell state at cell i, val(state) the value the
-// stencil applies A to; emit(lin, state, A val) is called for every cell of the chunk in
-// increasing z.  The row is evaluated in apply_nb's order, with the z neighbours' values and
-// the upper z face weight taken from the carried planes.
-template <class T, class St, class Val, class Emit>
-__device__ __forceinline__ void zmarch(const LV<T>& L, const ZChunk& zc, const St& st, const Val& val,
-                                       const Emit& emit) {
-  if (zc.z0 >= zc.z1) return;
-  const int nz = L.n[2], sz = L.stride[2];
-  const int col = zc.cx + zc.cy * L.stride[1];
-  const int c[2] = {zc.cx, zc.cy};
-  int lin = col + zc.z0 * sz;
-  auto vm = val(st(col + ((zc.z0 == 0) ? nz - 1 : zc.z0 - 1) * sz));
-  auto sc = st(lin);
-  T w2c = L.w[2][lin];
-  for (int z = zc.z0; z < zc.z1; ++z, lin += sz) {
-    const int ln = (z == nz - 1) ? col : lin + sz;
-    const auto sn = st(ln);
-    const T w2n = L.w[2][ln];
-    const T pc = val(sc);
-    T out = L.diag[lin] * pc;
-#pragma unroll
-    for (int d = 0; d < 2; ++d) {
-      const int n = L.n[d], s = L.stride[d];
-      const int cm = (c[d] == 0) ? lin + (n - 1) * s : lin - s;
-      const int cp = (c[d] == n - 1) ? lin - (n - 1) * s : lin + s;
-      const T wl = L.w[d][lin];
-      const T wu = (L.bc[d] == 1 && c[d] == n - 1) ? T(0) : L.w[d][cp];
-      out -= wu * (val(st(cp)) - pc) - wl * (pc - val(st(cm)));
-    }
-    {
-      const T wu = (L.bc[2] == 1 && z == nz - 1) ? T(0) : w2n;
-      out -= wu * (val(sn) - pc) - w2c * (pc - vm);
-    }
-    emit(lin, sc, out);
-    vm = pc;
-    sc = sn;
-    w2c = w2n;
-  }
-}
-
-template <class T>
-struct UpdSt {
-  T r, dv, x1;  // new residual, inverse diagonal, first smoothing iterate
-};
-
-// k_cg_update<T, 3, true> in z-marching form
-template <class T>
-__global__ void __launch_bounds__(kBlock) k_cg_update_zm(LV<T> L, const T* rold, const T* q, const T* p, T* x,
-                                                         T* rnew, T* xm, CGArgs g, int it, int zc) {
-  CGCtl* S = g.ctl;
-  if (S->flag) return;
-  if (it == 1 && S->bb == 0.0) {  // b = 0: x = 0 was written by the apply kernel
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      S->its = 0;
-      S->flag = 1;
-    }
-    return;
-  }
-  const double pq = block_sum_parts(g.part + kPartPQ * kRedBlocks, g.np);
-  const T al = (T)(S->rz[(it - 1) & 1] / pq);
-  const T th = T(1.0 / kChebTheta);
-  auto st = [&](int i) {
-    UpdSt<T> u;
-    u.r = rold[i] - al * q[i];
-    u.dv = L.dinv[i];
-    u.x1 = u.dv * u.r * th;
-    return u;
-  };
-  auto val = [](const UpdSt<T>& u) { return u.x1; };
-  T acc = T(0);
-  auto emit = [&](int lin, const UpdSt<T>& u, T Ax) {
-    const T xo = (it == 1) ? T(0) : x[lin];
-    x[lin] = xo + al * p[lin];
-    rnew[lin] = u.r;
-    acc += u.r * u.r;
-    xm[lin] = (T(1.0) + T(kChebC1)) * u.x1 + T(kChebC2) * u.dv * (u.r - Ax);
-  };
-  zmarch<T>(L, zchunk(L.n, zc), st, val, emit);
-  block_partial((double)acc, g.part + kPartRR * kRedBlocks);
-}
-
-// k_cg_apply<T, 3> in z-marching form
-template <class T>
-__global__ void __launch_bounds__(kBlock) k_cg_apply_zm(LV<T> L, const T* z, const T* pold, T* pnew, T* q, T* x,
-                                                        CGArgs g, int it, int zc) {
-  CGCtl* S = g.ctl;
-  if (S->flag) return;
-  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
-  const double rz = block_sum_parts(g.part + kPartRZ * kRedBlocks, g.np);
-  double beta = 0.0;
-  if (it == 1) {
-    const double bb = block_sum_parts(g.part + kPartBB * kRedBlocks, g.np);
-    if (lead) S->bb = bb;
-    if (bb == 0.0) {  // the update kernel of this iteration ends the solve
-      FOR_CELLS(lin, L.N) x[lin] = T(0);
-      return;
-    }
-  } else {
-    beta = rz / S->rz[it & 1];
-  }
-  if (lead) S->rz[(it - 1) & 1] = rz;
-  const T bt = (T)beta;
-  const T* po = (it == 1) ? z : pold;
-  auto st = [&](int i) { return z[i] + bt * po[i]; };
-  auto val = [](T v) { return v; };
-  T acc = T(0);
-  auto emit = [&](int lin, T pc, T qv) {
-    pnew[lin] = pc;
-    q[lin] = qv;
-    acc += pc * qv;
-  };
-  zmarch<T>(L, zchunk(L.n, zc), st, val, emit);
-  block_partial((double)acc, g.part + kPartPQ * kRedBlocks);
-}
-
-// planes per chunk of the z-marching forms on level L, or 0 when its columns outnumber the
-// partials (the grid-stride forms are used then)
-static int zm_chunk(const Level& L) {
-  const int nbx = (L.n[0] + kZX - 1) / kZX, nby = (L.n[1] + kZY - 1) / kZY;
-  const int per = cg_partials((size_t)L.N) / (nbx * nby);
-  if (per < 1) return 0;
-  return (L.n[2] + per - 1) / per;
 }
 
 // control reset and (b, b) partials; convergence decision alone; (r, z) partials alone
