@@ -120,9 +120,12 @@ def test_fd_jvp_parity_small(case):
 @pytest.mark.parametrize("mode", ["sound", "sound_thermal"])
 @pytest.mark.parametrize("shape,bc", [((32, 16), ("periodic", "wall")), ((8, 8, 16), ("periodic", "periodic", "wall")),
                                       ((96, 20), ("periodic", "wall")), ((24, 16), ("wall", "wall")),
-                                      ((8, 12, 8), ("wall", "wall", "wall"))])
+                                      ((8, 12, 8), ("wall", "wall", "wall")),
+                                      ((72, 6, 20), ("wall", "wall", "periodic"))])
 def test_precond_parity(mode, shape, bc):
-    """(96, 20): two multigrid levels, the coarser solved exactly right below a grid level."""
+    """(96, 20): two multigrid levels, the coarser solved exactly right below a grid level.
+    (72, 6, 20): the 3D z-marching kernels with a ragged second column tile in x, a ragged
+    one in y and seven z chunks of three planes (the last one short)."""
     J = _lib()
     nd = len(shape)
     pd, X = W.random_state(shape, bc, seed=12, g=tuple([0.0] * (nd - 1) + [-1.0]), chi_model="power",
