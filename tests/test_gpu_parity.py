@@ -168,9 +168,13 @@ def test_precond_parity_large(shape, bc):
         assert np.max(np.abs(got[k] - ref[k])) <= 1e-9 * np.max(np.abs(ref[k])), k
 
 
-def test_precond_fp32_variant():
+@pytest.mark.parametrize("shape,bc", [((64, 32), ("periodic", "wall")),
+                                      ((80, 8, 16), ("periodic", "periodic", "wall"))])
+def test_precond_fp32_variant(shape, bc):
+    """FP32 elliptic solves (3D: the z-marching kernels instantiated in FP32)."""
     J = _lib()
-    pd, X = W.random_state((64, 32), ("periodic", "wall"), seed=14, g=(0.0, -1.0), chi_model="power",
+    nd = len(shape)
+    pd, X = W.random_state(shape, bc, seed=14, g=tuple([0.0] * (nd - 1) + [-1.0]), chi_model="power",
                            chi0=0.02, amp=0.2)
     P = Problem.from_dict(pd)
     dt = 0.05
