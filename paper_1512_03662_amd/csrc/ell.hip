@@ -110,12 +110,13 @@ __device__ __forceinline__ T apply_row(const RowCoef<T, ND>& r, const F& nb, T p
   return out;
 }
 
-// restricted residual (mean over the 2^ND children of b - A x) of coarse cell cc
-template <class T, int ND>
+// restricted residual (mean over the 2^ND children of b - A x) of coarse cell cc; UNR
+// children are unrolled at a time (the sum's order is the same)
+template <class T, int ND, int UNR = (1 << ND)>
 __device__ __forceinline__ T restrict_at(const LV<T>& F, const T* b, const T* x, const int* cc) {
   auto xf = [&](int i) { return x[i]; };
   T sum = T(0);
-#pragma unroll
+#pragma unroll UNR
   for (int ch = 0; ch < (1 << ND); ++ch) {
     int c[3] = {0, 0, 0};
     int fl = 0;
@@ -1046,7 +1047,9 @@ __global__ void __launch_bounds__(kCoarseThreads) k_vcycle_coarse(CoarseArgs a, 
     for (int ic = tid; ic < Nc; ic += NT) {
       int cc[3];
       coords<ND>(a.n[j + 1], ic, cc);
-      bc[ic] = restrict_at<T, ND>(L, b, x, cc);
+      // in 3D two children at a time: the full unroll spilled registers in this
+      // 1024-thread kernel
+      bc[ic] = restrict_at<T, ND, (ND == 3) ? 2 : (1 << ND)>(L, b, x, cc);
     }
     __syncthreads();
   }
