@@ -370,7 +370,7 @@ __device__ __forceinline__ void vjp_tileA(const Grid& G, const PadGrid& PG, cons
 }
 
 template <int ND>
-__global__ void __launch_bounds__(kBlock) k_vjp_stageA(Grid G, PadGrid PG, const double* X, const double* w,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) k_vjp_stageA(Grid G, PadGrid PG, const double* X, const double* w,
                                                        double cR, const double* mf, double* fbar) {
   __shared__ double sV[ppoints_max<ND>()];
   const BTile<ND> T = btile_setup<ND>(G, PG);
@@ -625,7 +625,7 @@ __device__ __forceinline__ void preimages(int i, int n, int bc, bool normal, int
 }
 
 template <int ND>
-__global__ void __launch_bounds__(kBlock) k_vjp_fold(Grid G, PadGrid PG, const double* X, const double* w,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) k_vjp_fold(Grid G, PadGrid PG, const double* X, const double* w,
                                                      double cU, const double* xbar, int scaleR, double alpha2,
                                                      double* out) {
   int lin = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
