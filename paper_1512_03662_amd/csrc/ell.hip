@@ -657,6 +657,94 @@ __global__ void __launch_bounds__(kBlock) k_mg_prolong_smooth1_zm(LV<T> L, const
   zmarch<T>(L, zchunk(L.n, zc), st, val, emit);
 }
 
+// k_mg_restrict_resid<T, 3, CONV> in z-marching form: a thread owns one coarse column and
+// walks a chunk of coarse planes; the fine iterate of the plane below the current pair and
+// of the pair itself, and the z face weights of the pair, are carried from one coarse plane
+// to the next (the fine dimensions are even).  Each child's row is evaluated in apply_nb's
+// order and the children are summed in restrict_at's order.
+template <class T, bool CONV>
+__global__ void __launch_bounds__(kBlock) k_mg_restrict_resid_zm(LV<T> L, const T* b, const T* x, T* bc,
+                                                                 int ncx, int ncy, int ncz, int zc, CGArgs g,
+                                                                 int it) {
+  if (g.ctl->flag) return;
+  if (CONV && blockIdx.x == 0) {
+    const double rr = block_sum_parts(g.part + kPartRR * kRedBlocks, g.np);
+    if (threadIdx.x == 0) cg_decide(g, rr, it);
+  }
+  const int nbx = (ncx + kZX - 1) / kZX, nby = (ncy + kZY - 1) / kZY;
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int tile = blk % (nbx * nby), chunk = blk / (nbx * nby);
+  const int ccx = (tile % nbx) * kZX + (int)threadIdx.x % kZX;
+  const int ccy = (tile / nbx) * kZY + (int)threadIdx.x / kZX;
+  const int cz0 = chunk * zc, cz1 = min(cz0 + zc, ncz);
+  if (ccx >= ncx || ccy >= ncy || cz0 >= cz1) return;
+  const int nz = L.n[2], sz = L.stride[2];
+  // the four fine columns (child bits x, y) and their x/y coordinates
+  int col[4], fx[4], fy[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    fx[q] = 2 * ccx + (q & 1);
+    fy[q] = 2 * ccy + (q >> 1);
+    col[q] = fx[q] + fy[q] * L.stride[1];
+  }
+  // x/y part of a fine row, in apply_nb's order, started from diag * xc
+  auto rowxy = [&](int fl, int q, T xc) {
+    T out = L.diag[fl] * xc;
+    const int c2[2] = {fx[q], fy[q]};
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      const int n = L.n[d], st = L.stride[d];
+      const int cm = (c2[d] == 0) ? fl + (n - 1) * st : fl - st;
+      const int cp = (c2[d] == n - 1) ? fl - (n - 1) * st : fl + st;
+      const T wl = L.w[d][fl];
+      const T wu = (L.bc[d] == 1 && c2[d] == n - 1) ? T(0) : L.w[d][cp];
+      out -= wu * (x[cp] - xc) - wl * (xc - x[cm]);
+    }
+    return out;
+  };
+  const int f00 = 2 * cz0;
+  const int fm0 = (f00 == 0) ? nz - 1 : f00 - 1;
+  T xA[4], xB[4], wB[4];  // x on the fine plane below the pair, x and w2 on its first plane
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    xA[q] = x[col[q] + fm0 * sz];
+    xB[q] = x[col[q] + f00 * sz];
+    wB[q] = L.w[2][col[q] + f00 * sz];
+  }
+  for (int cz = cz0; cz < cz1; ++cz) {
+    const int f0 = 2 * cz, f1 = f0 + 1;
+    const int f2 = (f1 == nz - 1) ? 0 : f1 + 1;
+    T xC[4], xD[4], wC[4], wD[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      xC[q] = x[col[q] + f1 * sz];
+      xD[q] = x[col[q] + f2 * sz];
+      wC[q] = L.w[2][col[q] + f1 * sz];
+      wD[q] = L.w[2][col[q] + f2 * sz];
+    }
+    T sum = T(0);
+#pragma unroll
+    for (int ch = 0; ch < 8; ++ch) {
+      const int q = ch & 3, k = ch >> 2;
+      const int fl = col[q] + (k ? f1 : f0) * sz;
+      const T xc = k ? xC[q] : xB[q];
+      T out = rowxy(fl, q, xc);
+      const T zp = k ? xD[q] : xC[q], zm = k ? xB[q] : xA[q];
+      const T wl = k ? wC[q] : wB[q];
+      const T wu = k ? ((L.bc[2] == 1 && f1 == nz - 1) ? T(0) : wD[q]) : wC[q];
+      out -= wu * (zp - xc) - wl * (xc - zm);
+      sum += b[fl] - out;
+    }
+    bc[ccx + ccy * ncx + cz * ncx * ncy] = sum * T(1.0 / 8);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      xA[q] = xC[q];
+      xB[q] = xD[q];
+      wB[q] = wD[q];
+    }
+  }
+}
+
 // planes per chunk of the z-marching forms on level L, or 0 when its columns outnumber the
 // partials (the grid-stride forms are used then)
 static int zm_chunk(const Level& L) {
@@ -885,6 +973,19 @@ void launch_mg_restrict_resid(const Grid& G, const Level& f, const T* b, const T
                               const Level& c, const CGArgs& g, int conv_it, hipStream_t s) {
   LV<T> v = view<T>(G, f);
   const double by = ((3.0 + G.nd) * f.N + c.N) * (double)sizeof(T);
+  if (G.nd == 3) {
+    const int nbx = (c.n[0] + kZX - 1) / kZX, nby = (c.n[1] + kZY - 1) / kZY;
+    const int per = std::max(1, kRedBlocks / (nbx * nby));
+    const int zc = (c.n[2] + per - 1) / per;
+    const int nblk = nbx * nby * ((c.n[2] + zc - 1) / zc);
+    if (conv_it > 0)
+      launch_k(KF_MG_RESTRICT, by, k_mg_restrict_resid_zm<T, true>, dim3(nblk), dim3(kBlock), 0, s, v, b, x, bc,
+               c.n[0], c.n[1], c.n[2], zc, g, conv_it);
+    else
+      launch_k(KF_MG_RESTRICT, by, k_mg_restrict_resid_zm<T, false>, dim3(nblk), dim3(kBlock), 0, s, v, b, x, bc,
+               c.n[0], c.n[1], c.n[2], zc, g, 0);
+    return;
+  }
   if (conv_it > 0) {
     if (G.nd == 2)
       launch_k(KF_MG_RESTRICT, by, k_mg_restrict_resid<T, 2, true>, CELLS(c.N), 0, s, v, b, x, bc, c.N, c.n[0],
