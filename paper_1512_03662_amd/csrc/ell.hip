@@ -442,9 +442,10 @@ __global__ void __launch_bounds__(kBlock) k_mg_smooth2(LV<T> L, const T* b, cons
 // A block owns kZX x kZY columns of cells (x contiguous) and walks them along z through a
 // chunk of planes.  The state a cell's stencil needs from its z neighbours is carried in
 // registers from one plane to the next, so no plane is fetched a second time for the z+1 or
-// z-1 neighbour of another cell (the grid-stride forms above read those planes again, from
-// another XCD's L2 or from memory).  The launch has exactly cg_partials(N) blocks (one
-// partial each where the kernel writes partials); blocks past the last chunk have no cells.
+// z-1 neighbour of another cell (the grid-stride forms read those planes again, from another
+// XCD's L2 or from memory).  Except for the restriction, which has a grid of its own, a
+// launch has exactly cg_partials(N) blocks (one partial each where the kernel writes
+// partials); blocks past the last chunk have no cells.
 constexpr int kZX = 64, kZY = 4;
 static_assert(kZX * kZY == kBlock, "one cell column per thread");
 
