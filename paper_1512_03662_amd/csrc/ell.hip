@@ -909,6 +909,71 @@ __global__ void __launch_bounds__(kBlock) k_mg_up(LV<T> C, const T* bc, const T*
   t2f[lin] = dd;
 }
 
+// k_mg_up onto level 0 of a 2D grid followed by level 0's second post-smoothing with the
+// (b, x) partials (k_mg_smooth2 with RZ): the first post-smoothing step is evaluated on the
+// tile and on a ring of one cell around it (into LDS), the second on the tile from there.
+// One block per tile, each writing one partial.  x2f is only read: the result goes to xo.
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_mg_up_last(LV<T> C, const T* bc, const T* t1c, const T* t2c, LV<T> F,
+                                                       const T* bf, const T* x2f, T* xo, CGArgs g) {
+  using TD = TileDims<2>;
+  constexpr int PX = TD::X / 2 + 2, PY = TD::Y / 2 + 2, PN = PX * PY;
+  constexpr int QX = TD::X + 2, QY = TD::Y + 2, QN = QX * QY;
+  __shared__ T sx[PN];
+  __shared__ T s1[QN];
+  __shared__ T s2[QN];
+  if (g.ctl->flag) return;
+  int o[3];
+  tile_origin<2>(F.n, o);
+  const int p0[2] = {o[0] / 2, o[1] / 2};
+  // the coarse level's second smoothing on the parents of the tile and of two rings of cells
+  // around it (as in k_mg_up)
+  auto t1 = [&](int k) { return t1c[k]; };
+  for (int h = threadIdx.x; h < PN; h += kBlock) {
+    const int hx = h % PX, hy = h / PX;
+    int cc[3] = {wrapc(p0[0] + hx - 1, C.n[0]), wrapc(p0[1] + hy - 1, C.n[1]), 0};
+    const int k = cc[0] * C.stride[0] + cc[1] * C.stride[1];
+    const T x1c = t1c[k];
+    const T r1 = bc[k] - apply_at<T, 2>(C, cc, k, t1, x1c);
+    sx[h] = x1c + T(kChebC1) * t2c[k] + T(kChebC2) * C.dinv[k] * r1;
+  }
+  __syncthreads();
+  // LDS position of the parent of the fine cell with unwrapped coordinates (ux, uy)
+  auto ppos = [&](int ux, int uy) { return ((ux >> 1) - p0[0] + 1) + ((uy >> 1) - p0[1] + 1) * PX; };
+  // prolongation and the first post-smoothing step on the tile and its ring
+  for (int h = threadIdx.x; h < QN; h += kBlock) {
+    const int ux = o[0] + h % QX - 1, uy = o[1] + h / QX - 1;
+    int fw[3] = {wrapc(ux, F.n[0]), wrapc(uy, F.n[1]), 0};
+    const int lin = fw[0] * F.stride[0] + fw[1] * F.stride[1];
+    const T xpc = x2f[lin] + sx[ppos(ux, uy)];
+    auto xp = [&](int d, int sg, int k) {
+      return x2f[k] + sx[d == 0 ? ppos(ux + sg, uy) : ppos(ux, uy + sg)];
+    };
+    const T r0 = bf[lin] - apply_nb<T, 2>(F, fw, lin, xp, xpc);
+    const T dd = F.dinv[lin] * r0 * T(1.0 / kChebTheta);
+    s1[h] = xpc + dd;
+    s2[h] = dd;
+  }
+  __syncthreads();
+  // the second post-smoothing step on the tile
+  const int t = threadIdx.x;
+  const int l[2] = {t % TD::X, t / TD::X};
+  int c[3] = {o[0] + l[0], o[1] + l[1], 0};
+  T acc = T(0);
+  if (c[0] < F.n[0] && c[1] < F.n[1]) {
+    const int lin = c[0] * F.stride[0] + c[1] * F.stride[1];
+    const int hc = (l[0] + 1) + (l[1] + 1) * QX;
+    const int hs[2] = {1, QX};
+    const T x1c = s1[hc];
+    auto xf = [&](int d, int sg, int) { return s1[hc + sg * hs[d]]; };
+    const T r1 = bf[lin] - apply_nb<T, 2>(F, c, lin, xf, x1c);
+    const T xn = x1c + T(kChebC1) * s2[hc] + T(kChebC2) * F.dinv[lin] * r1;
+    xo[lin] = xn;
+    acc += bf[lin] * xn;
+  }
+  block_partial((double)acc, g.part + kPartRZ * kRedBlocks);
+}
+
 #define CELLS(n) dim3(((n) + kBlock - 1) / kBlock), dim3(kBlock)
 
 template <class T>
@@ -944,6 +1009,17 @@ void launch_mg_up(const Grid& G, const Level& c, const T* bc, const T* t1c, cons
   else
     launch_k(KF_MG_UP, by, k_mg_up<T, 3>, dim3(tile_blocks<3>(f.n)), dim3(kBlock), 0, s, vc, bc, t1c, t2c, vf, bf,
              x2f, t1f, t2f, g);
+}
+template <class T>
+bool launch_mg_up_last(const Grid& G, const Level& c, const T* bc, const T* t1c, const T* t2c, const Level& f,
+                       const T* bf, const T* x2f, T* x, const CGArgs& g, hipStream_t s) {
+  if (G.nd != 2) return false;
+  const int nb = tile_blocks<2>(f.n);
+  if (nb != g.np) return false;
+  LV<T> vc = view<T>(G, c), vf = view<T>(G, f);
+  const double by = ((5.0 + G.nd) * c.N + (5.0 + G.nd) * f.N) * (double)sizeof(T);
+  launch_k(KF_MG_UP, by, k_mg_up_last<T>, dim3(nb), dim3(kBlock), 0, s, vc, bc, t1c, t2c, vf, bf, x2f, x, g);
+  return true;
 }
 
 
@@ -1641,6 +1717,8 @@ void launch_pbp_out(const Grid& G, const double* X, const double* v, int scaled,
                                              const T*, const Level&, T*, T*, const CGArgs&, hipStream_t);\
   template void launch_mg_smooth2<T>(const Grid&, const Level&, const T*, const T*, const T*, T*,       \
                                      const CGArgs&, bool, hipStream_t);                                  \
+  template bool launch_mg_up_last<T>(const Grid&, const Level&, const T*, const T*, const T*,           \
+                                     const Level&, const T*, const T*, T*, const CGArgs&, hipStream_t);  \
   template void launch_dense_matvec<T>(int, const double*, const T*, T*, const CGArgs&, hipStream_t);   \
   template void launch_vcycle_coarse<T>(const Grid&, const Level*, int, const double*, const T*, T*,     \
                                         const CGArgs&, int, int, hipStream_t);                           \

@@ -163,6 +163,12 @@ constexpr int kFusePairMaxN = 65536;
 template <class T>
 void launch_mg_down(const Grid& G, const Level& f, const T* bf, const T* xf, const Level& c, T* bc, T* xc,
                     const CGArgs& g, int conv_it, hipStream_t s);
+// the last pair up onto level 0 (2D) with level 0's second post-smoothing and the (b, x)
+// partials: x = the V-cycle's result from x2f (read only); false (nothing launched) when
+// level 0's tiles are not the partials' blocks
+template <class T>
+bool launch_mg_up_last(const Grid& G, const Level& c, const T* bc, const T* t1c, const T* t2c, const Level& f,
+                       const T* bf, const T* x2f, T* x, const CGArgs& g, hipStream_t s);
 template <class T>
 void launch_mg_up(const Grid& G, const Level& c, const T* bc, const T* t1c, const T* t2c, const Level& f,
                   const T* bf, const T* x2f, T* t1f, T* t2f, const CGArgs& g, hipStream_t s);

@@ -69,8 +69,8 @@ struct jfnk_ctx {
   // preconditioner
   EllOp ops[2];
   double *rhs_p = nullptr, *dp = nullptr, *rhs_T = nullptr, *dT = nullptr;
-  double* cg64[6] = {};    // r1 r2 p1 p2 q z
-  float* cg32[8] = {};     // r1 r2 p1 p2 q z b x
+  double* cg64[7] = {};    // r1 r2 p1 p2 q z x2
+  float* cg32[9] = {};     // r1 r2 p1 p2 q z x2 b x
   CGCtl* ctl = nullptr;    // control block of the running CG solve
   CGCtl* hctl = nullptr;   // pinned host copy
   double* cgpart = nullptr;
@@ -333,15 +333,16 @@ int first_fused(const std::vector<Level>& lv, bool* fused) {
   return l0;
 }
 
-// The V-cycle z = M r after level 0's first smoothing (already in z), ending with the (r, z)
-// partials; with it > 0 the convergence decision of iteration it is taken on the way down.
-// Requires first_fused(lv) >= 1.  When the coarsest levels run in the single-workgroup
+// The V-cycle z = M r after level 0's first smoothing (in x2, read only), ending with the
+// (r, z) partials; with it > 0 the convergence decision of iteration it is taken on the way
+// down.  Requires first_fused(lv) >= 1.  When the coarsest levels run in the single-workgroup
 // kernel, level pairs are fused: down(l -> l+1) = restriction + first smoothing of l+1,
 // up(l -> l-1) = second smoothing of l + prolongation and first post-smoothing of l-1; the
 // coarse kernel starts from the first smoothing of its first level and stops after that
-// level's first post-smoothing step.
+// level's first post-smoothing step.  On 2D grids the last pair up also takes level 0's
+// second post-smoothing when its tiles are the partials' blocks.
 template <class T>
-void vcycle_rest(jfnk_ctx* c, std::vector<Level>& lv, const double* Ainv, const T* r, T* z,
+void vcycle_rest(jfnk_ctx* c, std::vector<Level>& lv, const double* Ainv, const T* r, T* x2, T* z,
                  const CGArgs& g, int it) {
   const Grid& G = c->G;
   hipStream_t s = c->stream;
@@ -349,7 +350,8 @@ void vcycle_rest(jfnk_ctx* c, std::vector<Level>& lv, const double* Ainv, const 
   bool fused;
   const int l0 = first_fused(lv, &fused);
   auto B = [&](int l) -> const T* { return l == 0 ? r : (const T*)lv[l].b; };
-  auto Xl = [&](int l) -> T* { return l == 0 ? z : (T*)lv[l].x; };
+  // the level's iterate as read on the way down and into the prolongation (x2 on level 0)
+  auto Xl = [&](int l) -> T* { return l == 0 ? x2 : (T*)lv[l].x; };
   if (fused) {
     // a pair is fused while its coarse level is small (launch-latency bound); on large levels
     // the halo recomputation costs more than the launch it saves
@@ -377,6 +379,9 @@ void vcycle_rest(jfnk_ctx* c, std::vector<Level>& lv, const double* Ainv, const 
     }
     for (int l = ltop; l >= 1; --l) {
       if (fuse(l)) {
+        if (l == 1 && launch_mg_up_last<T>(G, lv[1], B(1), (const T*)lv[1].t1, (const T*)lv[1].t2, lv[0], r, x2,
+                                           z, g, s))
+          return;
         launch_mg_up<T>(G, lv[l], B(l), (const T*)lv[l].t1, (const T*)lv[l].t2, lv[l - 1], B(l - 1), Xl(l - 1),
                         (T*)lv[l - 1].t1, (T*)lv[l - 1].t2, g, s);
       } else {
@@ -389,7 +394,7 @@ void vcycle_rest(jfnk_ctx* c, std::vector<Level>& lv, const double* Ainv, const 
     return;
   }
   // coarsest level solved by its dense inverse alone: one kernel per V-cycle piece
-  launch_mg_restrict_resid<T>(G, lv[0], r, z, (T*)lv[1].b, lv[1], g, it, s);
+  launch_mg_restrict_resid<T>(G, lv[0], r, x2, (T*)lv[1].b, lv[1], g, it, s);
   for (int l = 1; l < l0; ++l) {
     launch_mg_presmooth<T>(G, lv[l], B(l), Xl(l), g, false, s);
     launch_mg_restrict_resid<T>(G, lv[l], B(l), Xl(l), (T*)lv[l + 1].b, lv[l + 1], g, 0, s);
@@ -398,21 +403,23 @@ void vcycle_rest(jfnk_ctx* c, std::vector<Level>& lv, const double* Ainv, const 
   for (int l = l0 - 1; l >= 0; --l) {
     launch_mg_prolong_smooth1<T>(G, lv[l], B(l), Xl(l), Xl(l + 1), lv[l + 1], (T*)lv[l].t1,
                                  (T*)lv[l].t2, g, s);
-    launch_mg_smooth2<T>(G, lv[l], B(l), (const T*)lv[l].t1, (const T*)lv[l].t2, Xl(l), g, l == 0, s);
+    launch_mg_smooth2<T>(G, lv[l], B(l), (const T*)lv[l].t1, (const T*)lv[l].t2, l == 0 ? z : Xl(l), g, l == 0,
+                         s);
   }
 }
 
 // PCG on level 0 of lv: x = A^-1 b (x and b of type T, length N), stopping when
 // ||r|| < cg_eta ||b|| or after cg_maxit iterations.  The iterations run from the device
 // (CGCtl); the host enqueues `pred` of them (the previous count of this solver), then one
-// at a time until the control block reports a stop.  v: r1, r2, p1, p2, q, z.
+// at a time until the control block reports a stop.  v: r1, r2, p1, p2, q, z, x2 (x2: level 0's
+// iterate after its first smoothing, the V-cycle's input; z its output).
 template <class T>
 int pcg(jfnk_ctx* c, std::vector<Level>& lv, const double* Ainv, const T* b, T* x, T* const* v,
         int* pred) {
   const Grid& G = c->G;
   hipStream_t s = c->stream;
   const int N = G.N;
-  T *r1 = v[0], *r2 = v[1], *p1 = v[2], *p2 = v[3], *q = v[4], *z = v[5];
+  T *r1 = v[0], *r2 = v[1], *p1 = v[2], *p2 = v[3], *q = v[4], *z = v[5], *x2 = v[6];
   CGArgs g;
   g.ctl = c->ctl;
   g.part = c->cgpart;
@@ -427,8 +434,8 @@ int pcg(jfnk_ctx* c, std::vector<Level>& lv, const double* Ainv, const T* b, T* 
   if (g.maxit == 0) z = x;
   // z = M b with the (b, b) and (b, z) partials
   if (l0 >= 1) {
-    launch_mg_presmooth<T>(G, lv[0], b, z, g, true, s);
-    vcycle_rest<T>(c, lv, Ainv, b, z, g, 0);
+    launch_mg_presmooth<T>(G, lv[0], b, x2, g, true, s);
+    vcycle_rest<T>(c, lv, Ainv, b, x2, z, g, 0);
   } else if (fused) {
     launch_vcycle_coarse<T>(G, &lv[0], nl, Ainv, b, z, g, kCoarseInit | kCoarseRZ, 0, s);
   } else {
@@ -450,11 +457,11 @@ int pcg(jfnk_ctx* c, std::vector<Level>& lv, const double* Ainv, const T* b, T* 
       // next V-cycle is enqueued after the host has read it, and only if the solve goes on
       const bool last = (enq == g.maxit) || (k == batch - 1);
       launch_cg_apply<T>(G, lv[0], z, pold, pnew, q, x, g, it, s);
-      launch_cg_update<T>(G, lv[0], rold, q, pnew, x, rnew, (l0 >= 1 && !last) ? z : nullptr, g, it, s);
+      launch_cg_update<T>(G, lv[0], rold, q, pnew, x, rnew, (l0 >= 1 && !last) ? x2 : nullptr, g, it, s);
       if (last) {
         launch_cg_decide(g, it, s);
       } else if (l0 >= 1) {
-        vcycle_rest<T>(c, lv, Ainv, rnew, z, g, it);
+        vcycle_rest<T>(c, lv, Ainv, rnew, x2, z, g, it);
       } else if (fused) {
         launch_vcycle_coarse<T>(G, &lv[0], nl, Ainv, rnew, z, g, kCoarseConv | kCoarseRZ, it, s);
       } else {
@@ -474,8 +481,8 @@ int pcg(jfnk_ctx* c, std::vector<Level>& lv, const double* Ainv, const T* b, T* 
     // the solve goes on: z = M r for the last residual (with the first level-0 smoothing that
     // the update kernel skipped); the repeated decision in the V-cycle finds "go on" again
     if (l0 >= 1) {
-      launch_mg_presmooth<T>(G, lv[0], rold, z, g, false, s);
-      vcycle_rest<T>(c, lv, Ainv, rold, z, g, enq);
+      launch_mg_presmooth<T>(G, lv[0], rold, x2, g, false, s);
+      vcycle_rest<T>(c, lv, Ainv, rold, x2, z, g, enq);
     } else if (fused) {
       launch_vcycle_coarse<T>(G, &lv[0], nl, Ainv, rold, z, g, kCoarseConv | kCoarseRZ, enq, s);
     } else {
@@ -498,8 +505,8 @@ void ell_solve(jfnk_ctx* c, int o, const double* b, double* x) {
     c->cg_its += pcg<double>(c, op.lv64, op.Ainv, b, x, c->cg64, &c->cg_pred[o][0]);
   } else {
     launch_dot<double>(N, b, b, c->scal + S_TMP, c->red, c->stream);
-    float* b32 = c->cg32[6];
-    float* x32 = c->cg32[7];
+    float* b32 = c->cg32[7];
+    float* x32 = c->cg32[8];
     // S_TMP keeps ||b||^2 for the way back (a zero b gives b32 = 0 and x = 0)
     launch_cast_scale_f32(N, b, c->scal + S_TMP, b32, c->stream);
     c->cg_its += pcg<float>(c, op.lv32, op.Ainv, b32, x32, c->cg32, &c->cg_pred[o][1]);
@@ -883,9 +890,9 @@ void create(jfnk_ctx* c) {
   c->dp = dalloc<double>(c, N);
   c->rhs_T = dalloc<double>(c, N);
   c->dT = dalloc<double>(c, N);
-  for (int i = 0; i < 6; ++i) c->cg64[i] = dalloc<double>(c, N);
+  for (int i = 0; i < 7; ++i) c->cg64[i] = dalloc<double>(c, N);
   bool want32 = true;  // precision may be switched by jfnk_set_opts
-  for (int i = 0; i < 8; ++i) c->cg32[i] = dalloc<float>(c, N);
+  for (int i = 0; i < 9; ++i) c->cg32[i] = dalloc<float>(c, N);
   c->ctl = dalloc<CGCtl>(c, 1);
   HIPX(hipMemsetAsync(c->ctl, 0, sizeof(CGCtl), c->stream));
   c->cgpart = dalloc<double>(c, (size_t)kPartCount * kRedBlocks);
