@@ -14,7 +14,7 @@ dL/dX^n = (dU/dX|_{X^n})^T lam / dt + (1 - theta) (dR/dX|_{X^n})^T lam.
   (R J^T L^-1)(L lam) = R g with the transposed physics-based preconditioner
   L M^-T R^-1 on the right, mirroring the forward solver.
 
-Pins (tests/test_oracle_adjoint.py): dot-product tests <w, J v> = <J^T w, v> with the
+Pins (tests/test_oracle_newton_adjoint.py): dot-product tests <w, J v> = <J^T w, v> with the
 complex-step J.v; dU_dX_T against complex steps of U; the step adjoint against central
 finite differences of whole exact steps; FGMRES adjoint against the LU adjoint.
 """

@@ -13,7 +13,7 @@ between applications (inner CG to a tolerance) is allowed; restart length m = 30
 apply_op maps a direction z to A z in the space of b.  Directions may live in another space
 than b (here: unscaled state increments versus scaled residuals).
 
-Pins (tests/test_oracle_krylov.py): exact solve for n <= m against numpy.linalg.solve, the
+Pins (tests/test_oracle_mg_krylov.py): exact solve for n <= m against numpy.linalg.solve, the
 Arnoldi relation A Z_j = V_{j+1} H_j, orthonormality of V, monotone residual estimates that
 equal the true residual.
 """

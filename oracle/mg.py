@@ -21,7 +21,7 @@ preconditioner:
 products in FP32, the right-hand side divided by its FP64 2-norm before the cast, the
 result cast back and rescaled.
 
-Pins (tests/test_oracle_mg.py): the V-cycle is a symmetric positive definite operator
+Pins (tests/test_oracle_mg_krylov.py): the V-cycle is a symmetric positive definite operator
 (dense check on small grids); PCG meets its stopping rule and agrees with the sparse direct
 solve within eta' times the condition-number bound; iteration counts stay bounded as the grid
 is refined.

@@ -15,7 +15,7 @@ Two routes to X^{n+1}, the root of F(X) = 0 (eq. newtimestep):
   iterations (Sect. 4.1).  At most ``newton_max`` iterations (no line search: the paper
   describes none).
 
-Pins (tests/test_oracle_newton.py): exact Newton converges quadratically to a residual at
+Pins (tests/test_oracle_newton_adjoint.py): exact Newton converges quadratically to a residual at
 roundoff; linear acoustics through one exact step matches the closed-form amplification of
 the discrete wave equation; JFNK reaches the exact root within its tolerance; a uniform state
 is a fixed point.

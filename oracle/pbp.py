@@ -23,7 +23,7 @@ Readings where the paper is silent:
 The elliptic systems are solved here directly (scipy splu) or by ``mg.pcg`` (the same
 multigrid-preconditioned CG the GPU uses).
 
-Pins (tests/test_oracle_pbp.py): symmetry and positivity of A_p, A_T; Fourier eigenvalues
+Pins (tests/test_oracle_scaling_pbp.py): symmetry and positivity of A_p, A_T; Fourier eigenvalues
 for constant coefficients; the identity-based energy update equals the explicit Laplacian
 form; transformation matrix identities of App. B; M^-1 equals the exact inverse of the
 linearised semi-implicit system written out densely; the transposed operator passes the

@@ -8,7 +8,7 @@ L (residual scaling) and R (unknown scaling), per cell and variable:
 with the face means rho_f, c_s,f of the two cells sharing the face (mirror ghost at walls),
 u the stored face velocity.  Default alpha1 = 1e-5, alpha2 = 1 (Sect. 4.1 / Sect. 5.1.1).
 
-Pinned by tests/test_oracle_scaling.py against the definitions on hand-built states.
+Pinned by tests/test_oracle_scaling_pbp.py against the definitions on hand-built states.
 """
 from __future__ import annotations
 

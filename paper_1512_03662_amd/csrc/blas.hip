@@ -18,8 +18,13 @@ struct OpSum {
   static __device__ __forceinline__ double f(double a, double b) { return a + b; }
   static constexpr double id = 0.0;
 };
+// max that propagates NaN (fmax would return the other operand), so that a NaN anywhere in
+// a max-reduction reaches the host's finiteness checks
+__device__ __forceinline__ double nanmax(double a, double b) {
+  return (a != a) ? a : ((b != b) ? b : fmax(a, b));
+}
 struct OpMax {
-  static __device__ __forceinline__ double f(double a, double b) { return fmax(a, b); }
+  static __device__ __forceinline__ double f(double a, double b) { return nanmax(a, b); }
   static constexpr double id = 0.0;  // reductions of non-negative values only
 };
 
@@ -331,7 +336,7 @@ __global__ void __launch_bounds__(kBlock) k_scaled_red(Grid G, const double* X, 
 #pragma unroll
     for (int v = 0; v < 2 + ND; ++v) {
       double q = V[v * G.N + lin] / Rs[v];
-      if (MAX) acc = fmax(acc, fabs(q));
+      if (MAX) acc = nanmax(acc, fabs(q));
       else acc += q * q;
     }
   }
@@ -384,7 +389,7 @@ __global__ void __launch_bounds__(kBlock) k_cfl_speed(Grid G, const double* X, d
       double uc = 0.5 * (s0 * X[(2 + d) * G.N + i0] + s1 * X[(2 + d) * G.N + i1]);
       u2 += uc * uc;
     }
-    acc = fmax(acc, sqrt(u2) + sound_speed_rt(G, X[lin], X[G.N + lin]));
+    acc = nanmax(acc, sqrt(u2) + sound_speed_rt(G, X[lin], X[G.N + lin]));
   }
   double a[1] = {acc};
   block_finish<OpMax, 1>(a, out, ws);

@@ -685,7 +685,10 @@ GmresOut fgmres(jfnk_ctx* c, const double* X, double beta0, double sign) {
     for (int i = k - 1; i >= 0; --i) {
       double t = g[i];
       for (int l = i + 1; l < k; ++l) t -= Hx(i, l) * y[l];
+      // a zero pivot follows an exact breakdown with a singular Hessenberg block
+      if (Hx(i, i) == 0.0) throw FiniteErr("singular Hessenberg matrix in GMRES");
       y[i] = t / Hx(i, i);
+      if (!std::isfinite(y[i])) throw FiniteErr("non-finite GMRES coefficient");
     }
     for (int i = 0; i < k; ++i) c->hscal[S_Y + i] = y[i];
     push(c, S_Y, k);
