@@ -1,0 +1,171 @@
+"""GPU parity of whole implicit steps at the configurations' shapes, through the C ABI.
+
+* 3D steps (the z-marching multigrid kernels, 3D residual tiles and FGMRES together): the
+  Taylor-Green box at Mach 1e-6 (32^3, periodic, CFL 1000, sound preconditioner) and a
+  walled polytrope with chi ~ T^3 (16 x 16 x 32, sound + thermal, CFL 20), each in the plain
+  form (FD J.v, FP64 elliptic) and the exact-J.v + FP32-elliptic form, against the root of
+  the oracle's own JFNK step iterated far below the step's tolerance (Newton 1e-12, GMRES
+  1e-8, CG 1e-8): ||R^-1 (X_gpu - X*)||_inf <= 1e-8 (Sect. 4.1, eq. nr_terminate).
+* the first steps of the 2D 256^2 stratified box (constant chi, CFL 100) and of the 512^2
+  box with chi ~ T^3 (CFL 50) against the oracle's JFNK step with the same options.
+* iteration counts: the same algorithm on both sides, so Newton, GMRES and CG counts agree
+  with the oracle's on small 2D cases.
+* FP32 elliptic solves against the oracle's FP32 multigrid CG (np.float32 arithmetic) on
+  grids whose large levels run the single-level kernels.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle.mg import PCGSolver
+from oracle.newton import jfnk_step, Opts, Stats
+from oracle.pbp import PBP
+from oracle.residual import Problem, cfl_dt
+from oracle.scaling import scaling_LR
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _lib():
+    import paper_1512_03662_amd as J
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return J
+
+
+def T(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def H(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+TIGHT = dict(newton_tol=1e-12, newton_max=30, gmres_eta=1e-8, gmres_maxit=600, cg_eta=1e-8, cg_maxit=200)
+
+CASES_3D = {
+    "taylor_green_32": (lambda: W.taylor_green_3d(n=32), 1000.0, "sound"),
+    "polytrope_16x16x32": (lambda: W.polytrope((16, 16, 32), 20.0, mach=1e-4, seed=5, chi_model="power",
+                                               cfl=20.0, steps=1), 20.0, "sound_thermal"),
+}
+_ROOTS = {}
+
+
+def _tight_root(name):
+    """The oracle's root of the first step (cached per case)."""
+    if name not in _ROOTS:
+        mk, cfl, pc = CASES_3D[name]
+        w = mk()
+        P = Problem.from_dict(w["problem"])
+        dt = cfl_dt(P, w["X0"], cfl)
+        st = Stats()
+        Xr = jfnk_step(P, w["X0"], dt, Opts(precond=pc, jv_mode="fd", **TIGHT), st)
+        assert st.converged and st.dx_norms[-1] < 1e-12, st.dx_norms
+        _ROOTS[name] = (w, P, dt, Xr)
+    return _ROOTS[name]
+
+
+@pytest.mark.parametrize("form", ["fd_fp64", "exact_fp32"])
+@pytest.mark.parametrize("name", sorted(CASES_3D))
+def test_implicit_step_3d(name, form):
+    J = _lib()
+    w, P, dt, Xr = _tight_root(name)
+    jv, ell = form.split("_")
+    print(f"# 3D step {name} {form} shape {P.shape}", flush=True)
+    ctx = J.Context(w["problem"], precond=CASES_3D[name][2], jv_mode=jv, ell_precision=ell)
+    Xg = T(w["X0"])
+    assert abs(ctx.cfl_dt(Xg, CASES_3D[name][1]) - dt) <= 1e-14 * dt
+    st = ctx.implicit_step(Xg, dt)
+    assert st["converged"] == 1, st
+    _, R = scaling_LR(P, Xr)
+    err = float(np.max(np.abs((H(Xg) - Xr) / R)))
+    print(f"#   newton {st['newton_its']} gmres {st['gmres_its']} cg {st['cg_its']} "
+          f"||R^-1 (X - X*)||_inf {err:.3e}", flush=True)
+    assert err <= 1e-8, (err, st)
+    ctx.close()
+
+
+@pytest.mark.parametrize("cfg", ["stratified_2d", "stratified_2d_kappa"])
+def test_first_step_of_the_2d_configs(cfg):
+    """256^2 (constant chi, CFL 100) and 512^2 (chi ~ T^3, CFL 50): the first step against
+    the oracle's JFNK step with the same options (FD J.v, FP64 MG-CG, Newton 1e-8)."""
+    J = _lib()
+    w = W.CONFIGS[cfg]()
+    P = Problem.from_dict(w["problem"])
+    X0 = w["X0"]
+    dt = cfl_dt(P, X0, w["cfl"])
+    print(f"# first step {w['name']}", flush=True)
+    st_o = Stats()
+    Xo = jfnk_step(P, X0, dt, Opts(precond=w["precond"], jv_mode=w["jv_mode"]), st_o)
+    assert st_o.converged
+    ctx = J.Context(w["problem"], precond=w["precond"], jv_mode=w["jv_mode"])
+    Xg = T(X0)
+    st = ctx.implicit_step(Xg, dt)
+    assert st["converged"] == 1
+    _, R = scaling_LR(P, Xo)
+    err = float(np.max(np.abs((H(Xg) - Xo) / R)))
+    print(f"#   oracle newton {st_o.newton_its} gmres {sum(st_o.gmres_its)}; gpu newton "
+          f"{st['newton_its']} gmres {st['gmres_its']}; ||R^-1 (X - X_or)||_inf {err:.3e}", flush=True)
+    assert err <= 1e-8, err
+    ctx.close()
+
+
+COUNT_CASES = {
+    "acoustic_bump_32": (lambda: W.acoustic_bump_2d(n=32), 10.0, "sound", "fd"),
+    "polytrope_32_thermal": (lambda: W.polytrope((32, 32), 10.0, mach=1e-3, seed=5, chi_model="power",
+                                                 steps=1, cfl=100.0), 100.0, "sound_thermal", "fd"),
+    "polytrope_32_exact": (lambda: W.polytrope((32, 32), 10.0, mach=1e-3, seed=5, chi_model="const",
+                                               steps=1, cfl=50.0), 50.0, "sound_thermal", "exact"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(COUNT_CASES))
+def test_iteration_counts_match_the_oracle(name):
+    """The GPU runs the oracle's algorithm (Newton, FGMRES(30) with CGS2, MG-CG to 1e-4):
+    Newton iterations, GMRES iterations and CG iterations per step are the same."""
+    J = _lib()
+    mk, cfl, pc, jv = COUNT_CASES[name]
+    w = mk()
+    P = Problem.from_dict(w["problem"])
+    dt = cfl_dt(P, w["X0"], cfl)
+    st_o = Stats()
+    jfnk_step(P, w["X0"], dt, Opts(precond=pc, jv_mode=jv), st_o)
+    ctx = J.Context(w["problem"], precond=pc, jv_mode=jv)
+    st = ctx.implicit_step(T(w["X0"]), dt)
+    got = (st["newton_its"], st["gmres_its"], st["cg_its"])
+    ref = (st_o.newton_its, sum(st_o.gmres_its), sum(st_o.cg_its))
+    print(f"# counts {name}: gpu {got} oracle {ref} (per Newton: {st_o.gmres_its})", flush=True)
+    assert got == ref
+    ctx.close()
+
+
+@pytest.mark.parametrize("shape,bc", [((1024, 512), ("periodic", "wall")),
+                                      ((128, 128, 48), ("periodic", "periodic", "wall"))])
+def test_fp32_elliptic_against_the_oracle_fp32_mgcg(shape, bc):
+    """FP32 coefficients, vectors and dot products on both sides (the oracle in np.float32,
+    right-hand side normalised by its FP64 norm before the cast).  The two FP32 computations
+    round differently (summation order), so they agree to FP32 rounding amplified by the CG
+    iteration, not to FP64 rounding.  The oracle's FP32 and FP64 multigrid CG take the same
+    iteration counts here and differ by at most 2.2e-7 of the largest entry per variable;
+    the bar is 5e-6 against both (the solves' own tolerance is 1e-4)."""
+    J = _lib()
+    nd = len(shape)
+    pd, X = W.random_state(shape, bc, seed=16, g=tuple([0.0] * (nd - 1) + [-1.0]), chi_model="power",
+                           chi0=0.02, amp=0.2)
+    P = Problem.from_dict(pd)
+    dt = 0.05
+    r = W.random_vector(X, 17)
+    ref32 = PBP(P, X, dt, "sound_thermal", solver_factory=PCGSolver.factory(1e-4, 50, np.float32)).apply(r)
+    ref64 = PBP(P, X, dt, "sound_thermal", solver_factory=PCGSolver.factory(1e-4, 50)).apply(r)
+    ctx = J.Context(pd, precond="sound_thermal", ell_precision="fp32", cg_eta=1e-4, cg_maxit=50)
+    ctx.set_state_n(T(X), dt)
+    got = H(ctx.precond_apply(T(X), T(r)))
+    e32 = [float(np.max(np.abs(got[k] - ref32[k])) / np.max(np.abs(ref32[k]))) for k in range(P.nvar)]
+    e64 = [float(np.max(np.abs(got[k] - ref64[k])) / np.max(np.abs(ref64[k]))) for k in range(P.nvar)]
+    print(f"# fp32 {shape}: vs oracle fp32 {max(e32):.2e}, vs oracle fp64 {max(e64):.2e}", flush=True)
+    assert max(e32) <= 5e-6, e32
+    assert max(e64) <= 5e-6, e64
+    ctx.close()
