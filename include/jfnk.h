@@ -186,6 +186,21 @@ int jfnk_adjoint_step(jfnk_ctx* ctx, const double* Xn1, const double* Xn, double
  * velocities (Introduction, CFL_hydro).  Synchronises; returns a negative value on error. */
 double jfnk_cfl_dt(jfnk_ctx* ctx, const double* X, double cfl);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the time step of jfnk_cfl_dt without a
+ * context.  *dt_out (device pointer, one double) receives cfl * min_d dx_d /
+ * max_c(|u_c| + c_s) for the state X (device, FP64 SoA as everywhere) of problem prob; the
+ * value is bit for bit the one jfnk_cfl_dt returns.  Asynchronous on hip_stream (NULL: the
+ * null stream), whose device must be the current one.  Allocates nothing: the reduction's
+ * block partials live in a static device array of 1024 doubles (8 KiB) that every device
+ * the library runs on holds until the process ends; its address is looked up on the first
+ * call on each device.  All calls on one device share that array, so calls that overlap
+ * on one device (different streams, or threads) race.  JFNK_E_INVALID for a null pointer,
+ * cfl <= 0, a problem jfnk_create would refuse, or a stream of another device (message in
+ * jfnk_last_error(NULL)); JFNK_E_DEVICE on a HIP error.                                 */
+int jfnk_cfl_dt_noalloc(const jfnk_problem* prob, const double* X, double cfl, double* dt_out,
+                        void* hip_stream);
+
 /* Measurement hooks (process-wide, not thread-safe).  jfnk_probe_enable(1) clears the
  * counters and from then on brackets every launch of the instrumented kernels with HIP
  * events on the stream it is launched on; jfnk_probe_enable(0) stops.  Kernel family k

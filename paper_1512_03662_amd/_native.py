@@ -101,6 +101,7 @@ SIGNATURES = {
     "jfnk_si_step": (C.c_int, [_P, _P, _D, C.POINTER(StepStats)]),
     "jfnk_adjoint_step": (C.c_int, [_P, _P, _P, _D, _P, _P, C.POINTER(StepStats)]),
     "jfnk_cfl_dt": (C.c_double, [_P, _P, _D]),
+    "jfnk_cfl_dt_noalloc": (C.c_int, [C.POINTER(Problem), _P, _D, _P, _P]),
     "jfnk_probe_enable": (C.c_int, [C.c_int32]),
     "jfnk_probe_count": (C.c_int, []),
     "jfnk_probe_name": (C.c_char_p, [C.c_int32]),

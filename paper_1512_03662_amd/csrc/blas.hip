@@ -57,24 +57,30 @@ __device__ __forceinline__ void block_finish(const double (&vals)[K], double* ou
   (void)out;
 }
 
+// Sum k of K over the nb partials, combined in block order by one block; the result is
+// valid in thread 0.
+template <class Op>
+__device__ __forceinline__ double finalize_one(const double* part, int nb, int K, int k, double* sm) {
+  constexpr int NW = kBlock / 64;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  double acc = Op::id;
+  for (int b = threadIdx.x; b < nb; b += kBlock) acc = Op::f(acc, part[(size_t)b * K + k]);
+  acc = wave_reduce<Op>(acc);
+  __syncthreads();
+  if (lane == 0) sm[wid] = acc;
+  __syncthreads();
+  double s = sm[0];
+  for (int w = 1; w < NW; ++w) s = Op::f(s, sm[w]);
+  return s;
+}
+
 // One block combines the nb partials of each of the K sums in block order.
 template <class Op>
 __global__ void __launch_bounds__(kBlock) k_finalize(const double* part, int nb, int K, double* out) {
-  constexpr int NW = kBlock / 64;
-  __shared__ double sm[NW];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __shared__ double sm[kBlock / 64];
   for (int k = 0; k < K; ++k) {
-    double acc = Op::id;
-    for (int b = threadIdx.x; b < nb; b += kBlock) acc = Op::f(acc, part[(size_t)b * K + k]);
-    acc = wave_reduce<Op>(acc);
-    __syncthreads();
-    if (lane == 0) sm[wid] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double s = sm[0];
-      for (int w = 1; w < NW; ++w) s = Op::f(s, sm[w]);
-      out[k] = s;
-    }
+    const double s = finalize_one<Op>(part, nb, K, k, sm);
+    if (threadIdx.x == 0) out[k] = s;
   }
 }
 
@@ -399,6 +405,25 @@ void launch_cfl_speed(const Grid& G, const double* X, double* out, const RedWS& 
   if (G.nd == 2) k_cfl_speed<2><<<b, kBlock, 0, s>>>(G, X, out, ws);
   else k_cfl_speed<3><<<b, kBlock, 0, s>>>(G, X, out, ws);
   finalize<OpMax>(ws, b, 1, out, s);
+}
+
+// the maximum of the partials (the same combination as k_finalize) turned into the time step
+// num / max on the device, num = cfl * min_d dx_d
+__global__ void __launch_bounds__(kBlock) k_finalize_cfl_dt(const double* part, int nb, double num, double* dt) {
+  __shared__ double sm[kBlock / 64];
+  const double m = finalize_one<OpMax>(part, nb, 1, 0, sm);
+  if (threadIdx.x == 0) *dt = num / m;
+}
+
+int cfl_partials(const Grid& G) { return red_blocks(G.N); }
+
+void launch_cfl_dt_dev(const Grid& G, const double* X, double num, double* part, double* dt, hipStream_t s) {
+  const int b = red_blocks(G.N);
+  RedWS ws;
+  ws.part = part;
+  if (G.nd == 2) k_cfl_speed<2><<<b, kBlock, 0, s>>>(G, X, nullptr, ws);
+  else k_cfl_speed<3><<<b, kBlock, 0, s>>>(G, X, nullptr, ws);
+  k_finalize_cfl_dt<<<1, kBlock, 0, s>>>(part, b, num, dt);
 }
 
 }  // namespace jfnk

@@ -70,6 +70,9 @@ void launch_scaled_maxabs(const Grid& G, const double* X, const double* V, doubl
                           double* out, const RedWS& ws, hipStream_t s);
 // max over cells of |u_c| + c_s (CFL)
 void launch_cfl_speed(const Grid& G, const double* X, double* out, const RedWS& ws, hipStream_t s);
+// *dt = num / max_c(|u_c| + c_s) on the device, with cfl_partials(G) block partials in part
+int cfl_partials(const Grid& G);
+void launch_cfl_dt_dev(const Grid& G, const double* X, double num, double* part, double* dt, hipStream_t s);
 
 // ---- physics-based preconditioner ------------------------------------------------------
 struct Level {              // one multigrid level of one elliptic operator

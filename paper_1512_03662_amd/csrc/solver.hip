@@ -164,8 +164,8 @@ Grid make_grid(const jfnk_problem& p) {
   return G;
 }
 
-void validate(const jfnk_problem* p, const jfnk_opts* o) {
-  if (!p || !o) throw InvErr("null problem or options");
+void validate_problem(const jfnk_problem* p) {
+  if (!p) throw InvErr("null problem");
   if (p->ndim != 2 && p->ndim != 3) throw InvErr("ndim must be 2 or 3");
   double cells = 1.0;
   for (int d = 0; d < p->ndim; ++d) {
@@ -182,6 +182,11 @@ void validate(const jfnk_problem* p, const jfnk_opts* o) {
   if (p->chi_model == JFNK_CHI_POWER && !(p->chi_tref > 0.0)) throw InvErr("chi_tref must be > 0");
   if (!(p->theta > 0.0 && p->theta <= 1.0)) throw InvErr("theta must be in (0, 1]");
   if (!(p->a_rad >= 0.0 && p->a_rad < HUGE_VAL)) throw InvErr("a_rad must be finite and >= 0");
+}
+
+void validate(const jfnk_problem* p, const jfnk_opts* o) {
+  if (!p || !o) throw InvErr("null problem or options");
+  validate_problem(p);
   if (o->gmres_m < 1 || o->gmres_m > kMaxK - 2) throw InvErr("gmres_m out of range");
   if (o->gmres_maxit < 1) throw InvErr("gmres_maxit must be >= 1");
   if (o->newton_max < 1 || o->newton_min < 1) throw InvErr("newton_max/newton_min must be >= 1");
@@ -191,6 +196,25 @@ void validate(const jfnk_problem* p, const jfnk_opts* o) {
   if (o->cg_maxit < 0) throw InvErr("cg_maxit must be >= 0");
   if (o->pc_schur != 0 && o->pc_schur != 1) throw InvErr("pc_schur must be 0 or 1");
 }
+
+}  // namespace
+
+namespace jfnk {
+// Grid of a problem; a non-empty return is the reason the problem is refused.
+std::string grid_of_problem(const jfnk_problem* p, Grid* G) {
+  try {
+    validate_problem(p);
+    *G = make_grid(*p);
+  } catch (const InvErr& e) {
+    return e.msg;
+  }
+  return std::string();
+}
+// message returned by jfnk_last_error(NULL) for calls made without a context
+void set_context_free_error(const std::string& msg) { g_create_err = msg; }
+}  // namespace jfnk
+
+namespace {
 
 // ---- multigrid hierarchy ----------------------------------------------------------------
 bool coarsenable(const int* n, int nd) {
