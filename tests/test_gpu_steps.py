@@ -119,13 +119,21 @@ COUNT_CASES = {
                                                  steps=1, cfl=100.0), 100.0, "sound_thermal", "fd"),
     "polytrope_32_exact": (lambda: W.polytrope((32, 32), 10.0, mach=1e-3, seed=5, chi_model="const",
                                                steps=1, cfl=50.0), 50.0, "sound_thermal", "exact"),
+    "polytrope_32_thermal_exact": (lambda: W.polytrope((32, 32), 10.0, mach=1e-3, seed=5, chi_model="power",
+                                                       steps=1, cfl=100.0), 100.0, "sound_thermal", "exact"),
 }
 
 
 @pytest.mark.parametrize("name", sorted(COUNT_CASES))
 def test_iteration_counts_match_the_oracle(name):
     """The GPU runs the oracle's algorithm (Newton, FGMRES(30) with CGS2, MG-CG to 1e-4):
-    Newton iterations, GMRES iterations and CG iterations per step are the same."""
+    Newton and GMRES iterations per step are the same.  The CG total is the same up to a few
+    solves that stop one iteration apart: late Arnoldi vectors amplify rounding differences
+    (summation order), and the stopping test ||r|| < eta' ||b|| of a solve that ends near
+    the threshold can fall on the other side.  The oracle itself shows this: perturbing X^0
+    by 1e-15 relative changes its CG total on the thermal 32^2 case by up to 2 of 1243
+    (exact J.v) and 1281 (FD), with Newton and GMRES counts unchanged.  The bar is 0.5 %
+    of the CG total."""
     J = _lib()
     mk, cfl, pc, jv = COUNT_CASES[name]
     w = mk()
@@ -138,7 +146,8 @@ def test_iteration_counts_match_the_oracle(name):
     got = (st["newton_its"], st["gmres_its"], st["cg_its"])
     ref = (st_o.newton_its, sum(st_o.gmres_its), sum(st_o.cg_its))
     print(f"# counts {name}: gpu {got} oracle {ref} (per Newton: {st_o.gmres_its})", flush=True)
-    assert got == ref
+    assert got[:2] == ref[:2]
+    assert abs(got[2] - ref[2]) <= 0.005 * ref[2]
     ctx.close()
 
 
