@@ -181,14 +181,23 @@ def test_implicit_steps_gradient_vs_oracle_chain():
     g2 = X2t.grad.numpy()
     g1, _ = adjoint_step_exact(P, X2, X1, dt, g2)
     g0, _ = adjoint_step_exact(P, X1, X0, dt, g1)
-    for k in range(P.nvar):
-        assert np.max(np.abs(got[k] - g0[k])) <= 1e-6 * np.max(np.abs(g0[k])), k
+    err = [float(np.max(np.abs(got[k] - g0[k])) / np.max(np.abs(g0[k]))) for k in range(P.nvar)]
+    print(f"# gradient vs oracle LU chain, per variable: {err}", flush=True)
+    # the oracle's own FGMRES adjoint at the same GMRES tolerance (1e-11) meets the LU chain
+    # to 1e-10 on this case (scaled transposed operator's condition number ~2e7)
+    assert max(err) <= 1e-8, err
 
 
 def test_implicit_steps_gradient_fd():
     """Gradient of total kinetic energy after 2 steps w.r.t. the initial temperature, through
-    ImplicitSteps, against central differences along 8 seeded directions (1e-4: the
-    difference straddles rare upwind switches)."""
+    ImplicitSteps, against central differences (eps = 1e-7) of the GPU's own steps along 8
+    seeded directions.  The adjoint differentiates the upwind and limiter branches taken at
+    the converged states; a difference whose +eps and -eps trajectories take other branches
+    at some faces measures the slope across those kinks.  The oracle's trajectories (CPU
+    pin in test_oracle_gradient_branches.py) change no branch along directions 2001 and 2004
+    (there the oracle's difference quotient matches its LU adjoint chain to 2e-9) and 8-28
+    branches along the others (1e-6 to 1.2e-5 apart; at eps = 1e-5 several hundred branches
+    and up to 4e-3).  Bars: 1e-5 along 2001 and 2004, 1e-4 along the others."""
     J = _lib()
     w_ = W.polytrope((24, 24), 10.0, mach=1e-3, seed=1004, chi_model="power", steps=2, cfl=50.0)
     pd, X0 = w_["problem"], w_["X0"]
@@ -236,5 +245,7 @@ def test_implicit_steps_gradient_fd():
                 ctx.implicit_step(Xt, dtk)
             vals.append(float(ke(Xt)))
         fd = (vals[0] - vals[1]) / (2 * eps)
-        assert abs(fd - an) <= 1e-4 * abs(an), (k, fd, an)
+        rel = abs(fd - an) / abs(an)
+        print(f"# direction {2001 + k}: relative difference {rel:.2e}", flush=True)
+        assert rel <= (1e-5 if k in (0, 3) else 1e-4), (k, fd, an)
     del T0
