@@ -202,10 +202,13 @@ def main():
     print(f"# probe pass ({pk} step(s))", file=sys.stderr, flush=True)
     from paper_1512_03662_amd import _native as Nat
     Nat.probe_enable(True)
-    run_steps(ctx, pk)
+    ctx.set_opts(phase_timing=1)
+    _, stats_probe, _ = run_steps(ctx, pk)
+    ctx.set_opts(phase_timing=0)
     torch.cuda.synchronize()
     probes = Nat.probe_results()
     Nat.probe_enable(False)
+    phase_ms = {k: sum(s[k] for s in stats_probe) / pk for k in ("t_resid", "t_jv", "t_prec", "t_orth")}
     dom = max(probes.items(), key=lambda kv: kv[1][0])
     dom_name, (dom_ms, dom_n, dom_bytes) = dom
     avg_s = dom_ms * 1e-3 / dom_n
@@ -291,6 +294,7 @@ def main():
         "compare": compare,
         "tuned": tuned,
         "probe_ms": {k: round(v[0], 3) for k, v in sorted(probes.items(), key=lambda kv: -kv[1][0])},
+        "phase_ms_per_step": phase_ms,
     }
     if args.workload == "stratified_2d_kappa" and not args.no_adjoint:
         print("# adjoint run", file=sys.stderr, flush=True)

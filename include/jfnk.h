@@ -93,6 +93,8 @@ typedef struct {
                           * du exactly, keeping -dt div F~_u in the pressure right-hand  *
                           * side (exact inverse of J at a uniform state at rest without  *
                           * gravity or conduction)                                        */
+  int32_t phase_timing;  /* 1: time the phases of a step with HIP events on the context's  *
+                          * stream (jfnk_step_stats t_*); 0: no events (t_* = 0)          */
 } jfnk_opts;
 
 typedef struct {
@@ -104,11 +106,17 @@ typedef struct {
   double f_norm;         /* ||L^-1 F|| at the last Newton iterate                       */
   double last_dx_norm;   /* ||R^-1 dX||_inf of the last correction                      */
   double dt;             /* time step used                                              */
+  /* GPU time (ms, HIP events on the context's stream, host waits inside a phase included)
+   * of the step's phases when opts.phase_timing = 1, else 0: the Newton residual with its
+   * norms; the J.v products (FD: with the direction's norm); the preconditioner, its
+   * set-up (elliptic coefficients, multigrid hierarchy, coarse inverse) included; the
+   * Gram-Schmidt passes and normalisation of the Arnoldi vectors.                       */
+  double t_resid, t_jv, t_prec, t_orth;
 } jfnk_step_stats;
 
 /* Fill *opts with the defaults: newton_tol 1e-8, newton_max 20, newton_min 2, gmres_m 30,
  * gmres_maxit 300, gmres_eta 1e-4, JV_FD, fd_lambda 1e-7, alpha1 1e-5, alpha2 1,
- * PC_SOUND, FP64, cg_eta 1e-4, cg_maxit 50.                                            */
+ * PC_SOUND, FP64, cg_eta 1e-4, cg_maxit 50, pc_schur 0, phase_timing 0.               */
 void jfnk_default_opts(jfnk_opts* opts);
 
 /* Create a context for one problem on one HIP stream (hip_stream: hipStream_t or NULL for

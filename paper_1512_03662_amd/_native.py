@@ -62,6 +62,7 @@ class Opts(C.Structure):
         ("cg_eta", C.c_double),
         ("cg_maxit", C.c_int32),
         ("pc_schur", C.c_int32),
+        ("phase_timing", C.c_int32),
     ]
 
 
@@ -75,6 +76,10 @@ class StepStats(C.Structure):
         ("f_norm", C.c_double),
         ("last_dx_norm", C.c_double),
         ("dt", C.c_double),
+        ("t_resid", C.c_double),
+        ("t_jv", C.c_double),
+        ("t_prec", C.c_double),
+        ("t_orth", C.c_double),
     ]
 
     def as_dict(self):

@@ -80,6 +80,15 @@ struct jfnk_ctx {
   // adjoint
   double* vjps = nullptr;   // scratch of the transposed products
   bool adj = false;         // FGMRES works on the transposed system
+
+  // per-phase GPU time of a step (opts.phase_timing): start/stop event pairs recorded on the
+  // stream around each phase, read back after the next host synchronisation
+  static constexpr int kPhasePairs = 16;
+  hipEvent_t pev[2 * kPhasePairs] = {};
+  int pphase[kPhasePairs] = {};
+  int pused = 0;
+  bool pstarted = false;    // a start event is recorded in slot pused
+  double pms[4] = {};       // residual, J.v, preconditioner, orthogonalisation (ms)
 };
 
 static std::string g_create_err;
@@ -122,11 +131,61 @@ void check_launch() { HIPX(hipGetLastError()); }
 void sync(jfnk_ctx* c) { HIPX(hipStreamSynchronize(c->stream)); }
 
 // copy device scalars [first, first+count) to the host mirror and wait
+// ---- per-phase timing ----------------------------------------------------------------------
+enum Phase { PH_RESID = 0, PH_JV = 1, PH_PREC = 2, PH_ORTH = 3 };
+
+// adds the elapsed times of the recorded pairs (the stream has been synchronised)
+void phase_flush(jfnk_ctx* c) {
+  for (int i = 0; i < c->pused; ++i) {
+    float ms = 0.0f;
+    HIPX(hipEventElapsedTime(&ms, c->pev[2 * i], c->pev[2 * i + 1]));
+    c->pms[c->pphase[i]] += ms;
+  }
+  c->pused = 0;
+}
+
+void phase_begin(jfnk_ctx* c) {
+  if (!c->opts.phase_timing) return;
+  if (!c->pev[0])
+    for (auto& e : c->pev) HIPX(hipEventCreate(&e));
+  if (c->pused == jfnk_ctx::kPhasePairs) {  // pool full: wait for the recorded pairs
+    HIPX(hipStreamSynchronize(c->stream));
+    phase_flush(c);
+  }
+  HIPX(hipEventRecord(c->pev[2 * c->pused], c->stream));
+  c->pstarted = true;
+}
+
+void phase_end(jfnk_ctx* c, int ph) {
+  if (!c->opts.phase_timing || !c->pstarted) return;
+  HIPX(hipEventRecord(c->pev[2 * c->pused + 1], c->stream));
+  c->pphase[c->pused++] = ph;
+  c->pstarted = false;
+}
+
 void pull(jfnk_ctx* c, int first, int count) {
   check_launch();
   HIPX(hipMemcpyAsync(c->hscal + first, c->scal + first, count * sizeof(double),
                       hipMemcpyDeviceToHost, c->stream));
   sync(c);
+  if (c->pused) phase_flush(c);
+}
+
+// starts a step's phase clocks; phase_finish writes them into the step's statistics
+void phase_start(jfnk_ctx* c) {
+  c->pused = 0;
+  c->pstarted = false;
+  for (double& v : c->pms) v = 0.0;
+}
+void phase_finish(jfnk_ctx* c, jfnk_step_stats* S) {
+  if (c->opts.phase_timing) {
+    sync(c);
+    phase_flush(c);
+  }
+  S->t_resid = c->pms[PH_RESID];
+  S->t_jv = c->pms[PH_JV];
+  S->t_prec = c->pms[PH_PREC];
+  S->t_orth = c->pms[PH_ORTH];
 }
 
 void push(jfnk_ctx* c, int first, int count) {
@@ -195,6 +254,7 @@ void validate(const jfnk_problem* p, const jfnk_opts* o) {
   if (o->ell_precision != JFNK_FP64 && o->ell_precision != JFNK_FP32) throw InvErr("bad ell_precision");
   if (o->cg_maxit < 0) throw InvErr("cg_maxit must be >= 0");
   if (o->pc_schur != 0 && o->pc_schur != 1) throw InvErr("pc_schur must be 0 or 1");
+  if (o->phase_timing != 0 && o->phase_timing != 1) throw InvErr("phase_timing must be 0 or 1");
 }
 
 }  // namespace
@@ -646,7 +706,9 @@ GmresOut fgmres(jfnk_ctx* c, const double* X, double beta0, double sign) {
       launch_axpy(n, sign / beta, c->W, c->V, s);
     } else {
       // r = sign W - A dX
+      phase_begin(c);
       apply_J(c, X, c->dX, c->W2);
+      phase_end(c, PH_JV);
       launch_fill(n, 0.0, c->V, s);
       launch_axpy(n, sign, c->W, c->V, s);
       launch_axpy(n, -1.0, c->W2, c->V, s);
@@ -669,20 +731,30 @@ GmresOut fgmres(jfnk_ctx* c, const double* X, double beta0, double sign) {
       double* Vj = c->V + (size_t)j * n;
       double* Zj = c->Z + (size_t)j * n;
       double* w = c->V + (size_t)(j + 1) * n;
+      phase_begin(c);
       if (c->adj) precond_T(c, X, Vj, 1, Zj);
       else precond(c, X, Vj, 1, Zj);
+      phase_end(c, PH_PREC);
+      phase_begin(c);
       apply_J(c, X, Zj, w);
+      phase_end(c, PH_JV);
       const int K = j + 1;
+      phase_begin(c);
       launch_multidot(n, c->V, n, K, w, c->scal + S_H1, c->red, s);
       launch_cgs2_update_dot(n, c->V, n, K, c->scal + S_H1, w, c->scal + S_H2, c->red, s);
       launch_cgs2_update_norm(n, c->V, n, K, c->scal + S_H2, w, w, c->scal + S_NRM3, c->red, s);
+      phase_end(c, PH_ORTH);
       pull(c, S_H1, S_NRM3 + 1 - S_H1);
       double hn2 = c->hscal[S_NRM3];
       if (!std::isfinite(hn2)) throw FiniteErr("non-finite Arnoldi vector");
       double hn = std::sqrt(hn2);
       for (int i = 0; i < K; ++i) Hx(i, j) = c->hscal[S_H1 + i] + c->hscal[S_H2 + i];
       Hx(j + 1, j) = hn;
-      if (hn > 0.0) launch_scale_by_inv_sqrt(n, w, c->scal + S_NRM3, w, s);
+      if (hn > 0.0) {
+        phase_begin(c);
+        launch_scale_by_inv_sqrt(n, w, c->scal + S_NRM3, w, s);
+        phase_end(c, PH_ORTH);
+      }
       for (int i = 0; i < j; ++i) {
         double t = cs[i] * Hx(i, j) + sn[i] * Hx(i + 1, j);
         Hx(i + 1, j) = -sn[i] * Hx(i, j) + cs[i] * Hx(i + 1, j);
@@ -747,10 +819,12 @@ int implicit_step(jfnk_ctx* c, double* X, double dt, jfnk_step_stats* st) {
   hipStream_t s = c->stream;
   jfnk_step_stats S{};
   S.dt = dt;
+  phase_start(c);
   set_state(c, X, dt);
   c->cg_its = 0;
   int status = JFNK_E_NEWTON_NOCONV;
   for (int k = 0; k < o.newton_max; ++k) {
+    phase_begin(c);
     // W = L^-1 F(X), G0 = U/dt - theta R
     ResidArgs a;
     a.X = X;
@@ -764,6 +838,7 @@ int implicit_step(jfnk_ctx* c, double* X, double dt, jfnk_step_stats* st) {
     launch_resid(G, a, 0, s);
     launch_dot<double>(c->n, c->W, c->W, c->scal + S_FN2, c->red, s);
     if (o.jv_mode == JFNK_JV_FD) launch_scaled_norm2(G, X, X, o.alpha2, c->scal + S_XN2, c->red, s);
+    phase_end(c, PH_RESID);
     pull(c, S_FN2, 1);
     double fn = std::sqrt(c->hscal[S_FN2]);
     if (!std::isfinite(fn)) throw FiniteErr("non-finite residual norm");
@@ -771,7 +846,11 @@ int implicit_step(jfnk_ctx* c, double* X, double dt, jfnk_step_stats* st) {
     S.f_norm = fn;
     double dxmax = 0.0;
     if (fn > 0.0) {
-      if (o.precond != JFNK_PC_NONE) ell_setup(c, X, c->prob.theta * dt);
+      if (o.precond != JFNK_PC_NONE) {
+        phase_begin(c);
+        ell_setup(c, X, c->prob.theta * dt);
+        phase_end(c, PH_PREC);
+      }
       GmresOut go = fgmres(c, X, fn, -1.0);
       S.gmres_its += go.iters;
       launch_scaled_maxabs(G, X, c->dX, o.alpha2, c->scal + S_DXMAX, c->red, s);
@@ -789,6 +868,7 @@ int implicit_step(jfnk_ctx* c, double* X, double dt, jfnk_step_stats* st) {
     }
   }
   S.cg_its = c->cg_its;
+  phase_finish(c, &S);
   if (st) *st = S;
   if (status != JFNK_OK) c->err = "Newton did not converge within newton_max iterations";
   return status;
@@ -849,6 +929,7 @@ int adjoint_step(jfnk_ctx* c, const double* Xn1, const double* Xn, double dt, co
   S.dt = dt;
   c->dt = dt;
   c->cg_its = 0;
+  phase_start(c);
   int status = JFNK_OK;
   // rhs of the scaled transposed system: R gbar (R at X^{n+1})
   launch_scale_LR(G, Xn1, o.alpha2, 1, gbar, c->W, 1, s);
@@ -876,11 +957,14 @@ int adjoint_step(jfnk_ctx* c, const double* Xn1, const double* Xn, double dt, co
   check_launch();
   S.newton_its = 0;
   S.cg_its = c->cg_its;
+  phase_finish(c, &S);
   if (st) *st = S;
   return status;
 }
 
 void destroy_bufs(jfnk_ctx* c) {
+  for (auto& e : c->pev)
+    if (e) (void)hipEventDestroy(e);
   for (void* p : c->allocs) (void)hipFree(p);
   c->allocs.clear();
   if (c->hscal) (void)hipHostFree(c->hscal);
@@ -975,6 +1059,7 @@ void jfnk_default_opts(jfnk_opts* o) {
   o->cg_eta = 1e-4;
   o->cg_maxit = 50;
   o->pc_schur = 0;
+  o->phase_timing = 0;
 }
 
 int jfnk_create(const jfnk_problem* prob, const jfnk_opts* opts, void* hip_stream, jfnk_ctx** out) {

@@ -29,7 +29,8 @@ def test_struct_layout_matches_c(tmp_path):
         'printf("%zu %zu %zu\\n", sizeof(jfnk_problem), sizeof(jfnk_opts), sizeof(jfnk_step_stats));\n'
         'printf("%zu %zu %zu\\n", offsetof(jfnk_problem, qwall), offsetof(jfnk_problem, theta), '
         "offsetof(jfnk_opts, cg_maxit));\n"
-        'printf("%zu\\n", offsetof(jfnk_step_stats, dt));\n'
+        'printf("%zu %zu %zu\\n", offsetof(jfnk_step_stats, dt), offsetof(jfnk_step_stats, t_orth), '
+        "offsetof(jfnk_opts, phase_timing));\n"
         "return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
@@ -41,6 +42,7 @@ def test_struct_layout_matches_c(tmp_path):
     assert vals[3] == N.Problem.qwall.offset and vals[4] == N.Problem.theta.offset
     assert vals[5] == N.Opts.cg_maxit.offset
     assert vals[6] == N.StepStats.dt.offset
+    assert vals[7] == N.StepStats.t_orth.offset and vals[8] == N.Opts.phase_timing.offset
 
 
 def test_defaults_are_the_paper_values():

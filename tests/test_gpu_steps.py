@@ -178,3 +178,31 @@ def test_fp32_elliptic_against_the_oracle_fp32_mgcg(shape, bc):
     assert max(e32) <= 5e-6, e32
     assert max(e64) <= 5e-6, e64
     ctx.close()
+
+
+def test_phase_timing_of_a_step():
+    """opts.phase_timing = 1: the step's residual, J.v, preconditioner and orthogonalisation
+    phases get positive GPU times that sum to less than the step's wall time; 0: all zero.
+    The result of the step does not change."""
+    import time
+    J = _lib()
+    w = W.polytrope((64, 64), 10.0, mach=1e-3, seed=5, chi_model="power", steps=1, cfl=100.0)
+    ctx = J.Context(w["problem"], precond="sound_thermal")
+    X0 = T(w["X0"])
+    dt = ctx.cfl_dt(X0, 100.0)
+    Xa = X0.clone()
+    st0 = ctx.implicit_step(Xa, dt)
+    assert (st0["t_resid"], st0["t_jv"], st0["t_prec"], st0["t_orth"]) == (0.0, 0.0, 0.0, 0.0)
+    ctx.set_opts(phase_timing=1)
+    Xb = X0.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st1 = ctx.implicit_step(Xb, dt)
+    wall_ms = 1e3 * (time.perf_counter() - t0)
+    ph = [st1["t_resid"], st1["t_jv"], st1["t_prec"], st1["t_orth"]]
+    print(f"# phases (ms) {ph}, wall {wall_ms:.2f}", flush=True)
+    assert all(v > 0.0 for v in ph)
+    assert sum(ph) <= wall_ms
+    assert torch.equal(Xa, Xb)
+    assert (st0["newton_its"], st0["gmres_its"], st0["cg_its"]) == (st1["newton_its"], st1["gmres_its"], st1["cg_its"])
+    ctx.close()
