@@ -17,6 +17,7 @@ struct ResidArgs {
   double cU = 0.0, cR = 0.0;         // out = cU U + cR R - B
   const double* fd_norms = nullptr;  // device [||R^-1 X||^2, ||R^-1 V||^2] (FD mode)
   double fd_lambda = 1e-7;
+  double* shift = nullptr;           // FD mode: state-sized scratch for X + delta V, or null
   int scaleL = 0;                    // divide each row by L
   double alpha1 = 1e-5;
 };

@@ -51,7 +51,7 @@ const char* const kFamNames[KF_COUNT] = {
     "vjp_fold", "cgs2_multidot", "cgs2_update_dot", "cgs2_update_norm", "lincomb",
     "mg_presmooth", "mg_prolong_smooth1", "mg_smooth2", "mg_coarse", "cg_apply_dot",
     "cg_update", "cg_pupdate", "dot", "pbp_in", "pbp_out", "scaled_norm", "mg_restrict_resid",
-    "mg_down", "mg_up"};
+    "mg_down", "mg_up", "fd_shift"};
 
 bool probe_events(int fam, double bytes, hipEvent_t* start, hipEvent_t* stop) {
   *start = nullptr;

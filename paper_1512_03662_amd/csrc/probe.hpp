@@ -31,6 +31,7 @@ enum KFam {
   KF_MG_RESTRICT,
   KF_MG_DOWN,
   KF_MG_UP,
+  KF_FD_SHIFT,
   KF_COUNT
 };
 

@@ -15,6 +15,9 @@
 // rows of its cell.  The scalar type is double for values, dual for the exact forward-mode
 // product (branches frozen at the value), and the finite-difference product evaluates F at
 // X + delta V with delta of eq. pert_old.
+#include <algorithm>
+#include <type_traits>
+
 #include "common.hpp"
 #include "kernels.hpp"
 #include "probe.hpp"
@@ -465,7 +468,19 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
   }
 }
 
-template <int ND, bool RAD>
+// Xs = X + delta V with delta of eq. pert_old from the device norms (0 when V = 0), the
+// state at which the finite-difference product evaluates F
+__global__ void __launch_bounds__(kBlock) k_fd_shift(size_t n, const double* X, const double* V,
+                                                     const double* norms, double lam, double* Xs) {
+  const double xn2 = norms[0], zn2 = norms[1];
+  const double delta = (zn2 > 0.0) ? lam * (lam + sqrt(xn2) / sqrt(zn2)) : 0.0;
+  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
+    Xs[i] = X[i] + delta * V[i];
+}
+
+// PRE: F is evaluated at the precomputed X + delta V in a.shift (one array per value, as
+// for F itself); otherwise every load forms X + delta V from X and V
+template <int ND, bool RAD, bool PRE>
 __global__ void __launch_bounds__(kBlock) k_resid_fd(Grid G, ResidArgs a) {
   const double xn2 = a.fd_norms[0], zn2 = a.fd_norms[1];
   if (!(zn2 > 0.0)) {  // the same for every thread: no block-wide work follows
@@ -483,7 +498,11 @@ __global__ void __launch_bounds__(kBlock) k_resid_fd(Grid G, ResidArgs a) {
   }
   const double lam = a.fd_lambda;
   const double delta = lam * (lam + sqrt(xn2) / sqrt(zn2));
-  LoadShift ld{a.X, a.V, delta, G.N};
+  using LD = std::conditional_t<PRE, LoadVal<double>, LoadShift>;
+  LD ld = [&]() {
+    if constexpr (PRE) return LoadVal<double>{a.shift, G.N};
+    else return LoadShift{a.X, a.V, delta, G.N};
+  }();
   double R[2 + ND], U[2 + ND], L[2 + ND];
   int lin;
   if (!tile_RU<ND, RAD>(G, ld, R, U, &lin)) return;
@@ -531,14 +550,17 @@ static dim3 tile_grid(const Grid& G) {
 template <bool RAD>
 static void launch_resid_k(const Grid& G, const ResidArgs& a, int mode, int fam, double bytes, dim3 gr,
                            dim3 bl, hipStream_t s) {
+  const bool pre = a.shift != nullptr;
   if (G.nd == 2) {
     if (mode == 0) launch_k(fam, bytes, k_resid_value<2, RAD>, gr, bl, 0, s, G, a);
     else if (mode == 1) launch_k(fam, bytes, k_resid_tangent<2, RAD>, gr, bl, 0, s, G, a);
-    else launch_k(fam, bytes, k_resid_fd<2, RAD>, gr, bl, 0, s, G, a);
+    else if (pre) launch_k(fam, bytes, k_resid_fd<2, RAD, true>, gr, bl, 0, s, G, a);
+    else launch_k(fam, bytes, k_resid_fd<2, RAD, false>, gr, bl, 0, s, G, a);
   } else {
     if (mode == 0) launch_k(fam, bytes, k_resid_value<3, RAD>, gr, bl, 0, s, G, a);
     else if (mode == 1) launch_k(fam, bytes, k_resid_tangent<3, RAD>, gr, bl, 0, s, G, a);
-    else launch_k(fam, bytes, k_resid_fd<3, RAD>, gr, bl, 0, s, G, a);
+    else if (pre) launch_k(fam, bytes, k_resid_fd<3, RAD, true>, gr, bl, 0, s, G, a);
+    else launch_k(fam, bytes, k_resid_fd<3, RAD, false>, gr, bl, 0, s, G, a);
   }
 }
 
@@ -557,6 +579,12 @@ void launch_resid(const Grid& G, const ResidArgs& a, int mode, hipStream_t s) {
   } else {
     fam = KF_RESID_FD;
     bytes = nvN * 4;
+    if (a.shift) {
+      const size_t n = (size_t)(2 + G.nd) * G.N;
+      const int nb = (int)std::min<size_t>((n + kBlock - 1) / kBlock, 8192);
+      launch_k(KF_FD_SHIFT, nvN * 3, k_fd_shift, dim3(nb), dim3(kBlock), 0, s, n, a.X, a.V, a.fd_norms,
+               a.fd_lambda, a.shift);
+    }
   }
   if (G.a_rad == 0.0) launch_resid_k<false>(G, a, mode, fam, bytes, gr, bl, s);
   else launch_resid_k<true>(G, a, mode, fam, bytes, gr, bl, s);

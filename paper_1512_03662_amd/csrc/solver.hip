@@ -60,8 +60,8 @@ struct jfnk_ctx {
   std::vector<void*> allocs;
 
   // state-sized buffers
-  double *bn = nullptr, *Xn = nullptr, *F = nullptr, *G0 = nullptr, *W = nullptr, *W2 = nullptr,
-         *dX = nullptr, *Xk = nullptr, *V = nullptr, *Z = nullptr;
+  double *bn = nullptr, *Xn = nullptr, *G0 = nullptr, *W = nullptr, *W2 = nullptr,
+         *dX = nullptr, *Xk = nullptr /* X + delta Z of the FD product */, *V = nullptr, *Z = nullptr;
   double* scal = nullptr;   // device scalars
   double* hscal = nullptr;  // pinned host mirror
   RedWS red;
@@ -673,6 +673,7 @@ void apply_J(jfnk_ctx* c, const double* X, const double* z, double* out) {
     a.B = c->G0;
     a.fd_norms = c->scal + S_XN2;
     a.fd_lambda = c->opts.fd_lambda;
+    a.shift = c->Xk;
     launch_resid(G, a, 2, c->stream);
   }
 }
@@ -981,7 +982,6 @@ void create(jfnk_ctx* c) {
   size_t n = c->n;
   c->bn = dalloc<double>(c, n);
   c->Xn = dalloc<double>(c, n);
-  c->F = dalloc<double>(c, n);
   c->G0 = dalloc<double>(c, n);
   c->W = dalloc<double>(c, n);
   c->W2 = dalloc<double>(c, n);
@@ -1168,6 +1168,7 @@ int jfnk_jvp(jfnk_ctx* c, const double* X, const double* v, double* Jv, int32_t 
     a.B = c->G0;
     a.fd_norms = c->scal + S_XN2;
     a.fd_lambda = c->opts.fd_lambda;
+    a.shift = c->Xk;
     launch_resid(c->G, a, 2, c->stream);
   } else {
     throw InvErr("bad mode");
