@@ -206,3 +206,36 @@ def test_phase_timing_of_a_step():
     assert torch.equal(Xa, Xb)
     assert (st0["newton_its"], st0["gmres_its"], st0["cg_its"]) == (st1["newton_its"], st1["gmres_its"], st1["cg_its"])
     ctx.close()
+
+
+VORTEX = [(1.0, 0.5), (1e6, 0.5), (1e10, 0.05)]
+
+
+@pytest.mark.parametrize("t_inf,cfl_adv", VORTEX, ids=[f"Tinf{t:g}_cfladv{c:g}" for t, c in VORTEX])
+def test_isentropic_vortex_step(t_inf, cfl_adv):
+    """The isentropic vortex of the paper's low-Mach test (64^2, Mach 0.1, 1e-4, 1e-6 for
+    T_inf = 1, 1e6, 1e10), one implicit step at the advective CFL number (dt = cfl_adv dx /
+    u_inf) with the sound preconditioner and the FD J.v: the GPU against the oracle's JFNK step
+    with the same options, state ||R^-1 (X_gpu - X_or)||_inf <= 1e-8 and the same Newton and
+    GMRES counts (CG within 0.5 %)."""
+    J = _lib()
+    w = W.isentropic_vortex_2d(n=64, t_inf=t_inf)
+    P = Problem.from_dict(w["problem"])
+    dt = cfl_adv * w["problem"]["dx"][0] / 1.0
+    print(f"# vortex T_inf {t_inf:g}, CFL_adv {cfl_adv:g}", flush=True)
+    st_o = Stats()
+    Xo = jfnk_step(P, w["X0"], dt, Opts(precond="sound", jv_mode="fd"), st_o)
+    assert st_o.converged
+    ctx = J.Context(w["problem"], precond="sound", jv_mode="fd")
+    Xg = T(w["X0"])
+    st = ctx.implicit_step(Xg, dt)
+    assert st["converged"] == 1
+    _, R = scaling_LR(P, Xo)
+    err = float(np.max(np.abs((H(Xg) - Xo) / R)))
+    got = (st["newton_its"], st["gmres_its"], st["cg_its"])
+    ref = (st_o.newton_its, sum(st_o.gmres_its), sum(st_o.cg_its))
+    print(f"#   gpu {got} oracle {ref}; ||R^-1 (X - X_or)||_inf {err:.3e}", flush=True)
+    assert err <= 1e-8, err
+    assert got[:2] == ref[:2]
+    assert abs(got[2] - ref[2]) <= 0.005 * ref[2]
+    ctx.close()
