@@ -43,7 +43,9 @@ enum {
   JFNK_E_DEVICE = -2,        /* HIP error, including out-of-memory at create           */
   JFNK_E_NONFINITE = -3,     /* NaN/Inf met in a norm                                  */
   JFNK_E_GMRES_NOCONV = -4,  /* linear solve hit gmres_maxit (Newton continues)        */
-  JFNK_E_NEWTON_NOCONV = -5  /* newton_max iterations without meeting newton_tol      */
+  JFNK_E_NEWTON_NOCONV = -5, /* newton_max iterations without meeting newton_tol      */
+  JFNK_E_INADMISSIBLE = -6   /* a Newton (or semi-implicit) update gives rho <= 0 or   *
+                              * e <= 0; X holds that iterate (no line search, Sect. 4.1) */
 };
 
 enum { JFNK_BC_PERIODIC = 0, JFNK_BC_WALL = 1 };
@@ -168,7 +170,9 @@ int jfnk_precond_apply_transpose(jfnk_ctx* ctx, const double* X, const double* w
 /* One implicit step: X holds X^n on entry and X^{n+1} on return (Sect. 4).  dt > 0 is
  * used as given.  Newton from X^n on the scaled system, FGMRES(m) with CGS2, J.v per
  * opts.jv_mode, right preconditioner per opts.precond.  Returns JFNK_OK when converged,
- * JFNK_E_NEWTON_NOCONV otherwise (X then holds the last iterate).  stats may be NULL.   */
+ * JFNK_E_NEWTON_NOCONV otherwise (X then holds the last iterate), JFNK_E_INADMISSIBLE when a
+ * correction gives rho <= 0 or e <= 0 somewhere (X holds that iterate; the paper's Newton
+ * iteration has no line search).  stats may be NULL.                                    */
 int jfnk_implicit_step(jfnk_ctx* ctx, double* X, double dt, jfnk_step_stats* stats);
 
 /* One step of the semi-implicit scheme used as a time stepper (Sect. 3.6): X holds X^n on

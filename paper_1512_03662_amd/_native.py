@@ -19,6 +19,7 @@ E_DEVICE = -2
 E_NONFINITE = -3
 E_GMRES_NOCONV = -4
 E_NEWTON_NOCONV = -5
+E_INADMISSIBLE = -6
 
 BC_PERIODIC, BC_WALL = 0, 1
 CHI_NONE, CHI_CONST, CHI_POWER = 0, 1, 2

@@ -366,18 +366,35 @@ void launch_scaled_norm2(const Grid& G, const double* X, const double* V, double
   }
   finalize<OpSum>(ws, b, 1, out, s);
 }
-void launch_scaled_maxabs(const Grid& G, const double* X, const double* V, double alpha2,
-                          double* out, const RedWS& ws, hipStream_t s) {
+// out[0] = max |V / R(X)|, out[1] = max over cells of -min(rho, e) of X + sgn V: the Newton
+// correction's size and whether the corrected state keeps rho > 0 and e > 0 (out[1] < 0)
+template <int ND, bool RAD>
+__global__ void __launch_bounds__(kBlock) k_newton_check(Grid G, const double* X, const double* V, double alpha2,
+                                                         double sgn, double* out, RedWS ws) {
+  double acc[2] = {0.0, -HUGE_VAL};
+  for (int lin = blockIdx.x * kBlock + threadIdx.x; lin < G.N; lin += gridDim.x * kBlock) {
+    Pos P = make_pos<ND>(G, lin);
+    double Rs[2 + ND];
+    cell_R_scale<ND, RAD>(G, P, X, alpha2, Rs);
+#pragma unroll
+    for (int v = 0; v < 2 + ND; ++v) acc[0] = nanmax(acc[0], fabs(V[v * G.N + lin] / Rs[v]));
+    const double r1 = X[lin] + sgn * V[lin], e1 = X[G.N + lin] + sgn * V[G.N + lin];
+    acc[1] = nanmax(acc[1], nanmax(-r1, -e1));
+  }
+  block_finish<OpMax, 2>(acc, out, ws);
+}
+void launch_newton_check(const Grid& G, const double* X, const double* V, double alpha2, double sgn,
+                         double* out, const RedWS& ws, hipStream_t s) {
   int b = red_blocks(G.N);
   const bool rad = G.a_rad != 0.0;
   if (G.nd == 2) {
-    if (rad) k_scaled_red<2, true, true><<<b, kBlock, 0, s>>>(G, X, V, alpha2, out, ws);
-    else k_scaled_red<2, true, false><<<b, kBlock, 0, s>>>(G, X, V, alpha2, out, ws);
+    if (rad) k_newton_check<2, true><<<b, kBlock, 0, s>>>(G, X, V, alpha2, sgn, out, ws);
+    else k_newton_check<2, false><<<b, kBlock, 0, s>>>(G, X, V, alpha2, sgn, out, ws);
   } else {
-    if (rad) k_scaled_red<3, true, true><<<b, kBlock, 0, s>>>(G, X, V, alpha2, out, ws);
-    else k_scaled_red<3, true, false><<<b, kBlock, 0, s>>>(G, X, V, alpha2, out, ws);
+    if (rad) k_newton_check<3, true><<<b, kBlock, 0, s>>>(G, X, V, alpha2, sgn, out, ws);
+    else k_newton_check<3, false><<<b, kBlock, 0, s>>>(G, X, V, alpha2, sgn, out, ws);
   }
-  finalize<OpMax>(ws, b, 1, out, s);
+  finalize<OpMax>(ws, b, 2, out, s);
 }
 
 // max_c (|u_c| + c_s), u_c the mean of the two faces of c along each axis (Introduction)

@@ -64,11 +64,12 @@ void launch_fill(size_t n, double v, double* y, hipStream_t s);
 template <class T>
 void launch_fill_t(size_t n, T v, T* y, hipStream_t s);
 
-// scaled norms of a state-shaped vector: out = sum (V/R(X))^2 ; max |V/R(X)|
+// scaled norm of a state-shaped vector: out = sum (V/R(X))^2
 void launch_scaled_norm2(const Grid& G, const double* X, const double* V, double alpha2,
                          double* out, const RedWS& ws, hipStream_t s);
-void launch_scaled_maxabs(const Grid& G, const double* X, const double* V, double alpha2,
-                          double* out, const RedWS& ws, hipStream_t s);
+// out[0] = max |V/R(X)|, out[1] = max -min(rho, e) of X + sgn V (negative: admissible)
+void launch_newton_check(const Grid& G, const double* X, const double* V, double alpha2, double sgn,
+                         double* out, const RedWS& ws, hipStream_t s);
 // max over cells of |u_c| + c_s (CFL)
 void launch_cfl_speed(const Grid& G, const double* X, double* out, const RedWS& ws, hipStream_t s);
 // *dt = num / max_c(|u_c| + c_s) on the device, with cfl_partials(G) block partials in part

@@ -27,7 +27,8 @@ enum Slot {
   S_XN2 = 0,   // ||R^-1 X||^2   (followed by S_ZN2: the finite-difference kernel reads both)
   S_ZN2 = 1,   // ||R^-1 Z_j||^2
   S_FN2 = 2,   // ||L^-1 F||^2
-  S_DXMAX = 3, // ||R^-1 dX||_inf
+  S_DXMAX = 3, // ||R^-1 dX||_inf   (followed by S_ADM: max -min(rho, e) of the corrected state)
+  S_ADM = 4,
   S_TMP = 9,   // ||b||^2 of an FP32 elliptic solve
   S_H1 = 16,                       // h of the first Gram-Schmidt pass (kMaxK)
   S_H2 = S_H1 + kMaxK,             // h of the second pass (kMaxK) then ||w||^2
@@ -114,6 +115,10 @@ struct InvErr {
 struct FiniteErr {
   std::string msg;
   explicit FiniteErr(std::string m) : msg(std::move(m)) {}
+};
+struct AdmissErr {
+  std::string msg;
+  explicit AdmissErr(std::string m) : msg(std::move(m)) {}
 };
 
 template <class T>
@@ -854,11 +859,13 @@ int implicit_step(jfnk_ctx* c, double* X, double dt, jfnk_step_stats* st) {
       }
       GmresOut go = fgmres(c, X, fn, -1.0);
       S.gmres_its += go.iters;
-      launch_scaled_maxabs(G, X, c->dX, o.alpha2, c->scal + S_DXMAX, c->red, s);
+      launch_newton_check(G, X, c->dX, o.alpha2, 1.0, c->scal + S_DXMAX, c->red, s);
       launch_axpy(c->n, 1.0, c->dX, X, s);
-      pull(c, S_DXMAX, 1);
+      pull(c, S_DXMAX, 2);
       dxmax = c->hscal[S_DXMAX];
       if (!std::isfinite(dxmax)) throw FiniteErr("non-finite Newton correction");
+      if (!(c->hscal[S_ADM] < 0.0))
+        throw AdmissErr("the Newton correction gives a state with rho <= 0 or e <= 0 (no line search)");
     }
     S.newton_its = k + 1;
     S.last_dx_norm = dxmax;
@@ -901,11 +908,13 @@ int si_step(jfnk_ctx* c, double* X, double dt, jfnk_step_stats* st) {
   if (!std::isfinite(S.f0_norm)) throw FiniteErr("non-finite residual norm");
   ell_setup(c, X, si_dt(c));
   precond(c, X, c->W, 0, c->dX);
-  launch_scaled_maxabs(G, X, c->dX, o.alpha2, c->scal + S_DXMAX, c->red, s);
+  launch_newton_check(G, X, c->dX, o.alpha2, -1.0, c->scal + S_DXMAX, c->red, s);
   launch_axpy(c->n, -1.0, c->dX, X, s);
-  pull(c, S_DXMAX, 1);
+  pull(c, S_DXMAX, 2);
   S.last_dx_norm = c->hscal[S_DXMAX];
   if (!std::isfinite(S.last_dx_norm)) throw FiniteErr("non-finite semi-implicit update");
+  if (!(c->hscal[S_ADM] < 0.0))
+    throw AdmissErr("the semi-implicit update gives a state with rho <= 0 or e <= 0");
   S.cg_its = c->cg_its;
   S.converged = 1;
   if (st) *st = S;
@@ -1034,6 +1043,10 @@ void create(jfnk_ctx* c) {
   catch (const FiniteErr& e) {                                                   \
     (ctx)->err = e.msg;                                                          \
     return JFNK_E_NONFINITE;                                                     \
+  }                                                                              \
+  catch (const AdmissErr& e) {                                                   \
+    (ctx)->err = e.msg;                                                          \
+    return JFNK_E_INADMISSIBLE;                                                  \
   }                                                                              \
   catch (...) {                                                                  \
     (ctx)->err = "unexpected host exception";                                    \

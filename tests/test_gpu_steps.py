@@ -239,3 +239,34 @@ def test_isentropic_vortex_step(t_inf, cfl_adv):
     assert got[:2] == ref[:2]
     assert abs(got[2] - ref[2]) <= 0.005 * ref[2]
     ctx.close()
+
+
+def test_taylor_green_hardest_row_exact_jv():
+    """The hardest row of the paper's Taylor-Green timing table (Mach 1e-6, CFL_hydro 4.9e5,
+    CFL_adv 0.49; the paper needed 291.5 GMRES iterations per Newton iteration) at 32^3 with
+    the exact forward-mode J.v: one step against the oracle's JFNK step with the same options
+    (complex-step J.v), ||R^-1 (X_gpu - X_or)||_inf <= 1e-8, the same Newton and GMRES counts
+    (CG within 0.5 %), and pressure stays positive.  With the finite-difference product this
+    row's first linear solve sits at the edge of convergence (see the study in the docs)."""
+    J = _lib()
+    w = W.taylor_green_3d(n=32, mach=1e-6, noise=0.0)
+    P = Problem.from_dict(w["problem"])
+    dt = cfl_dt(P, w["X0"], 4.9e5)
+    st_o = Stats()
+    Xo = jfnk_step(P, w["X0"], dt, Opts(precond="sound", jv_mode="exact"), st_o)
+    assert st_o.converged
+    ctx = J.Context(w["problem"], precond="sound", jv_mode="exact")
+    Xg = T(w["X0"])
+    st = ctx.implicit_step(Xg, dt)
+    assert st["converged"] == 1
+    _, R = scaling_LR(P, Xo)
+    X1 = H(Xg)
+    err = float(np.max(np.abs((X1 - Xo) / R)))
+    got = (st["newton_its"], st["gmres_its"], st["cg_its"])
+    ref = (st_o.newton_its, sum(st_o.gmres_its), sum(st_o.cg_its))
+    print(f"# hardest TGV row 32^3 exact J.v: gpu {got} oracle {ref}; ||R^-1 (X - X_or)||_inf {err:.3e}", flush=True)
+    assert err <= 1e-8, err
+    assert got[:2] == ref[:2]
+    assert abs(got[2] - ref[2]) <= 0.005 * ref[2]
+    assert np.min((w["problem"]["gamma"] - 1.0) * X1[0] * X1[1]) > 0.0
+    ctx.close()
