@@ -25,7 +25,7 @@ __device__ __forceinline__ double nanmax(double a, double b) {
 }
 struct OpMax {
   static __device__ __forceinline__ double f(double a, double b) { return nanmax(a, b); }
-  static constexpr double id = 0.0;  // reductions of non-negative values only
+  static constexpr double id = -HUGE_VAL;
 };
 
 template <class Op>
