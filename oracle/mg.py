@@ -15,7 +15,11 @@ preconditioner:
 * smoother: Chebyshev polynomial of degree 2 in D^-1 A on [lmax/4, lmax] with
   lmax = 2, the Gershgorin bound of D^-1 A (discs centred at 1 with radius < 1); the same
   smoother before and after the coarse correction keeps the V-cycle symmetric;
-* coarsest level: dense Cholesky (always in FP64).
+* coarsest level: dense Cholesky (always in FP64) while it has at most ``DENSE_MAX`` = 4096
+  cells.  A grid with an odd axis cannot be coarsened that far (for example the 72 x 65 x 65
+  grid of the paper's 3D red-giant run, Sect. 5.2); its coarsest level is then not solved
+  but smoothed: the same Chebyshev smoothing from zero, then again from that iterate (the
+  polynomial of D^-1 A applied twice keeps the V-cycle symmetric positive definite).
 
 ``dtype=np.float32`` emulates the mixed-precision variant: coefficients, vectors and dot
 products in FP32, the right-hand side divided by its FP64 2-norm before the cast, the
@@ -90,6 +94,7 @@ class Level:
 class Multigrid:
     LMAX = 2.0
     LMIN = 0.5
+    DENSE_MAX = 4096
 
     def __init__(self, op: EllOp, dtype=np.float64):
         self.dtype = dtype
@@ -107,8 +112,10 @@ class Multigrid:
             w_c = [_coarse_face_weights(cur.prob, cur.op.w[d], d) for d in range(cur.prob.nd)]
             self.levels.append(Level(pc, EllOp(pc, diag_c.astype(dtype), [w.astype(dtype) for w in w_c])))
         coarse = self.levels[-1]
-        A = coarse.op.to_sparse().toarray().astype(np.float64)
-        self.coarse_chol = sla.cho_factor(A, lower=True)
+        self.coarse_chol = None
+        if coarse.prob.ncell <= self.DENSE_MAX:
+            A = coarse.op.to_sparse().toarray().astype(np.float64)
+            self.coarse_chol = sla.cho_factor(A, lower=True)
 
     def smooth(self, lev: Level, b, x):
         """Degree-2 Chebyshev-Jacobi smoothing of A x = b starting from x."""
@@ -128,6 +135,8 @@ class Multigrid:
     def vcycle(self, b, level=0):
         lev = self.levels[level]
         if level == len(self.levels) - 1:
+            if self.coarse_chol is None:  # too large for the dense solve: smoothing only
+                return self.smooth(lev, b, self.smooth(lev, b, np.zeros_like(b)))
             x = sla.cho_solve(self.coarse_chol, b.ravel().astype(np.float64))
             return x.reshape(b.shape).astype(self.dtype)
         x = self.smooth(lev, b, np.zeros_like(b))

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/jfnk.h"
@@ -37,9 +38,12 @@ enum Slot {
   S_COUNT = S_Y + kMaxK
 };
 
+// coarsest levels with more cells than this are smoothed, not solved by a dense inverse
+constexpr int kDenseMaxN = 4096;
+
 struct EllOp {
   std::vector<Level> lv64, lv32;
-  double* Ainv = nullptr;   // dense inverse of the coarsest level
+  double* Ainv = nullptr;   // dense inverse of the coarsest level (null: smoothed bottom)
   int Nc = 0;
   std::vector<double> hA;   // host scratch
 };
@@ -77,6 +81,10 @@ struct jfnk_ctx {
   double* cgpart = nullptr;
   int cg_pred[2][2] = {{4, 4}, {4, 4}};  // previous iteration count per operator and precision
   int cg_its = 0;
+
+  // zero "coarse correction" (one element, strides 0) for the smoothing of a bottom level
+  double* zero64 = nullptr;
+  float* zero32 = nullptr;
 
   // adjoint
   double* vjps = nullptr;   // scratch of the transposed products
@@ -326,9 +334,12 @@ void build_hierarchy(jfnk_ctx* c, EllOp& op, bool want32) {
     if (want32) op.lv32.push_back(make_level(c, n, G.nd, true, false));
   }
   op.Nc = op.lv64.back().N;
-  if (op.Nc > 4096) throw InvErr("coarsest multigrid level too large (grid sizes need factors of 2)");
-  op.Ainv = dalloc<double>(c, (size_t)op.Nc * op.Nc);
-  op.hA.resize((size_t)op.Nc * op.Nc);
+  // an odd axis stops the coarsening; a coarsest level too large for the dense inverse is
+  // smoothed instead (see bottom_smooth)
+  if (op.Nc <= kDenseMaxN) {
+    op.Ainv = dalloc<double>(c, (size_t)op.Nc * op.Nc);
+    op.hA.resize((size_t)op.Nc * op.Nc);
+  }
 }
 
 // dense inverse of the SPD coarsest operator (Cholesky), built on the host from the
@@ -407,8 +418,28 @@ void ell_setup(jfnk_ctx* c, const double* X, double dt) {
     if (c->opts.ell_precision == JFNK_FP32)
       for (size_t l = 0; l < op.lv64.size(); ++l) launch_level_to_f32(op.lv64[l], op.lv32[l], G.nd, c->stream);
     check_launch();
-    coarse_setup(c, op);
+    if (op.Ainv) coarse_setup(c, op);
   }
+}
+
+// The bottom of a V-cycle on level L: x = A^-1 b by the dense inverse, or, when the level is
+// too large for it, the degree-2 Chebyshev smoothing from zero (into xs) followed by the same
+// smoothing from that iterate (a "prolongation" of a zero coarse vector, then the second
+// smoothing), which keeps the V-cycle symmetric positive definite.
+template <class T>
+void bottom_solve(jfnk_ctx* c, const Level& L, const double* Ainv, const T* b, T* xs, T* x, const CGArgs& g) {
+  const Grid& G = c->G;
+  hipStream_t s = c->stream;
+  if (Ainv) {
+    launch_dense_matvec<T>(L.N, Ainv, b, x, g, s);
+    return;
+  }
+  Level zc{};
+  zc.N = 1;  // strides 0: every cell's parent is the single zero entry
+  const T* zero = std::is_same<T, float>::value ? (const T*)c->zero32 : (const T*)c->zero64;
+  launch_mg_presmooth<T>(G, L, b, xs, g, false, s);
+  launch_mg_prolong_smooth1<T>(G, L, b, xs, zero, zc, (T*)L.t1, (T*)L.t2, g, s);
+  launch_mg_smooth2<T>(G, L, b, (const T*)L.t1, (const T*)L.t2, x, g, false, s);
 }
 
 // first level handled by the single-workgroup coarse kernel (nl - 1 when the coarsest
@@ -488,7 +519,7 @@ void vcycle_rest(jfnk_ctx* c, std::vector<Level>& lv, const double* Ainv, const 
     launch_mg_presmooth<T>(G, lv[l], B(l), Xl(l), g, false, s);
     launch_mg_restrict_resid<T>(G, lv[l], B(l), Xl(l), (T*)lv[l + 1].b, lv[l + 1], g, 0, s);
   }
-  launch_dense_matvec<T>(lv[nl - 1].N, Ainv, B(nl - 1), Xl(nl - 1), g, s);
+  bottom_solve<T>(c, lv[nl - 1], Ainv, B(nl - 1), Xl(nl - 1), Xl(nl - 1), g);
   for (int l = l0 - 1; l >= 0; --l) {
     launch_mg_prolong_smooth1<T>(G, lv[l], B(l), Xl(l), Xl(l + 1), lv[l + 1], (T*)lv[l].t1,
                                  (T*)lv[l].t2, g, s);
@@ -529,7 +560,7 @@ int pcg(jfnk_ctx* c, std::vector<Level>& lv, const double* Ainv, const T* b, T* 
     launch_vcycle_coarse<T>(G, &lv[0], nl, Ainv, b, z, g, kCoarseInit | kCoarseRZ, 0, s);
   } else {
     launch_cg_init<T>(N, b, g, s);
-    launch_dense_matvec<T>(N, Ainv, b, z, g, s);
+    bottom_solve<T>(c, lv[0], Ainv, b, x2, z, g);
     launch_cg_dot_rz<T>(N, b, z, g, s);
   }
   if (g.maxit == 0) return 0;
@@ -555,7 +586,7 @@ int pcg(jfnk_ctx* c, std::vector<Level>& lv, const double* Ainv, const T* b, T* 
         launch_vcycle_coarse<T>(G, &lv[0], nl, Ainv, rnew, z, g, kCoarseConv | kCoarseRZ, it, s);
       } else {
         launch_cg_decide(g, it, s);
-        launch_dense_matvec<T>(N, Ainv, rnew, z, g, s);
+        bottom_solve<T>(c, lv[0], Ainv, rnew, x2, z, g);
         launch_cg_dot_rz<T>(N, rnew, z, g, s);
       }
       rold = rnew;
@@ -575,7 +606,7 @@ int pcg(jfnk_ctx* c, std::vector<Level>& lv, const double* Ainv, const T* b, T* 
     } else if (fused) {
       launch_vcycle_coarse<T>(G, &lv[0], nl, Ainv, rold, z, g, kCoarseConv | kCoarseRZ, enq, s);
     } else {
-      launch_dense_matvec<T>(N, Ainv, rold, z, g, s);
+      bottom_solve<T>(c, lv[0], Ainv, rold, x2, z, g);
       launch_cg_dot_rz<T>(N, rold, z, g, s);
     }
     batch = 1;
@@ -1018,6 +1049,10 @@ void create(jfnk_ctx* c) {
   c->cgpart = dalloc<double>(c, (size_t)kPartCount * kRedBlocks);
   HIPX(hipHostMalloc((void**)&c->hctl, sizeof(CGCtl), hipHostMallocDefault));
   std::memset(c->hctl, 0, sizeof(CGCtl));
+  c->zero64 = dalloc<double>(c, 1);
+  c->zero32 = dalloc<float>(c, 1);
+  HIPX(hipMemsetAsync(c->zero64, 0, sizeof(double), c->stream));
+  HIPX(hipMemsetAsync(c->zero32, 0, sizeof(float), c->stream));
   build_hierarchy(c, c->ops[0], want32);
   build_hierarchy(c, c->ops[1], want32);
   c->vjps = dalloc<double>(c, vjp_scratch_doubles(G));

@@ -270,3 +270,70 @@ def test_taylor_green_hardest_row_exact_jv():
     assert abs(got[2] - ref[2]) <= 0.005 * ref[2]
     assert np.min((w["problem"]["gamma"] - 1.0) * X1[0] * X1[1]) > 0.0
     ctx.close()
+
+
+ODD = [((65, 65), ("periodic", "wall")), ((130, 130), ("periodic", "wall")),
+       ((17, 16, 17), ("periodic", "periodic", "wall"))]
+
+
+@pytest.mark.parametrize("shape,bc", ODD, ids=["x".join(map(str, s)) for s, _ in ODD])
+def test_precond_with_smoothed_bottom_level(shape, bc):
+    """Grids whose coarsest multigrid level is too large for the dense inverse (an odd axis
+    stops the coarsening: 65^2 and 17 x 16 x 17 have one level, 130^2 two): that level is
+    smoothed instead of solved, on both sides; the preconditioner (MG-CG to 1e-4) and its
+    transpose against the oracle's, 1e-9 of the largest entry per variable."""
+    J = _lib()
+    nd = len(shape)
+    pd, X = W.random_state(shape, bc, seed=41, g=tuple([0.0] * (nd - 1) + [-1.0]), chi_model="power",
+                           chi0=0.02, amp=0.2)
+    P = Problem.from_dict(pd)
+    dt = 0.05
+    r = W.random_vector(X, 42)
+    pbp = PBP(P, X, dt, "sound_thermal", solver_factory=PCGSolver.factory(1e-4))
+    assert pbp.solve_p.mg.coarse_chol is None
+    ctx = J.Context(pd, precond="sound_thermal")
+    ctx.set_state_n(T(X), dt)
+    ref, got = pbp.apply(r), H(ctx.precond_apply(T(X), T(r)))
+    refT, gotT = pbp.apply_T(r), H(ctx.precond_apply_transpose(T(X), T(r)))
+    for k in range(P.nvar):
+        assert np.max(np.abs(got[k] - ref[k])) <= 1e-9 * np.max(np.abs(ref[k])), k
+        assert np.max(np.abs(gotT[k] - refT[k])) <= 1e-9 * np.max(np.abs(refT[k])), k
+    ctx.close()
+
+
+def test_implicit_step_with_smoothed_bottom_level():
+    """A 65^2 polytrope (one multigrid level, smoothed): the step against the oracle's JFNK
+    step with the same options, and the same Newton and GMRES counts (CG within 0.5 %)."""
+    J = _lib()
+    w = W.polytrope((65, 65), 10.0, mach=1e-3, seed=5, chi_model="power", steps=1, cfl=100.0)
+    P = Problem.from_dict(w["problem"])
+    dt = cfl_dt(P, w["X0"], 100.0)
+    st_o = Stats()
+    Xo = jfnk_step(P, w["X0"], dt, Opts(precond="sound_thermal", jv_mode="fd"), st_o)
+    ctx = J.Context(w["problem"], precond="sound_thermal")
+    Xg = T(w["X0"])
+    st = ctx.implicit_step(Xg, dt)
+    _, R = scaling_LR(P, Xo)
+    err = float(np.max(np.abs((H(Xg) - Xo) / R)))
+    got = (st["newton_its"], st["gmres_its"], st["cg_its"])
+    ref = (st_o.newton_its, sum(st_o.gmres_its), sum(st_o.cg_its))
+    print(f"# 65^2 smoothed bottom: gpu {got} oracle {ref}; ||R^-1 (X - X_or)||_inf {err:.3e}", flush=True)
+    assert st["converged"] == 1 and err <= 1e-8, err
+    assert got[:2] == ref[:2]
+    assert abs(got[2] - ref[2]) <= 0.005 * ref[2]
+    ctx.close()
+
+
+def test_red_giant_grid_shape_steps():
+    """The grid shape of the paper's 3D red-giant run (72 x 65 x 65, Sect. 5.2) can be created
+    (odd axes: one multigrid level, smoothed) and a step of a polytrope on it converges."""
+    J = _lib()
+    w = W.polytrope((72, 65, 65), 20.0, mach=1e-4, seed=5, chi_model="power", steps=1, cfl=50.0)
+    ctx = J.Context(w["problem"], precond="sound_thermal")
+    Xg = T(w["X0"])
+    dt = ctx.cfl_dt(Xg, 50.0)
+    st = ctx.implicit_step(Xg, dt)
+    print(f"# 72x65x65: newton {st['newton_its']} gmres {st['gmres_its']} cg {st['cg_its']}", flush=True)
+    assert st["converged"] == 1
+    assert torch.isfinite(Xg).all() and float(Xg[0].min()) > 0.0
+    ctx.close()

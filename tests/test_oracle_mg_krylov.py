@@ -135,3 +135,29 @@ def test_single_vcycle_solve_is_a_symmetric_contraction():
     assert rho < 0.5, rho
     b = np.random.default_rng(6).uniform(-1, 1, P.field_shape)
     assert np.array_equal(pcg(op, b, maxit=0), Multigrid(op).vcycle(b.astype(np.float64)))
+
+
+@pytest.mark.parametrize("shape,bc", [((9, 7), ("periodic", "wall")), ((16, 8), ("periodic", "wall")),
+                                      ((5, 7, 6), ("wall", "periodic", "wall"))])
+def test_vcycle_with_smoothed_bottom_is_spd(shape, bc, monkeypatch):
+    """A coarsest level too large for the dense solve (here forced with a dense limit of 8
+    cells; odd axes stop the coarsening at once) is smoothed instead of solved: the V-cycle
+    stays a symmetric positive definite operator, and CG preconditioned by it still meets
+    its stopping rule."""
+    monkeypatch.setattr(Multigrid, "DENSE_MAX", 8)
+    P, X = _state(shape, bc)
+    op = pressure_operator(P, X, _stiff_dt(P, 30.0))
+    mg = Multigrid(op)
+    assert mg.coarse_chol is None
+    N = P.ncell
+    B = np.empty((N, N))
+    for k in range(N):
+        e = np.zeros(N)
+        e[k] = 1.0
+        B[:, k] = mg.vcycle(e.reshape(P.field_shape)).ravel()
+    assert np.max(np.abs(B - B.T)) <= 1e-12 * np.max(np.abs(B))
+    assert np.min(np.linalg.eigvalsh(0.5 * (B + B.T))) > 0
+    b = np.random.default_rng(3).uniform(-1, 1, P.field_shape)
+    its = []
+    x = pcg(op, b, eta=1e-8, maxit=400, stats=its)
+    assert np.linalg.norm(b.ravel() - op.to_sparse() @ x.ravel()) < 1e-8 * np.linalg.norm(b)
