@@ -179,3 +179,42 @@ def test_fullsize_gradient_through_steps_fd():
         fd = (vals[0] - vals[1]) / (2 * eps)
         assert abs(fd - an) <= 3e-4 * abs(an), (k, fd, an)
     ctx.close()
+
+
+@pytest.mark.parametrize("form", ["fd_fp64", "exact_fp32"])
+@pytest.mark.parametrize("name", ["convective_3d_256", "taylor_green_3d_128"])
+def test_fullsize_first_step_is_a_root_of_the_oracle_residual(name, form):
+    """The first implicit step of the 256^3 convective box (CFL 500) and of the 128^3
+    Taylor-Green box (CFL 1000) in both forms, as bench.py runs them: at 4096 sampled cells
+    (boundary cells included) the oracle's F at the GPU's X^1 (b from X^0) matches the
+    library's F there to 1e-12 of S_k (operator parity at the converged state) and is itself
+    below 1e-10 of S_k (X^1 is a root of the oracle's residual to the Newton tolerance; a wrong
+    step leaves O(1e-6) or more), S_k = max(|U_k|/dt + |b_k|) + max A_k over the sampled cells."""
+    J = _lib()
+    w = _workload(name)
+    pd, X0 = w["problem"], w["X0"]
+    P = Problem.from_dict(pd)
+    jv, ell = form.split("_")
+    print(f"# full-size first step {name} {form}", flush=True)
+    ctx = J.Context(pd, precond=w["precond"], jv_mode=jv, ell_precision=ell)
+    Xg = torch.tensor(X0, dtype=torch.float64, device=DEV)
+    dt = ctx.cfl_dt(Xg, w["cfl"])
+    st = ctx.implicit_step(Xg, dt)
+    assert st["converged"] == 1
+    Xn = torch.tensor(X0, dtype=torch.float64, device=DEV)
+    ctx.set_state_n(Xn, dt)
+    Fg = ctx.residual(Xg).cpu().numpy()
+    X1 = Xg.cpu().numpy()
+    ctx.close()
+    cells = _sample(P, 4096, 91)
+    b = _rhs_b_cells(P, X0, dt, cells)
+    U1 = conserved_U(P, X1, cells)
+    R1, A1 = residual_R(P, X1, cells, with_abs=True)
+    Fo = U1 / dt - R1 - b
+    S = np.max(np.abs(U1) / dt + np.abs(b), axis=1) + np.max(A1, axis=1)
+    par = float(np.max(np.max(np.abs(_at(Fg, P, cells) - Fo), axis=1) / S))
+    root = float(np.max(np.max(np.abs(Fo), axis=1) / S))
+    print(f"#   newton {st['newton_its']} gmres {st['gmres_its']}: F parity {par:.2e}, oracle F at X^1 {root:.2e}",
+          flush=True)
+    assert par <= 1e-12, par
+    assert root <= 1e-10, root
