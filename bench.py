@@ -241,6 +241,14 @@ def main():
     if args.compare:
         ctx_ai = J.Context(pd, precond=precond, jv_mode="exact", ell_precision="fp32")
         Xa, stats_a, sec_a, first_ai = timed_form(ctx_ai, "exact J.v + FP32 elliptic")
+        print(f"# exact J.v + FP32 elliptic: probe pass ({pk} step(s))", file=sys.stderr, flush=True)
+        Nat.probe_enable(True)
+        ctx_ai.set_opts(phase_timing=1)
+        _, stats_ap, _ = run_steps(ctx_ai, pk)
+        torch.cuda.synchronize()
+        probes_a = Nat.probe_results()
+        Nat.probe_enable(False)
+        dom_a, (dms_a, dn_a, db_a) = max(probes_a.items(), key=lambda kv: kv[1][0])
         compare = {
             "form": "exact J.v + FP32 elliptic (MG-CG) solves",
             "value": args.steps / sec_a, "unit": "implicit steps/s",
@@ -250,6 +258,12 @@ def main():
             "max_rel_diff_vs_plain_per_var": rel_diff_per_var(Xa.cpu().numpy(), Xk.cpu().numpy()),
             "first_step_max_rel_diff_vs_plain_per_var": rel_diff_per_var(first_ai[0].cpu().numpy(),
                                                                          first_plain[0].cpu().numpy()),
+            "dominant_kernel": {"kernel": dom_a, "launches": dn_a, "avg_us": 1e3 * dms_a / dn_a,
+                                "achieved_GBps": db_a / (dms_a * 1e-3) / 1e9,
+                                "frac_of_hbm_peak": db_a / (dms_a * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                "share_of_kernel_time": dms_a / sum(v[0] for v in probes_a.values())},
+            "probe_ms": {k: round(v[0], 3) for k, v in sorted(probes_a.items(), key=lambda kv: -kv[1][0])},
+            "phase_ms_per_step": {k: sum(s[k] for s in stats_ap) / pk for k in ("t_resid", "t_jv", "t_prec", "t_orth")},
         }
         ctx_ai.close()
         del Xa
