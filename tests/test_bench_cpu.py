@@ -41,3 +41,19 @@ def test_traffic_summary_needs_the_same_source(tmp_path, monkeypatch):
     assert bench.measured_traffic("other", "mg_down") is None    # no summary
     write("0" * 64)                                               # source changed since
     assert bench.measured_traffic("wl", "mg_down") is None
+
+
+def test_extrapolated_cpu_baseline_on_a_small_sample():
+    """The extrapolated oracle baseline of the 3D boxes runs on the CPU, labels itself, scales
+    by the cell count and combines the per-call costs with the given iteration counts."""
+    class A:
+        workload = "convective_box_3d"
+    w = W.convective_box_3d(n=32)
+    stats = [dict(newton_its=6, gmres_its=120, cg_its=900, converged=1)] * 2
+    r = bench.cpu_baseline_extrapolated(w, stats, A(), sample_n=16)
+    assert r["kind"] == "oracle" and r["extrapolated"] and r["cores"] == 1
+    assert "scaled x8" in r["sample"] and "Newton 6.00, GMRES 120.0, CG 900.0" in r["sample"]
+    c = r["components_s_at_sample"]
+    step = 8 * (6 * (c["residual_and_scalings"] + c["pc_setup"])
+                + 120 * (c["fd_jv"] + c["pc_apply_at_gpu_cg_count"] + c["arnoldi_per_iteration"]))
+    assert abs(r["seconds_per_step"] - step) <= 1e-9 * step and abs(r["value"] * step - 1.0) < 1e-12
