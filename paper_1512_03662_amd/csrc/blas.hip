@@ -1,7 +1,7 @@
 // Vector kernels of the Krylov solvers: deterministic reductions (64-lane wavefront
 // shuffles, then LDS across the 4 waves of a block, then per-block partials summed in block
-// order by a one-block finalize kernel), the fused classical Gram-Schmidt passes of the Arnoldi
-// step (Sect. 4.1: GMRES), linear combinations and the scaled norms of eq. nr_terminate.
+// order by a one-block finalize kernel), the fused Gram-Schmidt passes of the Arnoldi step
+// (Sect. 4.1: GMRES), linear combinations and the scaled norms of eq. nr_terminate.
 //
 // Every reduction visits elements in a fixed order for a given grid, so results are
 // bitwise reproducible run to run.
@@ -121,65 +121,77 @@ void launch_dot(size_t n, const T* a, const T* b, double* out, const RedWS& w, h
 template void launch_dot<double>(size_t, const double*, const double*, double*, const RedWS&, hipStream_t);
 template void launch_dot<float>(size_t, const float*, const float*, double*, const RedWS&, hipStream_t);
 
-// ---- Gram-Schmidt passes -----------------------------------------------------------------
+// ---- Gram-Schmidt with delayed reorthogonalisation (two passes per Arnoldi step) ----------
+// Slots 0..K-2 of V hold the finished orthonormal basis, slot j = K-1 the newest vector q~
+// after one orthogonalisation (normalised by that pass's norm), w the new product.
+// Pass 1: a_i = V_i . q~ and b_i = V_i . w for i <= j (2K sums).
 template <int K>
-__global__ void __launch_bounds__(kBlock) k_multidot(size_t n, const double* V, size_t ld, const double* w,
-                                                     double* out, RedWS ws) {
-  double acc[K];
+__global__ void __launch_bounds__(kBlock) k_dcgs2_dots(size_t n, const double* V, size_t ld, const double* w,
+                                                       RedWS ws) {
+  double acc[2 * K];
 #pragma unroll
-  for (int k = 0; k < K; ++k) acc[k] = 0.0;
+  for (int k = 0; k < 2 * K; ++k) acc[k] = 0.0;
   for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
-    double wi = w[i];
+    const double qi = V[(K - 1) * ld + i];
+    const double wi = w[i];
 #pragma unroll
-    for (int k = 0; k < K; ++k) acc[k] += V[k * ld + i] * wi;
-  }
-  block_finish<OpSum, K>(acc, out, ws);
-}
-
-template <int K>
-__global__ void __launch_bounds__(kBlock) k_cgs2_update_dot(size_t n, const double* V, size_t ld,
-                                                            const double* h, double* w, double* out,
-                                                            RedWS ws) {
-  double acc[K + 1];
-  double hk[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    acc[k] = 0.0;
-    hk[k] = h[k];
-  }
-  acc[K] = 0.0;
-  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
-    double v[K];
-    double wi = w[i];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      v[k] = V[k * ld + i];
-      wi -= hk[k] * v[k];
+    for (int k = 0; k < K - 1; ++k) {
+      const double v = V[k * ld + i];
+      acc[k] += v * qi;
+      acc[K + k] += v * wi;
     }
-    w[i] = wi;
-#pragma unroll
-    for (int k = 0; k < K; ++k) acc[k] += v[k] * wi;
-    acc[K] += wi * wi;
+    acc[K - 1] += qi * qi;
+    acc[2 * K - 1] += qi * wi;
   }
-  block_finish<OpSum, K + 1>(acc, out, ws);
+  block_finish<OpSum, 2 * K>(acc, nullptr, ws);
 }
 
+// Coefficients of pass 2 from the sums of pass 1 (j = K - 1; j = 0: q~ is final already):
+// s_i = a_i, nu = sqrt(a_j - sum s_i^2), h_i = b_i (i < j), h_j = (b_j - sum s_i b_i) / nu.
+// The host forms the same numbers for the Hessenberg matrix.
 template <int K>
-__global__ void __launch_bounds__(kBlock) k_cgs2_update_norm(size_t n, const double* V, size_t ld,
-                                                             const double* h, const double* w,
-                                                             double* dst, double* out, RedWS ws) {
-  double hk[K];
+__device__ __forceinline__ void dcgs2_coef(const double* sums, double* sc, double& inv_nu, double* h) {
+  constexpr int j = K - 1;
+  double ss = 0.0, sb = 0.0;
 #pragma unroll
-  for (int k = 0; k < K; ++k) hk[k] = h[k];
+  for (int k = 0; k < j; ++k) {
+    sc[k] = sums[k];
+    h[k] = sums[K + k];
+    ss += sc[k] * sc[k];
+    sb += sc[k] * h[k];
+  }
+  const double nu = (j == 0) ? 1.0 : sqrt(sums[j] - ss);
+  inv_nu = 1.0 / nu;
+  h[j] = (sums[K + j] - sb) * inv_nu;
+}
+
+// Pass 2: q = (q~ - sum_{i<j} s_i V_i) / nu replaces slot j (j >= 1), dst = w - sum_{i<j} h_i V_i
+// - h_j q, and the partial sums of ||dst||^2.
+template <int K>
+__global__ void __launch_bounds__(kBlock) k_dcgs2_update(size_t n, double* V, size_t ld, const double* sums,
+                                                         const double* w, double* dst, RedWS ws) {
+  constexpr int j = K - 1;
+  double sc[K], h[K], inv_nu;
+  dcgs2_coef<K>(sums, sc, inv_nu, h);
   double acc[1] = {0.0};
   for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+    double q = V[j * ld + i];
     double wi = w[i];
 #pragma unroll
-    for (int k = 0; k < K; ++k) wi -= hk[k] * V[k * ld + i];
+    for (int k = 0; k < j; ++k) {
+      const double v = V[k * ld + i];
+      q -= sc[k] * v;
+      wi -= h[k] * v;
+    }
+    if (j > 0) {
+      q *= inv_nu;
+      V[j * ld + i] = q;
+    }
+    wi -= h[j] * q;
     dst[i] = wi;
     acc[0] += wi * wi;
   }
-  block_finish<OpSum, 1>(acc, out, ws);
+  block_finish<OpSum, 1>(acc, nullptr, ws);
 }
 
 template <int K>
@@ -200,36 +212,6 @@ using MdFn = void (*)(size_t, const double*, size_t, const double*, const double
                       const RedWS&, hipStream_t);
 
 template <int K>
-static void md_launch(size_t n, const double* V, size_t ld, const double* h, const double* w,
-                      double* w_mut, double* out, const RedWS& ws, hipStream_t s) {
-  (void)h;
-  (void)w_mut;
-  {
-    launch_k(KF_MULTIDOT, 8.0 * n * (K + 1), k_multidot<K>, dim3(red_blocks(n)), dim3(kBlock), 0, s,
-             n, V, ld, w, out, ws);
-  }
-  finalize<OpSum>(ws, red_blocks(n), K, out, s);
-}
-template <int K>
-static void ud_launch(size_t n, const double* V, size_t ld, const double* h, const double* w,
-                      double* w_mut, double* out, const RedWS& ws, hipStream_t s) {
-  (void)w;
-  {
-    launch_k(KF_CGS2_UD, 8.0 * n * (K + 2), k_cgs2_update_dot<K>, dim3(red_blocks(n)), dim3(kBlock),
-             0, s, n, V, ld, h, w_mut, out, ws);
-  }
-  finalize<OpSum>(ws, red_blocks(n), K + 1, out, s);
-}
-template <int K>
-static void un_launch(size_t n, const double* V, size_t ld, const double* h, const double* w,
-                      double* dst, double* out, const RedWS& ws, hipStream_t s) {
-  {
-    launch_k(KF_CGS2_UN, 8.0 * n * (K + 2), k_cgs2_update_norm<K>, dim3(red_blocks(n)), dim3(kBlock),
-             0, s, n, V, ld, h, w, dst, out, ws);
-  }
-  finalize<OpSum>(ws, red_blocks(n), 1, out, s);
-}
-template <int K>
 static void lc_launch(size_t n, const double* Z, size_t ld, const double* y, const double* w,
                       double* dst, double* out, const RedWS& ws, hipStream_t s) {
   (void)w;
@@ -241,35 +223,55 @@ static void lc_launch(size_t n, const double* Z, size_t ld, const double* y, con
            ld, y, dst);
 }
 
+// the sums are finalised by 2K blocks, one per sum (each in block order, as finalize)
+__global__ void __launch_bounds__(kBlock) k_finalize_each(const double* part, int nb, int K, double* out) {
+  __shared__ double sm[kBlock / 64];
+  const double v = finalize_one<OpSum>(part, nb, K, blockIdx.x, sm);
+  if (threadIdx.x == 0) out[blockIdx.x] = v;
+}
+
+template <int K>
+static void d1_launch(size_t n, const double* V, size_t ld, const double* h, const double* w, double* w_mut,
+                      double* out, const RedWS& ws, hipStream_t s) {
+  (void)h;
+  (void)w_mut;
+  launch_k(KF_GS_DOTS, 8.0 * n * (K + 1), k_dcgs2_dots<K>, dim3(red_blocks(n)), dim3(kBlock), 0, s, n, V, ld,
+           w, ws);
+  k_finalize_each<<<2 * K, kBlock, 0, s>>>(ws.part, red_blocks(n), 2 * K, out);
+}
+template <int K>
+static void d2_launch(size_t n, const double* V, size_t ld, const double* sums, const double* w, double* dst,
+                      double* out, const RedWS& ws, hipStream_t s) {
+  // reads slots 0..j and w; writes slot j (j >= 1) and dst
+  const double by = 8.0 * n * (K + 1 + (K > 1 ? 2 : 1));
+  launch_k(KF_GS_UPDATE, by, k_dcgs2_update<K>, dim3(red_blocks(n)), dim3(kBlock), 0, s, n,
+           const_cast<double*>(V), ld, sums, w, dst, ws);
+  finalize<OpSum>(ws, red_blocks(n), 1, out, s);
+}
+
 constexpr int kMaxBasis = kMaxK - 1;  // K ranges over 1..kMaxBasis
 
 template <template <int> class F, size_t... I>
 constexpr std::array<MdFn, sizeof...(I)> make_table(std::index_sequence<I...>) {
   return {{&F<(int)I + 1>::run...}};
 }
-template <int K> struct MdT { static void run(size_t n, const double* V, size_t ld, const double* h, const double* w, double* m, double* o, const RedWS& ws, hipStream_t s) { md_launch<K>(n, V, ld, h, w, m, o, ws, s); } };
-template <int K> struct UdT { static void run(size_t n, const double* V, size_t ld, const double* h, const double* w, double* m, double* o, const RedWS& ws, hipStream_t s) { ud_launch<K>(n, V, ld, h, w, m, o, ws, s); } };
-template <int K> struct UnT { static void run(size_t n, const double* V, size_t ld, const double* h, const double* w, double* m, double* o, const RedWS& ws, hipStream_t s) { un_launch<K>(n, V, ld, h, w, m, o, ws, s); } };
 template <int K> struct LcT { static void run(size_t n, const double* V, size_t ld, const double* h, const double* w, double* m, double* o, const RedWS& ws, hipStream_t s) { lc_launch<K>(n, V, ld, h, w, m, o, ws, s); } };
 
-static const auto kMd = make_table<MdT>(std::make_index_sequence<kMaxBasis>{});
-static const auto kUd = make_table<UdT>(std::make_index_sequence<kMaxBasis - 1>{});
-static const auto kUn = make_table<UnT>(std::make_index_sequence<kMaxBasis>{});
 static const auto kLc = make_table<LcT>(std::make_index_sequence<kMaxBasis>{});
+template <int K> struct D1T { static void run(size_t n, const double* V, size_t ld, const double* h, const double* w, double* m, double* o, const RedWS& ws, hipStream_t s) { d1_launch<K>(n, V, ld, h, w, m, o, ws, s); } };
+template <int K> struct D2T { static void run(size_t n, const double* V, size_t ld, const double* h, const double* w, double* m, double* o, const RedWS& ws, hipStream_t s) { d2_launch<K>(n, V, ld, h, w, m, o, ws, s); } };
+static const auto kD1 = make_table<D1T>(std::make_index_sequence<kMaxBasis - 1>{});
+static const auto kD2 = make_table<D2T>(std::make_index_sequence<kMaxBasis - 1>{});
 
-void launch_multidot(size_t n, const double* V, size_t ld, int K, const double* w, double* out,
-                     const RedWS& ws, hipStream_t s) {
-  kMd[K - 1](n, V, ld, nullptr, w, nullptr, out, ws, s);
+void launch_dcgs2_dots(size_t n, const double* V, size_t ld, int K, const double* w, double* sums,
+                       const RedWS& ws, hipStream_t s) {
+  kD1[K - 1](n, V, ld, nullptr, w, nullptr, sums, ws, s);
 }
-void launch_cgs2_update_dot(size_t n, const double* V, size_t ld, int K, const double* h, double* w,
-                            double* out, const RedWS& ws, hipStream_t s) {
-  kUd[K - 1](n, V, ld, h, nullptr, w, out, ws, s);
+void launch_dcgs2_update(size_t n, double* V, size_t ld, int K, const double* sums, const double* w, double* dst,
+                         double* nrm2, const RedWS& ws, hipStream_t s) {
+  kD2[K - 1](n, V, ld, sums, w, dst, nrm2, ws, s);
 }
-void launch_cgs2_update_norm(size_t n, const double* V, size_t ld, int K, const double* h,
-                             const double* w, double* dst, double* out, const RedWS& ws,
-                             hipStream_t s) {
-  kUn[K - 1](n, V, ld, h, w, dst, out, ws, s);
-}
+
 void launch_lincomb(size_t n, const double* Z, size_t ld, int K, const double* y, double* dst,
                     hipStream_t s) {
   kLc[K - 1](n, Z, ld, y, nullptr, dst, nullptr, RedWS{}, s);

@@ -33,7 +33,7 @@ constexpr int kRedBlocks = 1024;   // maximum blocks of a reduction grid
 constexpr int kMaxK = 72;          // maximum simultaneous sums (Krylov basis size + 1)
 
 struct RedWS {
-  double* part = nullptr;          // kRedBlocks * kMaxK partials
+  double* part = nullptr;          // kRedBlocks * 2 kMaxK partials
   unsigned int* count = nullptr;   // unused (kept zero)
 };
 
@@ -42,16 +42,15 @@ void launch_finalize_sum(const RedWS& ws, int nb, int K, double* out, hipStream_
 
 template <class T>
 void launch_dot(size_t n, const T* a, const T* b, double* out, const RedWS& w, hipStream_t s);
-// out[k] = sum_i V[k*ld + i] w[i], k < K
-void launch_multidot(size_t n, const double* V, size_t ld, int K, const double* w, double* out,
-                     const RedWS& ws, hipStream_t s);
-// w -= sum_k h[k] V_k; out[k] = V_k . w (k < K); out[K] = ||w||^2
-void launch_cgs2_update_dot(size_t n, const double* V, size_t ld, int K, const double* h, double* w,
-                            double* out, const RedWS& ws, hipStream_t s);
-// dst = w - sum_k h[k] V_k; out[0] = ||dst||^2
-void launch_cgs2_update_norm(size_t n, const double* V, size_t ld, int K, const double* h,
-                             const double* w, double* dst, double* out, const RedWS& ws,
-                             hipStream_t s);
+// Arnoldi orthogonalisation with delayed reorthogonalisation (slots 0..K-2 of V final, slot
+// K-1 the newest vector after one pass, w the new product):
+// sums[k] = V_k . V_{K-1}, sums[K + k] = V_k . w for k < K
+void launch_dcgs2_dots(size_t n, const double* V, size_t ld, int K, const double* w, double* sums,
+                       const RedWS& ws, hipStream_t s);
+// slot K-1 reorthogonalised and renormalised (K >= 2), dst = w orthogonalised against slots
+// 0..K-1, *nrm2 = ||dst||^2 (coefficients formed on the device from sums)
+void launch_dcgs2_update(size_t n, double* V, size_t ld, int K, const double* sums, const double* w, double* dst,
+                         double* nrm2, const RedWS& ws, hipStream_t s);
 // dst = src / sqrt(*nrm2)
 void launch_scale_by_inv_sqrt(size_t n, const double* src, const double* nrm2, double* dst,
                               hipStream_t s);

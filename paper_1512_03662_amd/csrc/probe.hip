@@ -48,7 +48,7 @@ void drain(Fam& f) {
 
 const char* const kFamNames[KF_COUNT] = {
     "residual_value", "residual_fd_jv", "residual_exact_jv", "vjp_stage_a", "vjp_stage_b",
-    "vjp_fold", "cgs2_multidot", "cgs2_update_dot", "cgs2_update_norm", "lincomb",
+    "vjp_fold", "gs_dots", "gs_update", "lincomb",
     "mg_presmooth", "mg_prolong_smooth1", "mg_smooth2", "mg_coarse", "cg_apply_dot",
     "cg_update", "cg_pupdate", "dot", "pbp_in", "pbp_out", "scaled_norm", "mg_restrict_resid",
     "mg_down", "mg_up", "fd_shift"};

@@ -13,9 +13,8 @@ enum KFam {
   KF_VJP_A,
   KF_VJP_B,
   KF_VJP_FOLD,
-  KF_MULTIDOT,
-  KF_CGS2_UD,
-  KF_CGS2_UN,
+  KF_GS_DOTS,
+  KF_GS_UPDATE,
   KF_LINCOMB,
   KF_MG_PRE,
   KF_MG_PROLONG,

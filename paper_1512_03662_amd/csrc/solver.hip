@@ -714,6 +714,18 @@ void apply_J(jfnk_ctx* c, const double* X, const double* z, double* out) {
   }
 }
 
+// plane rotation (c, s) that zeroes b in (a, b)
+void givens(double a, double b, double* c, double* s) {
+  if (b == 0.0) {
+    *c = 1.0;
+    *s = 0.0;
+  } else {
+    const double r = std::hypot(a, b);
+    *c = a / r;
+    *s = b / r;
+  }
+}
+
 struct GmresOut {
   int iters = 0;
   bool converged = false;
@@ -764,6 +776,14 @@ GmresOut fgmres(jfnk_ctx* c, const double* X, double beta0, double sign) {
     g[0] = beta;
     int k = 0;
     double res = beta;
+    // Arnoldi with delayed reorthogonalisation: step j orthogonalises w = A z_j once against
+    // V_0..V_j and, in the same two passes, reorthogonalises V_j (orthogonalised once in
+    // step j - 1) against V_0..V_{j-1}.  Column j - 1 of H is then corrected for the change of
+    // V_j and its Givens rotation recomputed; the residual estimate of step j uses the
+    // once-orthogonalised norm of w (the correction is of the order of rounding).
+    double hprev = 0.0;                // norm of w of step j - 1 (V_j = w / hprev)
+    std::vector<double> hcol(m + 1);   // unrotated column j - 1
+    double gsave = 0.0;                // g[j - 1] before the provisional rotation j - 1
     for (int j = 0; j < m; ++j) {
       double* Vj = c->V + (size_t)j * n;
       double* Zj = c->Z + (size_t)j * n;
@@ -777,16 +797,45 @@ GmresOut fgmres(jfnk_ctx* c, const double* X, double beta0, double sign) {
       phase_end(c, PH_JV);
       const int K = j + 1;
       phase_begin(c);
-      launch_multidot(n, c->V, n, K, w, c->scal + S_H1, c->red, s);
-      launch_cgs2_update_dot(n, c->V, n, K, c->scal + S_H1, w, c->scal + S_H2, c->red, s);
-      launch_cgs2_update_norm(n, c->V, n, K, c->scal + S_H2, w, w, c->scal + S_NRM3, c->red, s);
+      launch_dcgs2_dots(n, c->V, n, K, w, c->scal + S_H1, c->red, s);
+      launch_dcgs2_update(n, c->V, n, K, c->scal + S_H1, w, w, c->scal + S_NRM3, c->red, s);
       phase_end(c, PH_ORTH);
       pull(c, S_H1, S_NRM3 + 1 - S_H1);
+      const double* sums = c->hscal + S_H1;
       double hn2 = c->hscal[S_NRM3];
       if (!std::isfinite(hn2)) throw FiniteErr("non-finite Arnoldi vector");
+      // the coefficients of the device's second pass
+      double ss = 0.0, sb = 0.0;
+      for (int i = 0; i < j; ++i) {
+        ss += sums[i] * sums[i];
+        sb += sums[i] * sums[K + i];
+      }
+      const double nu = (j == 0) ? 1.0 : std::sqrt(sums[j] - ss);
+      if (!(nu > 0.0) || !std::isfinite(nu)) throw FiniteErr("loss of orthogonality in the Arnoldi basis");
+      const double inv_nu = 1.0 / nu;
+      if (j > 0) {
+        // V_j = hprev^-1 w_prev was replaced by (V_j - sum s_i V_i) / nu: column j - 1 gains
+        // hprev s_i in rows i < j and hprev nu in row j; redo its rotation
+        for (int i = 0; i < j; ++i) hcol[i] += hprev * sums[i];
+        hcol[j] = hprev * nu;
+        for (int i = 0; i <= j; ++i) Hx(i, j - 1) = hcol[i];
+        for (int i = 0; i < j - 1; ++i) {
+          double t = cs[i] * Hx(i, j - 1) + sn[i] * Hx(i + 1, j - 1);
+          Hx(i + 1, j - 1) = -sn[i] * Hx(i, j - 1) + cs[i] * Hx(i + 1, j - 1);
+          Hx(i, j - 1) = t;
+        }
+        givens(Hx(j - 1, j - 1), Hx(j, j - 1), &cs[j - 1], &sn[j - 1]);
+        Hx(j - 1, j - 1) = cs[j - 1] * Hx(j - 1, j - 1) + sn[j - 1] * Hx(j, j - 1);
+        Hx(j, j - 1) = 0.0;
+        g[j] = -sn[j - 1] * gsave;
+        g[j - 1] = cs[j - 1] * gsave;
+      }
       double hn = std::sqrt(hn2);
-      for (int i = 0; i < K; ++i) Hx(i, j) = c->hscal[S_H1 + i] + c->hscal[S_H2 + i];
-      Hx(j + 1, j) = hn;
+      for (int i = 0; i < j; ++i) hcol[i] = sums[K + i];
+      hcol[j] = (sums[K + j] - sb) * inv_nu;
+      hcol[j + 1] = hn;
+      for (int i = 0; i <= j + 1; ++i) Hx(i, j) = hcol[i];
+      hprev = hn;
       if (hn > 0.0) {
         phase_begin(c);
         launch_scale_by_inv_sqrt(n, w, c->scal + S_NRM3, w, s);
@@ -797,16 +846,9 @@ GmresOut fgmres(jfnk_ctx* c, const double* X, double beta0, double sign) {
         Hx(i + 1, j) = -sn[i] * Hx(i, j) + cs[i] * Hx(i + 1, j);
         Hx(i, j) = t;
       }
-      double a = Hx(j, j), b = Hx(j + 1, j);
-      if (b == 0.0) {
-        cs[j] = 1.0;
-        sn[j] = 0.0;
-      } else {
-        double r = std::hypot(a, b);
-        cs[j] = a / r;
-        sn[j] = b / r;
-      }
-      Hx(j, j) = cs[j] * a + sn[j] * b;
+      gsave = g[j];
+      givens(Hx(j, j), Hx(j + 1, j), &cs[j], &sn[j]);
+      Hx(j, j) = cs[j] * Hx(j, j) + sn[j] * Hx(j + 1, j);
       Hx(j + 1, j) = 0.0;
       g[j + 1] = -sn[j] * g[j];
       g[j] = cs[j] * g[j];
@@ -1032,7 +1074,7 @@ void create(jfnk_ctx* c) {
   c->scal = dalloc<double>(c, S_COUNT);
   HIPX(hipHostMalloc((void**)&c->hscal, S_COUNT * sizeof(double), hipHostMallocDefault));
   std::memset(c->hscal, 0, S_COUNT * sizeof(double));
-  c->red.part = dalloc<double>(c, (size_t)kRedBlocks * kMaxK);
+  c->red.part = dalloc<double>(c, (size_t)kRedBlocks * 2 * kMaxK);
   c->red.count = dalloc<unsigned int>(c, 1);
   HIPX(hipMemsetAsync(c->red.count, 0, sizeof(unsigned int), c->stream));
   HIPX(hipMemsetAsync(c->scal, 0, S_COUNT * sizeof(double), c->stream));
