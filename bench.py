@@ -3,7 +3,7 @@
     python bench.py [--steps K] [--warmup W] [--workload convective_box_3d] [--gpus 1]
 
 A step is one implicit time step X^n -> X^{n+1} (CFL time step from X^n, Newton to
-||R^-1 dX||_inf < 1e-8, FGMRES(30) with CGS2, physics-based preconditioner with multigrid
+||R^-1 dX||_inf < 1e-8, FGMRES(30) with delayed CGS2, physics-based preconditioner with multigrid
 CG).  Default workload: the 3D convective box, 256^3 cells (x, y periodic, walls in z,
 polytrope n = 1.5 with density contrast 20, conductivity ~ T^3, Mach 1e-4 velocity noise),
 CFL_hydro = 500, sound + thermal preconditioner.  `value` is the plain method: FP64
@@ -301,7 +301,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w["name"], "grid": list(pd["shape"]), "cfl_hydro": cfl,
                    "jv": jv, "precond": precond, "elliptic": args.ell, "newton_tol": 1e-8,
-                   "gmres": "FGMRES(30)+CGS2, eta 1e-4", "cg_eta": 1e-4},
+                   "gmres": "FGMRES(30), delayed CGS2, eta 1e-4", "cg_eta": 1e-4},
         "solver": solver_totals(stats),
         "roofline": roofline,
         "kernels": kernels,
