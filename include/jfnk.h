@@ -78,7 +78,7 @@ typedef struct {
   double newton_tol;     /* ||R^-1 dX||_inf stopping threshold (eq. nr_terminate)       */
   int32_t newton_max;    /* maximum Newton iterations                                   */
   int32_t newton_min;    /* minimum Newton iterations (the paper enforces 2)            */
-  int32_t gmres_m;       /* restart length (<= 64)                                       */
+  int32_t gmres_m;       /* restart length (<= 70)                                       */
   int32_t gmres_maxit;   /* maximum GMRES iterations per Newton iteration               */
   double gmres_eta;      /* forcing term eta (eq. forcing_term)                         */
   int32_t jv_mode;       /* JFNK_JV_FD (eqs. jacobian_free, pert_old) | JFNK_JV_EXACT  */
@@ -97,6 +97,15 @@ typedef struct {
                           * gravity or conduction)                                        */
   int32_t phase_timing;  /* 1: time the phases of a step with HIP events on the context's  *
                           * stream (jfnk_step_stats t_*); 0: no events (t_* = 0)          */
+  int32_t mg_levels;     /* multigrid levels of the elliptic solves (Sect. 3.5 leaves the  *
+                          * multi-level method's depth open): 0 = coarsen by 2 while every *
+                          * used axis is even and longer than 4 cells; L >= 1 = at most L  *
+                          * levels.  Fixed when the context is created (jfnk_set_opts      *
+                          * rejects a change).  A coarsest level of more than 4096 cells   *
+                          * is smoothed instead of solved exactly                          */
+  int32_t mg_smooth;     /* degree of the Chebyshev-Jacobi smoother: 2 (0 selects it); the  *
+                          * kernels implement degree 2 only, other values are rejected     *
+                          * with JFNK_E_INVALID                                            */
 } jfnk_opts;
 
 typedef struct {

@@ -8,7 +8,9 @@ eigenvalue estimates by a norm bound so that restarts reproduce (Sect. 3.5).  Be
 operators here are SPD (see ``pbp``), CG is used with one symmetric V-cycle as
 preconditioner:
 
-* cell-centred coarsening by 2 per axis while every axis is even and longer than 4 cells;
+* cell-centred coarsening by 2 per axis while every axis is even and longer than 4 cells,
+  and, when ``max_levels`` > 0, while there are fewer than ``max_levels`` levels (the paper
+  leaves the multi-level method's depth open);
 * coarse diagonal = mean of the 2^d children; coarse face weight = mean of the covered fine
   face weights / 4 (the same operator rediscretised at twice the spacing);
 * restriction = mean of the children; prolongation = piecewise-constant injection;
@@ -96,12 +98,12 @@ class Multigrid:
     LMIN = 0.5
     DENSE_MAX = 4096
 
-    def __init__(self, op: EllOp, dtype=np.float64):
+    def __init__(self, op: EllOp, dtype=np.float64, max_levels=0):
         self.dtype = dtype
         prob = op.prob
         cast = lambda a: np.asarray(a, dtype=dtype)
         self.levels = [Level(prob, EllOp(prob, cast(op.diag), [cast(w) for w in op.w]))]
-        while True:
+        while max_levels == 0 or len(self.levels) < max_levels:
             cur = self.levels[-1]
             cs = coarsen_shape(cur.prob.shape)
             if cs is None:
@@ -198,15 +200,15 @@ def pcg(op: EllOp, b, eta=1e-4, maxit=50, dtype=np.float64, mg=None, stats=None)
 class PCGSolver:
     """Callable b -> A^-1 b by MG-preconditioned CG (for ``pbp.PBP(solver_factory=...)``)."""
 
-    def __init__(self, op, eta=1e-4, maxit=50, dtype=np.float64):
+    def __init__(self, op, eta=1e-4, maxit=50, dtype=np.float64, max_levels=0):
         self.op = op
         self.eta, self.maxit, self.dtype = eta, maxit, dtype
-        self.mg = Multigrid(op, dtype)
+        self.mg = Multigrid(op, dtype, max_levels)
         self.iters = []
 
     def __call__(self, b):
         return pcg(self.op, b, self.eta, self.maxit, self.dtype, self.mg, self.iters)
 
     @staticmethod
-    def factory(eta=1e-4, maxit=50, dtype=np.float64):
-        return lambda op: PCGSolver(op, eta, maxit, dtype)
+    def factory(eta=1e-4, maxit=50, dtype=np.float64, max_levels=0):
+        return lambda op: PCGSolver(op, eta, maxit, dtype, max_levels)

@@ -53,6 +53,7 @@ class Opts:
     ell_dtype: object = np.float64
     cg_eta: float = 1e-4
     cg_maxit: int = 50
+    mg_levels: int = 0           # 0: coarsen as far as the grid allows; L: at most L levels
 
 
 @dataclass
@@ -118,7 +119,7 @@ def jfnk_step(prob: Problem, Xn, dt, opts: Opts = None, stats: Stats = None):
                 fac_list = []
 
                 def fac(op):
-                    s = PCGSolver(op, opts.cg_eta, opts.cg_maxit, opts.ell_dtype)
+                    s = PCGSolver(op, opts.cg_eta, opts.cg_maxit, opts.ell_dtype, opts.mg_levels)
                     fac_list.append(s)
                     return s
                 pbp = PBP(prob, X, dt, opts.precond, solver_factory=fac, schur=opts.pc_schur)

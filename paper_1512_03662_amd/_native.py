@@ -64,6 +64,8 @@ class Opts(C.Structure):
         ("cg_maxit", C.c_int32),
         ("pc_schur", C.c_int32),
         ("phase_timing", C.c_int32),
+        ("mg_levels", C.c_int32),
+        ("mg_smooth", C.c_int32),
     ]
 
 

@@ -268,6 +268,8 @@ void validate(const jfnk_problem* p, const jfnk_opts* o) {
   if (o->cg_maxit < 0) throw InvErr("cg_maxit must be >= 0");
   if (o->pc_schur != 0 && o->pc_schur != 1) throw InvErr("pc_schur must be 0 or 1");
   if (o->phase_timing != 0 && o->phase_timing != 1) throw InvErr("phase_timing must be 0 or 1");
+  if (o->mg_levels < 0) throw InvErr("mg_levels must be >= 0");
+  if (o->mg_smooth != 0 && o->mg_smooth != 2) throw InvErr("mg_smooth: only the degree-2 Chebyshev smoother is implemented");
 }
 
 }  // namespace
@@ -328,7 +330,8 @@ void build_hierarchy(jfnk_ctx* c, EllOp& op, bool want32) {
   int n[3] = {G.n[0], G.n[1], G.n[2]};
   op.lv64.push_back(make_level(c, n, G.nd, false, true));
   if (want32) op.lv32.push_back(make_level(c, n, G.nd, true, true));
-  while (coarsenable(n, G.nd)) {
+  const int maxl = c->opts.mg_levels;  // 0: as deep as the grid allows
+  while (coarsenable(n, G.nd) && (maxl == 0 || (int)op.lv64.size() < maxl)) {
     for (int d = 0; d < G.nd; ++d) n[d] /= 2;
     op.lv64.push_back(make_level(c, n, G.nd, false, false));
     if (want32) op.lv32.push_back(make_level(c, n, G.nd, true, false));
@@ -1150,6 +1153,8 @@ void jfnk_default_opts(jfnk_opts* o) {
   o->cg_maxit = 50;
   o->pc_schur = 0;
   o->phase_timing = 0;
+  o->mg_levels = 0;
+  o->mg_smooth = 2;
 }
 
 int jfnk_create(const jfnk_problem* prob, const jfnk_opts* opts, void* hip_stream, jfnk_ctx** out) {
@@ -1198,6 +1203,7 @@ int jfnk_set_opts(jfnk_ctx* c, const jfnk_opts* o) {
   ABI_BEGIN
   validate(&c->prob, o);
   if (o->gmres_m > c->m_alloc) throw InvErr("gmres_m exceeds the restart length the context was created with");
+  if (o->mg_levels != c->opts.mg_levels) throw InvErr("mg_levels is fixed when the context is created");
   c->opts = *o;
   return JFNK_OK;
   ABI_END(c)

@@ -31,6 +31,7 @@ def test_struct_layout_matches_c(tmp_path):
         "offsetof(jfnk_opts, cg_maxit));\n"
         'printf("%zu %zu %zu\\n", offsetof(jfnk_step_stats, dt), offsetof(jfnk_step_stats, t_orth), '
         "offsetof(jfnk_opts, phase_timing));\n"
+        'printf("%zu %zu\\n", offsetof(jfnk_opts, mg_levels), offsetof(jfnk_opts, mg_smooth));\n'
         "return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
@@ -43,6 +44,7 @@ def test_struct_layout_matches_c(tmp_path):
     assert vals[5] == N.Opts.cg_maxit.offset
     assert vals[6] == N.StepStats.dt.offset
     assert vals[7] == N.StepStats.t_orth.offset and vals[8] == N.Opts.phase_timing.offset
+    assert vals[9] == N.Opts.mg_levels.offset and vals[10] == N.Opts.mg_smooth.offset
 
 
 def test_defaults_are_the_paper_values():
@@ -55,6 +57,29 @@ def test_defaults_are_the_paper_values():
     assert o.gmres_maxit == gold["gmres_maxit"]["value"]
     assert o.newton_min == gold["newton_min"]["value"]
     assert o.jv_mode == N.JV_FD and o.precond == N.PC_SOUND and o.ell_precision == N.FP64
+
+
+def test_multigrid_options_are_validated_without_device():
+    """mg_levels >= 0 (0: as deep as the grid allows) and mg_smooth in {0, 2} (the degree the
+    kernels implement); bad values are refused on the host before any device call."""
+    lib = N.lib()
+    p = N.Problem()
+    p.ndim = 2
+    p.n[0], p.n[1], p.n[2] = 16, 16, 1
+    p.dx[0] = p.dx[1] = p.dx[2] = 1.0
+    p.gamma = 1.4
+    p.theta = 1.0
+    o = N.Opts()
+    lib.jfnk_default_opts(C.byref(o))
+    assert o.mg_levels == 0 and o.mg_smooth == 2
+    h = C.c_void_p()
+    for field, value, msg in (("mg_smooth", 3, b"degree-2"), ("mg_smooth", 1, b"degree-2"),
+                              ("mg_levels", -1, b"mg_levels")):
+        q = N.Opts()
+        C.memmove(C.byref(q), C.byref(o), C.sizeof(N.Opts))
+        setattr(q, field, value)
+        assert lib.jfnk_create(C.byref(p), C.byref(q), None, C.byref(h)) == N.E_INVALID
+        assert msg in lib.jfnk_last_error(None), (field, lib.jfnk_last_error(None))
 
 
 def test_create_rejects_bad_problem_without_device():

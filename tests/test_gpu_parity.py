@@ -320,6 +320,39 @@ def test_precond_parity_few_cg_iterations(mode, shape, bc, maxit):
         assert np.max(np.abs(gotT[k] - refT[k])) <= 1e-10 * np.max(np.abs(refT[k])), k
 
 
+@pytest.mark.parametrize("shape,bc,levels", [
+    ((16, 16), ("periodic", "wall"), 1), ((128, 64), ("periodic", "wall"), 1),
+    ((64, 32), ("periodic", "wall"), 2), ((16, 16, 16), ("periodic", "periodic", "wall"), 2),
+    ((32, 32, 32), ("periodic", "periodic", "wall"), 1), ((64, 32, 32), ("periodic", "periodic", "wall"), 3)])
+@pytest.mark.parametrize("maxit", [0, 2])
+def test_precond_parity_level_cap(shape, bc, levels, maxit):
+    """opts.mg_levels caps the multigrid hierarchy as the oracle's max_levels does: with a
+    fixed number of CG iterations the preconditioner and its transpose match the oracle's
+    to rounding.  The caps leave a coarsest level solved densely (16^2, 32 x 16, 8^3, 16 x 8^2)
+    or, above 4096 cells, smoothed (128 x 64, 32^3; the latter through the 3D z-marching
+    kernels)."""
+    from oracle.mg import PCGSolver
+    J = _lib()
+    nd = len(shape)
+    pd, X = W.random_state(shape, bc, seed=21, g=tuple([0.0] * (nd - 1) + [-1.0]), chi_model="power",
+                           chi0=0.02, amp=0.2)
+    P = Problem.from_dict(pd)
+    dt = 0.05
+    r = W.random_vector(X, 22)
+    print(f"# level cap {shape} levels {levels} cg_maxit {maxit}", flush=True)
+    pbp = PBP(P, X, dt, "sound_thermal", solver_factory=PCGSolver.factory(1e-4, maxit, max_levels=levels))
+    ctx = J.Context(pd, precond="sound_thermal", cg_maxit=maxit, mg_levels=levels)
+    ctx.set_state_n(T(X), dt)
+    ref, got = pbp.apply(r), H(ctx.precond_apply(T(X), T(r)))
+    refT, gotT = pbp.apply_T(r), H(ctx.precond_apply_transpose(T(X), T(r)))
+    for k in range(P.nvar):
+        assert np.max(np.abs(got[k] - ref[k])) <= 1e-10 * np.max(np.abs(ref[k])), k
+        assert np.max(np.abs(gotT[k] - refT[k])) <= 1e-10 * np.max(np.abs(refT[k])), k
+    with pytest.raises(J.JfnkError):
+        ctx.set_opts(mg_levels=levels + 1)
+    ctx.close()
+
+
 def test_implicit_step_single_vcycle_solves():
     """FGMRES with the one-V-cycle preconditioner reaches the same root."""
     w = W.polytrope((32, 32), 10.0, mach=1e-3, seed=5, chi_model="power", steps=1, cfl=50.0)

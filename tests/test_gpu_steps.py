@@ -182,6 +182,33 @@ def test_restart_lengths_match_the_oracle(name, m):
     ctx.close()
 
 
+@pytest.mark.parametrize("levels", [1, 2])
+def test_level_cap_step_matches_the_oracle(levels):
+    """A whole step with the multigrid hierarchy capped (opts.mg_levels; the oracle's
+    max_levels): one level (the 32^2 operator solved densely) or two.  Newton and GMRES
+    counts as the oracle's, CG totals within 0.5 %, state within the Newton tolerance."""
+    J = _lib()
+    mk, cfl, pc, jv = COUNT_CASES["polytrope_32_thermal"]
+    w = mk()
+    P = Problem.from_dict(w["problem"])
+    dt = cfl_dt(P, w["X0"], cfl)
+    st_o = Stats()
+    Xo = jfnk_step(P, w["X0"], dt, Opts(precond=pc, jv_mode=jv, mg_levels=levels), st_o)
+    assert st_o.converged
+    ctx = J.Context(w["problem"], precond=pc, jv_mode=jv, mg_levels=levels)
+    Xg = T(w["X0"])
+    st = ctx.implicit_step(Xg, dt)
+    got = (st["newton_its"], st["gmres_its"], st["cg_its"])
+    ref = (st_o.newton_its, sum(st_o.gmres_its), sum(st_o.cg_its))
+    _, R = scaling_LR(P, Xo)
+    err = float(np.max(np.abs((H(Xg) - Xo) / R)))
+    print(f"# mg_levels {levels}: gpu {got} oracle {ref}; ||R^-1 (X - X_or)||_inf {err:.3e}", flush=True)
+    assert got[:2] == ref[:2]
+    assert abs(got[2] - ref[2]) <= 0.005 * ref[2]
+    assert err <= 1e-8, err
+    ctx.close()
+
+
 @pytest.mark.parametrize("shape,bc", [((1024, 512), ("periodic", "wall")),
                                       ((128, 128, 48), ("periodic", "periodic", "wall"))])
 def test_fp32_elliptic_against_the_oracle_fp32_mgcg(shape, bc):

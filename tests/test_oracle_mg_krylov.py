@@ -161,3 +161,32 @@ def test_vcycle_with_smoothed_bottom_is_spd(shape, bc, monkeypatch):
     its = []
     x = pcg(op, b, eta=1e-8, maxit=400, stats=its)
     assert np.linalg.norm(b.ravel() - op.to_sparse() @ x.ravel()) < 1e-8 * np.linalg.norm(b)
+
+
+def test_level_cap():
+    """max_levels caps the hierarchy (16^2 coarsens to 8^2 and 4^2 by itself).  One level: the
+    V-cycle is the dense solve of the level itself, i.e. A^-1 b.  Two levels: still a symmetric
+    positive definite operator, and CG preconditioned by it meets its stopping rule."""
+    P, X = _state((16, 16), ("periodic", "wall"))
+    op = pressure_operator(P, X, _stiff_dt(P, 30.0))
+    assert [lev.prob.shape for lev in Multigrid(op).levels] == [(16, 16), (8, 8), (4, 4)]
+    for L in (1, 2, 3, 7):
+        assert len(Multigrid(op, max_levels=L).levels) == min(L, 3)
+    A = op.to_sparse()
+    b = np.random.default_rng(4).uniform(-1, 1, P.field_shape)
+    x1 = Multigrid(op, max_levels=1).vcycle(b)
+    xd = spla.spsolve(A.tocsc(), b.ravel())
+    assert np.max(np.abs(x1.ravel() - xd)) <= 1e-11 * np.max(np.abs(xd))
+    mg2 = Multigrid(op, max_levels=2)
+    N = P.ncell
+    B = np.empty((N, N))
+    for k in range(N):
+        e = np.zeros(N)
+        e[k] = 1.0
+        B[:, k] = mg2.vcycle(e.reshape(P.field_shape)).ravel()
+    assert np.max(np.abs(B - B.T)) <= 1e-12 * np.max(np.abs(B))
+    assert np.min(np.linalg.eigvalsh(0.5 * (B + B.T))) > 0
+    its = []
+    x = pcg(op, b, eta=1e-8, maxit=200, mg=mg2, stats=its)
+    assert np.linalg.norm(b.ravel() - A @ x.ravel()) < 1e-8 * np.linalg.norm(b)
+
