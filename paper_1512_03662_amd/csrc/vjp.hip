@@ -658,9 +658,20 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))
     res[0] = cU * r0;
     res[1] = cU * r1;
   }
-  // R part: sum over padded copies
+  // R part: sum over padded copies (a cell at least 4 cells from both ends of every axis has
+  // no image in the padded grid, only itself with sign +1, whatever the axis's boundary)
+  bool inner = true;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) inner = inner && P.c[d] >= 4 && P.c[d] <= G.n[d] - 4;
+  if (inner) {
+    int pl = (P.c[0] + 3) + (P.c[1] + (ND >= 2 ? 3 : 0)) * PG.pstride[1];
+    if (ND == 3) pl += (P.c[2] + 3) * PG.pstride[2];
+#pragma unroll
+    for (int var = 0; var < 2 + ND; ++var) res[var] += xbar[(size_t)var * PG.PN + pl];
+  }
 #pragma unroll
   for (int var = 0; var < 2 + ND; ++var) {
+    if (inner) break;
     int pos[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
     double sg[3][3] = {{1.0, 0.0, 0.0}, {1.0, 0.0, 0.0}, {1.0, 0.0, 0.0}};
 #pragma unroll
