@@ -14,9 +14,10 @@ preconditioner:
 * coarse diagonal = mean of the 2^d children; coarse face weight = mean of the covered fine
   face weights / 4 (the same operator rediscretised at twice the spacing);
 * restriction = mean of the children; prolongation = piecewise-constant injection;
-* smoother: Chebyshev polynomial of degree 2 in D^-1 A on [lmax/4, lmax] with
-  lmax = 2, the Gershgorin bound of D^-1 A (discs centred at 1 with radius < 1); the same
-  smoother before and after the coarse correction keeps the V-cycle symmetric;
+* smoother: Chebyshev polynomial of degree k (default 2) in D^-1 A on [lmax/4, lmax] with
+  lmax = 2, the Gershgorin bound of D^-1 A (discs centred at 1 with radius < 1), by the
+  three-term recurrence of the Chebyshev semi-iteration; the same smoother before and after
+  the coarse correction keeps the V-cycle symmetric;
 * coarsest level: dense Cholesky (always in FP64) while it has at most ``DENSE_MAX`` = 4096
   cells.  A grid with an odd axis cannot be coarsened that far (for example the 72 x 65 x 65
   grid of the paper's 3D red-giant run, Sect. 5.2); its coarsest level is then not solved
@@ -98,8 +99,9 @@ class Multigrid:
     LMIN = 0.5
     DENSE_MAX = 4096
 
-    def __init__(self, op: EllOp, dtype=np.float64, max_levels=0):
+    def __init__(self, op: EllOp, dtype=np.float64, max_levels=0, degree=2):
         self.dtype = dtype
+        self.degree = degree
         prob = op.prob
         cast = lambda a: np.asarray(a, dtype=dtype)
         self.levels = [Level(prob, EllOp(prob, cast(op.diag), [cast(w) for w in op.w]))]
@@ -120,19 +122,24 @@ class Multigrid:
             self.coarse_chol = sla.cho_factor(A, lower=True)
 
     def smooth(self, lev: Level, b, x):
-        """Degree-2 Chebyshev-Jacobi smoothing of A x = b starting from x."""
+        """Chebyshev-Jacobi smoothing of A x = b starting from x: d_0 = D^-1 r_0 / theta,
+        then d_i = rho_i rho_{i-1} d_{i-1} + (2 rho_i / delta) D^-1 r_i with
+        rho_0 = delta / theta, rho_i = 1 / (2 theta / delta - rho_{i-1}); x += d_i each step."""
         t = self.dtype
         theta = t(0.5 * (self.LMAX + self.LMIN))
         delta = t(0.5 * (self.LMAX - self.LMIN))
         sigma = theta / delta
-        rho0 = t(1.0) / sigma
+        rho = t(1.0) / sigma
         r = b - lev.op.apply(x)
         dvec = lev.dinv * r / theta
         x = x + dvec
-        r = b - lev.op.apply(x)
-        rho1 = t(1.0) / (t(2.0) * sigma - rho0)
-        dvec = rho1 * rho0 * dvec + (t(2.0) * rho1 / delta) * (lev.dinv * r)
-        return x + dvec
+        for _ in range(1, self.degree):
+            r = b - lev.op.apply(x)
+            rho_new = t(1.0) / (t(2.0) * sigma - rho)
+            dvec = rho_new * rho * dvec + (t(2.0) * rho_new / delta) * (lev.dinv * r)
+            rho = rho_new
+            x = x + dvec
+        return x
 
     def vcycle(self, b, level=0):
         lev = self.levels[level]
@@ -200,15 +207,15 @@ def pcg(op: EllOp, b, eta=1e-4, maxit=50, dtype=np.float64, mg=None, stats=None)
 class PCGSolver:
     """Callable b -> A^-1 b by MG-preconditioned CG (for ``pbp.PBP(solver_factory=...)``)."""
 
-    def __init__(self, op, eta=1e-4, maxit=50, dtype=np.float64, max_levels=0):
+    def __init__(self, op, eta=1e-4, maxit=50, dtype=np.float64, max_levels=0, degree=2):
         self.op = op
         self.eta, self.maxit, self.dtype = eta, maxit, dtype
-        self.mg = Multigrid(op, dtype, max_levels)
+        self.mg = Multigrid(op, dtype, max_levels, degree)
         self.iters = []
 
     def __call__(self, b):
         return pcg(self.op, b, self.eta, self.maxit, self.dtype, self.mg, self.iters)
 
     @staticmethod
-    def factory(eta=1e-4, maxit=50, dtype=np.float64, max_levels=0):
-        return lambda op: PCGSolver(op, eta, maxit, dtype, max_levels)
+    def factory(eta=1e-4, maxit=50, dtype=np.float64, max_levels=0, degree=2):
+        return lambda op: PCGSolver(op, eta, maxit, dtype, max_levels, degree)

@@ -54,6 +54,7 @@ class Opts:
     cg_eta: float = 1e-4
     cg_maxit: int = 50
     mg_levels: int = 0           # 0: coarsen as far as the grid allows; L: at most L levels
+    mg_smooth: int = 2           # degree of the Chebyshev-Jacobi smoother
 
 
 @dataclass
@@ -119,7 +120,7 @@ def jfnk_step(prob: Problem, Xn, dt, opts: Opts = None, stats: Stats = None):
                 fac_list = []
 
                 def fac(op):
-                    s = PCGSolver(op, opts.cg_eta, opts.cg_maxit, opts.ell_dtype, opts.mg_levels)
+                    s = PCGSolver(op, opts.cg_eta, opts.cg_maxit, opts.ell_dtype, opts.mg_levels, opts.mg_smooth)
                     fac_list.append(s)
                     return s
                 pbp = PBP(prob, X, dt, opts.precond, solver_factory=fac, schur=opts.pc_schur)

@@ -190,3 +190,54 @@ def test_level_cap():
     x = pcg(op, b, eta=1e-8, maxit=200, mg=mg2, stats=its)
     assert np.linalg.norm(b.ravel() - A @ x.ravel()) < 1e-8 * np.linalg.norm(b)
 
+
+
+@pytest.mark.parametrize("degree", [1, 2, 3, 4])
+def test_smoother_is_the_scaled_chebyshev_polynomial(degree):
+    """k steps of the smoother from x = 0 give x = S b whose error propagator I - S A equals
+    P_k(D^-1 A) with P_k(l) = T_k((theta - l)/delta) / T_k(theta/delta), theta = 1.25,
+    delta = 0.75 (the interval [0.5, 2]): the closed form of the Chebyshev semi-iteration,
+    evaluated through the eigenvectors of D^-1/2 A D^-1/2 and numpy's Chebyshev series."""
+    from numpy.polynomial import chebyshev as C
+    P, X = _state((6, 5), ("periodic", "wall"))
+    op = pressure_operator(P, X, _stiff_dt(P, 30.0))
+    mg = Multigrid(op, max_levels=1, degree=degree)
+    lev = mg.levels[0]
+    A = op.to_sparse().toarray()
+    N = A.shape[0]
+    S = np.empty((N, N))
+    for k in range(N):
+        e = np.zeros(N)
+        e[k] = 1.0
+        S[:, k] = mg.smooth(lev, e.reshape(P.field_shape), np.zeros(P.field_shape)).ravel()
+    E = np.eye(N) - S @ A
+    Dh = np.sqrt(np.diag(A))
+    lam, Q = np.linalg.eigh(A / np.outer(Dh, Dh))
+    coef = np.zeros(degree + 1)
+    coef[degree] = 1.0
+    p = C.chebval((1.25 - lam) / 0.75, coef) / C.chebval(1.25 / 0.75, coef)
+    Eref = (Q * p) @ Q.T / Dh[:, None] * Dh[None, :]
+    assert np.max(np.abs(E - Eref)) <= 1e-12
+    # and the smoothing damps the upper part of the spectrum [0.5, 2] at least by T_k(5/3)^-1
+    assert np.max(np.abs(p[lam >= 0.5])) <= 1.0 / C.chebval(1.25 / 0.75, coef) + 1e-12
+
+
+@pytest.mark.parametrize("degree", [1, 3])
+def test_vcycle_other_degrees_is_spd(degree):
+    """The V-cycle with the degree-1 or degree-3 smoother is symmetric positive definite
+    and preconditions CG to its stopping rule."""
+    P, X = _state((16, 8), ("periodic", "wall"))
+    op = pressure_operator(P, X, _stiff_dt(P, 30.0))
+    mg = Multigrid(op, degree=degree)
+    assert len(mg.levels) >= 2
+    N = P.ncell
+    B = np.empty((N, N))
+    for k in range(N):
+        e = np.zeros(N)
+        e[k] = 1.0
+        B[:, k] = mg.vcycle(e.reshape(P.field_shape)).ravel()
+    assert np.max(np.abs(B - B.T)) <= 1e-12 * np.max(np.abs(B))
+    assert np.min(np.linalg.eigvalsh(0.5 * (B + B.T))) > 0
+    b = np.random.default_rng(5).uniform(-1, 1, P.field_shape)
+    x = pcg(op, b, eta=1e-8, maxit=200, mg=mg)
+    assert np.linalg.norm(b.ravel() - op.to_sparse() @ x.ravel()) < 1e-8 * np.linalg.norm(b)
