@@ -103,9 +103,10 @@ typedef struct {
                           * levels.  Fixed when the context is created (jfnk_set_opts      *
                           * rejects a change).  A coarsest level of more than 4096 cells   *
                           * is smoothed instead of solved exactly                          */
-  int32_t mg_smooth;     /* degree of the Chebyshev-Jacobi smoother: 2 (0 selects it); the  *
-                          * kernels implement degree 2 only, other values are rejected     *
-                          * with JFNK_E_INVALID                                            */
+  int32_t mg_smooth;     /* degree k of the Chebyshev-Jacobi smoother on [0.5, 2] in       *
+                          * D^-1 A, before and after the coarse correction: 1..8, 0 = 2    *
+                          * (the default; its steps run fused with the V-cycle's other     *
+                          * kernels, the other degrees one launch per step)                */
 } jfnk_opts;
 
 typedef struct {

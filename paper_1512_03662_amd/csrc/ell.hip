@@ -1387,6 +1387,64 @@ void launch_dense_matvec(int n, const double* A, const T* x, T* y, const CGArgs&
   k_dense_matvec<T><<<CELLS(n), 0, s>>>(n, A, x, y, g);
 }
 
+// ---- Chebyshev smoothing of any degree (every level, grid-stride) ------------------------
+// The kernels above fuse the two steps of the degree-2 smoother with their neighbours; other
+// degrees take one launch per step: from zero, d = x = D^-1 b / theta; then, from x,
+// d = c1 d + c2 D^-1 (b - A x) and x + d, with c1 = rho_i rho_{i-1}, c2 = 2 rho_i / delta of
+// the Chebyshev semi-iteration on [0.5, 2] (cheb_coefs).  d is updated in place (each cell
+// reads and writes only its own entry); x is read at the neighbours, so xout != xin.
+void cheb_coefs(int k, double* c1, double* c2) {
+  const double theta = kChebTheta, delta = 2.0 - kChebTheta, sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  for (int i = 1; i < k; ++i) {
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    c1[i] = rn * rho;
+    c2[i] = 2.0 * rn / delta;
+    rho = rn;
+  }
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_cheb_zero(int n, const T* dinv, const T* b, T* x, T* d, CGArgs g) {
+  if (g.ctl->flag) return;
+  const T th = T(1.0 / kChebTheta);
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    const T dd = dinv[i] * b[i] * th;
+    x[i] = dd;
+    d[i] = dd;
+  }
+}
+template <class T, int ND>
+__global__ void __launch_bounds__(kBlock) k_cheb_step(LV<T> L, const T* b, const T* xin, T* xout, T* d, T c1, T c2,
+                                                      CGArgs g) {
+  if (g.ctl->flag) return;
+  auto xf = [&](int i) { return xin[i]; };
+  FOR_CELLS(lin, L.N) {
+    int c[3];
+    coords<ND>(L.n, lin, c);
+    const T xc = xin[lin];
+    const T r = b[lin] - apply_at<T, ND>(L, c, lin, xf, xc);
+    const T dd = c1 * d[lin] + c2 * (L.dinv[lin] * r);
+    d[lin] = dd;
+    xout[lin] = xc + dd;
+  }
+}
+template <class T>
+void launch_cheb_zero(const Grid& G, const Level& L, const T* b, T* x, T* d, const CGArgs& g, hipStream_t s) {
+  (void)G;
+  launch_k(KF_MG_PRE, 4.0 * L.N * sizeof(T), k_cheb_zero<T>, CELLS(L.N), 0, s, L.N, (const T*)L.dinv, b, x, d, g);
+}
+template <class T>
+void launch_cheb_step(const Grid& G, const Level& L, const T* b, const T* xin, T* xout, T* d, double c1, double c2,
+                      const CGArgs& g, hipStream_t s) {
+  LV<T> v = view<T>(G, L);
+  const double by = (7.0 + G.nd) * L.N * (double)sizeof(T);
+  if (G.nd == 2)
+    launch_k(KF_MG_SMOOTH2, by, k_cheb_step<T, 2>, CELLS(L.N), 0, s, v, b, xin, xout, d, (T)c1, (T)c2, g);
+  else
+    launch_k(KF_MG_SMOOTH2, by, k_cheb_step<T, 3>, CELLS(L.N), 0, s, v, b, xin, xout, d, (T)c1, (T)c2, g);
+}
+
 // ---- CG kernels ------------------------------------------------------------------------
 // iteration it (1-based).  apply: p = z + beta p_old with beta = (r,z)_{it-1}/(r,z)_{it-2}
 // (p = z when it = 1), q = A p, partials of (p, q).  It also stores (r,z)_{it-1}, and at
@@ -1731,7 +1789,11 @@ void launch_pbp_out(const Grid& G, const double* X, const double* v, int scaled,
   template void launch_cg_update<T>(const Grid&, const Level&, const T*, const T*, const T*, T*, T*, T*,\
                                     const CGArgs&, int, hipStream_t);                                    \
   template void launch_cg_init<T>(int, const T*, const CGArgs&, hipStream_t);                           \
-  template void launch_cg_dot_rz<T>(int, const T*, const T*, const CGArgs&, hipStream_t);
+  template void launch_cg_dot_rz<T>(int, const T*, const T*, const CGArgs&, hipStream_t);              \
+  template void launch_cheb_zero<T>(const Grid&, const Level&, const T*, T*, T*, const CGArgs&,         \
+                                    hipStream_t);                                                       \
+  template void launch_cheb_step<T>(const Grid&, const Level&, const T*, const T*, T*, T*, double,      \
+                                    double, const CGArgs&, hipStream_t);
 INST(float)
 INST(double)
 

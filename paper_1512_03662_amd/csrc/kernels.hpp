@@ -136,6 +136,16 @@ void launch_mg_smooth2(const Grid& G, const Level& L, const T* b, const T* x1, c
                        const CGArgs& g, bool rz, hipStream_t s);
 template <class T>
 void launch_dense_matvec(int n, const double* A, const T* x, T* y, const CGArgs& g, hipStream_t s);
+// Chebyshev-Jacobi smoothing of any degree, one launch per step (the fused V-cycle kernels
+// implement degree 2): coefficients c1[i], c2[i] of steps i = 1..k-1; the first step from
+// zero (x = d = D^-1 b / theta); a further step (d = c1 d + c2 D^-1 (b - A xin),
+// xout = xin + d; xout != xin)
+void cheb_coefs(int k, double* c1, double* c2);
+template <class T>
+void launch_cheb_zero(const Grid& G, const Level& L, const T* b, T* x, T* d, const CGArgs& g, hipStream_t s);
+template <class T>
+void launch_cheb_step(const Grid& G, const Level& L, const T* b, const T* xin, T* xout, T* d, double c1, double c2,
+                      const CGArgs& g, hipStream_t s);
 
 // coarse part of a V-cycle (levels of at most kCoarseMaxN cells) in one workgroup
 constexpr int kCoarseMaxN = 1024;

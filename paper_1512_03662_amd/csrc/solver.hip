@@ -269,7 +269,7 @@ void validate(const jfnk_problem* p, const jfnk_opts* o) {
   if (o->pc_schur != 0 && o->pc_schur != 1) throw InvErr("pc_schur must be 0 or 1");
   if (o->phase_timing != 0 && o->phase_timing != 1) throw InvErr("phase_timing must be 0 or 1");
   if (o->mg_levels < 0) throw InvErr("mg_levels must be >= 0");
-  if (o->mg_smooth != 0 && o->mg_smooth != 2) throw InvErr("mg_smooth: only the degree-2 Chebyshev smoother is implemented");
+  if (o->mg_smooth < 0 || o->mg_smooth > 8) throw InvErr("mg_smooth (Chebyshev degree) must be in 1..8 (0: 2)");
 }
 
 }  // namespace
@@ -531,6 +531,118 @@ void vcycle_rest(jfnk_ctx* c, std::vector<Level>& lv, const double* Ainv, const 
   }
 }
 
+// One V-cycle z = M r with the Chebyshev smoother of degree k != 2 (opts.mg_smooth), one
+// launch per smoothing step on every level (the fused kernels above implement degree 2).  On
+// level l the result goes to out (lv[l].x, or z on level 0); the presmoothed iterate is kept
+// in `pre` for the restriction and the prolongation, and the smoother's x iterates alternate
+// so that the last step of each smoothing lands where it must (steps never read and write
+// the same x buffer; d is updated in place).  The coarsest level is solved by its dense
+// inverse, or, above the dense limit, smoothed from zero and then from that iterate.
+template <class T>
+void vcycle_any(jfnk_ctx* c, std::vector<Level>& lv, const double* Ainv, int l, const T* b, T* out, T* other, T* d,
+                const CGArgs& g, int k) {
+  const Grid& G = c->G;
+  hipStream_t s = c->stream;
+  const int nl = (int)lv.size();
+  double c1[16], c2[16];
+  cheb_coefs(k, c1, c2);
+  // the presmoothed iterate sits in `out` when k is even and in `other` when k is odd, so that
+  // the post-smoothing (which starts by reading it and alternates from the other buffer)
+  // ends in `out`
+  T* pre = (k % 2 == 0) ? out : other;
+  T* alt = (k % 2 == 0) ? other : out;
+  // k steps from zero, ending in pre
+  auto smooth_zero = [&]() {
+    T* y = ((k - 1) % 2 == 0) ? pre : alt;
+    launch_cheb_zero<T>(G, lv[l], b, y, d, g, s);
+    for (int i = 1; i < k; ++i) {
+      T* yn = ((k - 1 - i) % 2 == 0) ? pre : alt;
+      launch_cheb_step<T>(G, lv[l], b, y, yn, d, c1[i], c2[i], g, s);
+      y = yn;
+    }
+  };
+  // k steps from pre + P xc (xc on level C), ending in out
+  auto smooth_post = [&](const T* xc, const Level& C) {
+    launch_mg_prolong_smooth1<T>(G, lv[l], b, pre, xc, C, alt, d, g, s);
+    T* y = alt;
+    for (int i = 1; i < k; ++i) {
+      T* yn = (y == alt) ? pre : alt;
+      launch_cheb_step<T>(G, lv[l], b, y, yn, d, c1[i], c2[i], g, s);
+      y = yn;
+    }
+  };
+  if (l == nl - 1) {
+    if (Ainv) {
+      launch_dense_matvec<T>(lv[l].N, Ainv, b, out, g, s);
+      return;
+    }
+    Level zc{};
+    zc.N = 1;  // strides 0: every cell's parent is the single zero entry
+    const T* zero = std::is_same<T, float>::value ? (const T*)c->zero32 : (const T*)c->zero64;
+    smooth_zero();
+    smooth_post(zero, zc);
+    return;
+  }
+  smooth_zero();
+  Level& C = lv[l + 1];
+  launch_mg_restrict_resid<T>(G, lv[l], b, pre, (T*)C.b, C, g, 0, s);
+  vcycle_any<T>(c, lv, Ainv, l + 1, (const T*)C.b, (T*)C.x, (T*)C.t1, (T*)C.t2, g, k);
+  smooth_post((const T*)C.x, C);
+}
+
+// PCG as below with the V-cycle of vcycle_any (smoother degree k != 2): the decision of each
+// iteration is a kernel of its own, and the (r, z) partials a dot product after the V-cycle.
+template <class T>
+int pcg_any(jfnk_ctx* c, std::vector<Level>& lv, const double* Ainv, const T* b, T* x, T* const* v, int* pred,
+            const CGArgs& g, int k) {
+  const Grid& G = c->G;
+  hipStream_t s = c->stream;
+  const int N = G.N;
+  T *r1 = v[0], *r2 = v[1], *p1 = v[2], *p2 = v[3], *q = v[4], *z = v[5], *x2 = v[6];
+  T* d = (T*)lv[0].t2;
+  launch_cg_init<T>(N, b, g, s);
+  if (g.maxit == 0) {
+    vcycle_any<T>(c, lv, Ainv, 0, b, x, x2, d, g, k);
+    return 0;
+  }
+  vcycle_any<T>(c, lv, Ainv, 0, b, z, x2, d, g, k);
+  launch_cg_dot_rz<T>(N, b, z, g, s);
+  const T* rold = b;
+  T* rnew = r1;
+  const T* pold = z;
+  T* pnew = p1;
+  int enq = 0;
+  int batch = std::max(1, std::min(*pred, g.maxit));
+  for (;;) {
+    for (int i = 0; i < batch && enq < g.maxit; ++i) {
+      const int it = ++enq;
+      const bool last = (enq == g.maxit) || (i == batch - 1);
+      launch_cg_apply<T>(G, lv[0], z, pold, pnew, q, x, g, it, s);
+      launch_cg_update<T>(G, lv[0], rold, q, pnew, x, rnew, nullptr, g, it, s);
+      launch_cg_decide(g, it, s);
+      if (!last) {
+        vcycle_any<T>(c, lv, Ainv, 0, rnew, z, x2, d, g, k);
+        launch_cg_dot_rz<T>(N, rnew, z, g, s);
+      }
+      rold = rnew;
+      rnew = (rnew == r1) ? r2 : r1;
+      pold = pnew;
+      pnew = (pnew == p1) ? p2 : p1;
+    }
+    check_launch();
+    HIPX(hipMemcpyAsync(c->hctl, c->ctl, sizeof(CGCtl), hipMemcpyDeviceToHost, s));
+    sync(c);
+    if (c->hctl->flag != 0 || enq >= g.maxit) break;
+    vcycle_any<T>(c, lv, Ainv, 0, rold, z, x2, d, g, k);
+    launch_cg_dot_rz<T>(N, rold, z, g, s);
+    batch = 1;
+  }
+  if (c->hctl->flag < 0) throw FiniteErr("non-finite residual in an elliptic solve");
+  if (c->hctl->flag == 0) throw FiniteErr("elliptic solve ended without a decision");
+  *pred = std::max(1, c->hctl->its);
+  return c->hctl->its;
+}
+
 // PCG on level 0 of lv: x = A^-1 b (x and b of type T, length N), stopping when
 // ||r|| < cg_eta ||b|| or after cg_maxit iterations.  The iterations run from the device
 // (CGCtl); the host enqueues `pred` of them (the previous count of this solver), then one
@@ -549,6 +661,8 @@ int pcg(jfnk_ctx* c, std::vector<Level>& lv, const double* Ainv, const T* b, T* 
   g.np = cg_partials((size_t)N);
   g.eta = c->opts.cg_eta;
   g.maxit = c->opts.cg_maxit;
+  const int deg = (c->opts.mg_smooth == 0) ? 2 : c->opts.mg_smooth;
+  if (deg != 2) return pcg_any<T>(c, lv, Ainv, b, x, v, pred, g, deg);
   bool fused;
   const int l0 = first_fused(lv, &fused);
   const int nl = (int)lv.size();

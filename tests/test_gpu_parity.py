@@ -353,6 +353,37 @@ def test_precond_parity_level_cap(shape, bc, levels, maxit):
     ctx.close()
 
 
+@pytest.mark.parametrize("shape,bc,levels", [
+    ((64, 32), ("periodic", "wall"), 0), ((64, 32), ("periodic", "wall"), 2),
+    ((16, 16, 16), ("periodic", "periodic", "wall"), 0), ((32, 32, 32), ("periodic", "periodic", "wall"), 1)])
+@pytest.mark.parametrize("degree", [1, 3])
+@pytest.mark.parametrize("maxit", [0, 2])
+def test_precond_parity_smoother_degree(shape, bc, levels, degree, maxit):
+    """opts.mg_smooth = 1 or 3 (the Chebyshev degree; the library's default 2 runs fused
+    kernels, the other degrees one launch per step) against the oracle's smoother of the same
+    degree, with a fixed number of CG iterations: full hierarchies down to the dense solve and
+    a single 32^3 level smoothed at the bottom."""
+    from oracle.mg import PCGSolver
+    J = _lib()
+    nd = len(shape)
+    pd, X = W.random_state(shape, bc, seed=23, g=tuple([0.0] * (nd - 1) + [-1.0]), chi_model="power",
+                           chi0=0.02, amp=0.2)
+    P = Problem.from_dict(pd)
+    dt = 0.05
+    r = W.random_vector(X, 24)
+    print(f"# smoother degree {degree} {shape} levels {levels} cg_maxit {maxit}", flush=True)
+    fac = PCGSolver.factory(1e-4, maxit, max_levels=levels, degree=degree)
+    pbp = PBP(P, X, dt, "sound_thermal", solver_factory=fac)
+    ctx = J.Context(pd, precond="sound_thermal", cg_maxit=maxit, mg_levels=levels, mg_smooth=degree)
+    ctx.set_state_n(T(X), dt)
+    ref, got = pbp.apply(r), H(ctx.precond_apply(T(X), T(r)))
+    refT, gotT = pbp.apply_T(r), H(ctx.precond_apply_transpose(T(X), T(r)))
+    for k in range(P.nvar):
+        assert np.max(np.abs(got[k] - ref[k])) <= 1e-10 * np.max(np.abs(ref[k])), k
+        assert np.max(np.abs(gotT[k] - refT[k])) <= 1e-10 * np.max(np.abs(refT[k])), k
+    ctx.close()
+
+
 def test_implicit_step_single_vcycle_solves():
     """FGMRES with the one-V-cycle preconditioner reaches the same root."""
     w = W.polytrope((32, 32), 10.0, mach=1e-3, seed=5, chi_model="power", steps=1, cfl=50.0)

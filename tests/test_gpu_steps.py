@@ -182,27 +182,29 @@ def test_restart_lengths_match_the_oracle(name, m):
     ctx.close()
 
 
-@pytest.mark.parametrize("levels", [1, 2])
-def test_level_cap_step_matches_the_oracle(levels):
+@pytest.mark.parametrize("levels,degree", [(1, 2), (2, 2), (0, 1), (0, 3), (2, 3)])
+def test_level_cap_step_matches_the_oracle(levels, degree):
     """A whole step with the multigrid hierarchy capped (opts.mg_levels; the oracle's
-    max_levels): one level (the 32^2 operator solved densely) or two.  Newton and GMRES
-    counts as the oracle's, CG totals within 0.5 %, state within the Newton tolerance."""
+    max_levels): one level (the 32^2 operator solved densely) or two, and with the smoother's
+    degree set (opts.mg_smooth; the oracle's degree).  Newton and GMRES counts as the
+    oracle's, CG totals within 0.5 %, state within the Newton tolerance."""
     J = _lib()
     mk, cfl, pc, jv = COUNT_CASES["polytrope_32_thermal"]
     w = mk()
     P = Problem.from_dict(w["problem"])
     dt = cfl_dt(P, w["X0"], cfl)
     st_o = Stats()
-    Xo = jfnk_step(P, w["X0"], dt, Opts(precond=pc, jv_mode=jv, mg_levels=levels), st_o)
+    Xo = jfnk_step(P, w["X0"], dt, Opts(precond=pc, jv_mode=jv, mg_levels=levels, mg_smooth=degree), st_o)
     assert st_o.converged
-    ctx = J.Context(w["problem"], precond=pc, jv_mode=jv, mg_levels=levels)
+    ctx = J.Context(w["problem"], precond=pc, jv_mode=jv, mg_levels=levels, mg_smooth=degree)
     Xg = T(w["X0"])
     st = ctx.implicit_step(Xg, dt)
     got = (st["newton_its"], st["gmres_its"], st["cg_its"])
     ref = (st_o.newton_its, sum(st_o.gmres_its), sum(st_o.cg_its))
     _, R = scaling_LR(P, Xo)
     err = float(np.max(np.abs((H(Xg) - Xo) / R)))
-    print(f"# mg_levels {levels}: gpu {got} oracle {ref}; ||R^-1 (X - X_or)||_inf {err:.3e}", flush=True)
+    print(f"# mg_levels {levels} degree {degree}: gpu {got} oracle {ref}; ||R^-1 (X - X_or)||_inf {err:.3e}",
+          flush=True)
     assert got[:2] == ref[:2]
     assert abs(got[2] - ref[2]) <= 0.005 * ref[2]
     assert err <= 1e-8, err
