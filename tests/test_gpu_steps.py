@@ -240,6 +240,31 @@ def test_fp32_elliptic_against_the_oracle_fp32_mgcg(shape, bc):
     ctx.close()
 
 
+@pytest.mark.parametrize("shape,bc,levels,degree", [((256, 128), ("periodic", "wall"), 0, 3),
+                                                    ((64, 32, 32), ("periodic", "periodic", "wall"), 2, 1)])
+def test_fp32_elliptic_with_multigrid_options(shape, bc, levels, degree):
+    """The FP32 elliptic solves with the multigrid options set (smoother degree 3 or 1, which
+    run the one-launch-per-step kernels, and a capped hierarchy) against the oracle's FP32
+    multigrid CG with the same options, to the bar of the FP32 test above."""
+    J = _lib()
+    nd = len(shape)
+    pd, X = W.random_state(shape, bc, seed=25, g=tuple([0.0] * (nd - 1) + [-1.0]), chi_model="power",
+                           chi0=0.02, amp=0.2)
+    P = Problem.from_dict(pd)
+    dt = 0.05
+    r = W.random_vector(X, 26)
+    fac = PCGSolver.factory(1e-4, 50, np.float32, max_levels=levels, degree=degree)
+    ref32 = PBP(P, X, dt, "sound_thermal", solver_factory=fac).apply(r)
+    ctx = J.Context(pd, precond="sound_thermal", ell_precision="fp32", cg_eta=1e-4, cg_maxit=50,
+                    mg_levels=levels, mg_smooth=degree)
+    ctx.set_state_n(T(X), dt)
+    got = H(ctx.precond_apply(T(X), T(r)))
+    e32 = [float(np.max(np.abs(got[k] - ref32[k])) / np.max(np.abs(ref32[k]))) for k in range(P.nvar)]
+    print(f"# fp32 {shape} levels {levels} degree {degree}: vs oracle fp32 {max(e32):.2e}", flush=True)
+    assert max(e32) <= 5e-6, e32
+    ctx.close()
+
+
 def test_phase_timing_of_a_step():
     """opts.phase_timing = 1: the step's residual, J.v, preconditioner and orthogonalisation
     phases get positive GPU times that sum to less than the step's wall time; 0: all zero.
