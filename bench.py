@@ -92,19 +92,26 @@ def measured_traffic(workload_name, kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary of this workload
     (FETCH_SIZE and WRITE_SIZE per dispatch, scaled by the copy-kernel calibration), or None
     when there is none for this kernel or its source has changed since the counters were
-    taken."""
+    taken.  The summary's machine-readable part holds one block per kernel family, each
+    opened by a `kernel:` line."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload_name}.txt")
     if not os.path.exists(path):
         return None
-    kv = {}
+    blocks, cur = {}, None
     with open(path) as f:
         for line in f:
             if line.startswith("#") or ":" not in line:
                 continue
-            k, v = line.split(":", 1)
-            kv[k.strip()] = v.strip()
+            k, v = (t.strip() for t in line.split(":", 1))
+            if k == "kernel":
+                cur = blocks.setdefault(v, {})
+            elif cur is not None:
+                cur[k] = v
+    kv = blocks.get(kernel)
+    if kv is None:
+        return None
     try:
-        if kv.get("kernel") != kernel or source_sha256(kv["source"]) != kv["source_sha256"]:
+        if source_sha256(kv["source"]) != kv["source_sha256"]:
             return None
         return 1024.0 * (float(kv["fetch_kib_per_launch"]) * float(kv["fetch_calibration"])
                          + float(kv["write_kib_per_launch"]) * float(kv["write_calibration"]))

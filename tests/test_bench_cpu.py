@@ -43,6 +43,28 @@ def test_traffic_summary_needs_the_same_source(tmp_path, monkeypatch):
     assert bench.measured_traffic("wl", "mg_down") is None
 
 
+def test_traffic_summary_with_one_block_per_family(tmp_path, monkeypatch):
+    """Several families in one summary, each with its own source file: each block is read
+    for its own kernel, and a changed source voids only the blocks that name it."""
+    (tmp_path / "a.hip").write_text("a\n")
+    (tmp_path / "b.hip").write_text("b\n")
+    (tmp_path / "profiles").mkdir()
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+
+    def block(name, fetch, src, sha):
+        return (f"kernel: {name}\nfetch_kib_per_launch: {fetch}\nwrite_kib_per_launch: 1.0\n"
+                f"fetch_calibration: 2.0\nwrite_calibration: 1.0\nsource: {src}\nsource_sha256: {sha}\n")
+
+    (tmp_path / "profiles" / "traffic_wl.txt").write_text(
+        "# counters\n" + block("mg_smooth2", 10.0, "a.hip", bench.source_sha256("a.hip"))
+        + block("cg_update", 20.0, "a.hip", bench.source_sha256("a.hip"))
+        + block("gs_update", 30.0, "b.hip", "0" * 64))
+    assert bench.measured_traffic("wl", "mg_smooth2") == 1024.0 * (10.0 * 2.0 + 1.0)
+    assert bench.measured_traffic("wl", "cg_update") == 1024.0 * (20.0 * 2.0 + 1.0)
+    assert bench.measured_traffic("wl", "gs_update") is None     # its source changed since
+    assert bench.measured_traffic("wl", "mg_down") is None       # no block for it
+
+
 def test_extrapolated_cpu_baseline_on_a_small_sample():
     """The extrapolated oracle baseline of the 3D boxes runs on the CPU, labels itself, scales
     by the cell count and combines the per-call costs with the given iteration counts."""
