@@ -1698,47 +1698,62 @@ __global__ void __launch_bounds__(kBlock) k_pbp_rhsT(Grid G, const double* X, co
 template <int ND>
 __global__ void __launch_bounds__(kBlock) k_pbp_out(Grid G, const double* X, const double* v, int scaled,
                                                     double alpha1, double dt, const double* dp,
-                                                    const double* dT, double zs, double* z) {
-  int lin = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-  if (lin >= G.N) return;
-  Pos P = make_pos<ND>(G, lin);
+                                                    const double* dT, double zs, double* z, double alpha2,
+                                                    double* zpart) {
   const double gm1 = G.gamma - 1.0;
   const bool rad = G.a_rad != 0.0;
-  double rho = X[lin], e = X[G.N + lin];
-  double r0, rE;
-  r_cell(G, X, v, scaled, lin, &r0, &rE);
-  const Thermo th = thermo_rt(G, rho, e);
-  const double dpdr = th.dpdr, dpde = th.dpde;
-  double Fp = (dpdr - (e / rho) * dpde) * r0 + (dpde / rho) * rE;
-  double Fe = (rE - e * r0) / rho;
-  double dpc = dp[lin];
-  double de;
-  if (dT) de = rad ? th.cv * dT[lin] : dT[lin] / gm1;  // de = c_v dT
-  else de = dt * Fe + (dpc - dt * Fp) / (th.G1 * rho);
-  z[lin] = zs * ((dpc - dpde * de) / dpdr);
-  z[G.N + lin] = zs * de;
-#pragma unroll
-  for (int d = 0; d < ND; ++d) {
-    double s;
-    int im = gidx<ND>(G, P, 0, shift(off0(), d, -1), &s);
-    double rhom = X[im];
-    double rf = 0.5 * (rhom + rho);
-    double vm = v[(2 + d) * G.N + lin];
-    double rm = vm;
-    double r0m = v[im];
-    double r0c = v[lin];
-    double ud = X[(2 + d) * G.N + lin];
-    if (scaled) {
-      double csf = 0.5 * (sound_speed_rt(G, rhom, X[G.N + im]) + sound_speed_rt(G, rho, e));
-      rm = vm * rf * fmax(fabs(ud), alpha1 * csf);
-      r0m *= rhom;
-      r0c *= rho;
+  double acc = 0.0;  // zpart: sum over the block's cells of (z / R)^2 (R the unknown scaling, alpha2)
+  FOR_CELLS(lin, G.N) {
+    Pos P = make_pos<ND>(G, lin);
+    double rho = X[lin], e = X[G.N + lin];
+    double r0, rE;
+    r_cell(G, X, v, scaled, lin, &r0, &rE);
+    const Thermo th = thermo_rt(G, rho, e);
+    const double dpdr = th.dpdr, dpde = th.dpde;
+    double Fp = (dpdr - (e / rho) * dpde) * r0 + (dpde / rho) * rE;
+    double Fe = (rE - e * r0) / rho;
+    double dpc = dp[lin];
+    double de;
+    if (dT) de = rad ? th.cv * dT[lin] : dT[lin] / gm1;  // de = c_v dT
+    else de = dt * Fe + (dpc - dt * Fp) / (th.G1 * rho);
+    const double z0 = zs * ((dpc - dpde * de) / dpdr), z1 = zs * de;
+    z[lin] = z0;
+    z[G.N + lin] = z1;
+    if (zpart) {
+      const double q0 = z0 / rho, q1 = z1 / e;
+      acc += q0 * q0;
+      acc += q1 * q1;
     }
-    double rbar = 0.5 * (r0m + r0c);
-    double Fu = (rm - ud * rbar) / rf;
-    double grad = (G.bc[d] == 1 && P.c[d] == 0) ? 0.0 : (dpc - dp[im]) / (rf * G.dx[d]);
-    z[(2 + d) * G.N + lin] = zs * (dt * (Fu - grad));
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      double s;
+      int im = gidx<ND>(G, P, 0, shift(off0(), d, -1), &s);
+      double rhom = X[im];
+      double rf = 0.5 * (rhom + rho);
+      double vm = v[(2 + d) * G.N + lin];
+      double rm = vm;
+      double r0m = v[im];
+      double r0c = v[lin];
+      double ud = X[(2 + d) * G.N + lin];
+      double csf = 0.0;
+      if (scaled || zpart) csf = 0.5 * (sound_speed_rt(G, rhom, X[G.N + im]) + sound_speed_rt(G, rho, e));
+      if (scaled) {
+        rm = vm * rf * fmax(fabs(ud), alpha1 * csf);
+        r0m *= rhom;
+        r0c *= rho;
+      }
+      double rbar = 0.5 * (r0m + r0c);
+      double Fu = (rm - ud * rbar) / rf;
+      double grad = (G.bc[d] == 1 && P.c[d] == 0) ? 0.0 : (dpc - dp[im]) / (rf * G.dx[d]);
+      const double zu = zs * (dt * (Fu - grad));
+      z[(2 + d) * G.N + lin] = zu;
+      if (zpart) {
+        const double q = zu / fmax(fabs(ud), alpha2 * csf);
+        acc += q * q;
+      }
+    }
   }
+  if (zpart) block_partial(acc, zpart);
 }
 
 void launch_pbp_in(const Grid& G, const double* X, const double* v, int scaled, double alpha1,
@@ -1755,12 +1770,19 @@ void launch_pbp_rhsT(const Grid& G, const double* X, const double* v, int scaled
   k_pbp_rhsT<<<CELLS(G.N), 0, s>>>(G, X, v, scaled, dt, dp, rhs_T);
 }
 void launch_pbp_out(const Grid& G, const double* X, const double* v, int scaled, double alpha1,
-                    double dt, const double* dp, const double* dT, double zscale, double* z, hipStream_t s) {
+                    double dt, const double* dp, const double* dT, double zscale, double* z, hipStream_t s,
+                    double alpha2, const RedWS* zn2_ws, double* zn2) {
   const double by = 8.0 * G.N * (3.0 * (2 + G.nd) + 1 + (dT ? 1 : 0));
+  double* part = zn2 ? zn2_ws->part : nullptr;
+  // with the norm, one partial per block of a reduction-sized grid
+  const dim3 gr = zn2 ? dim3(red_grid(G.N)) : dim3((G.N + kBlock - 1) / kBlock);
   if (G.nd == 2)
-    launch_k(KF_PBP_OUT, by, k_pbp_out<2>, CELLS(G.N), 0, s, G, X, v, scaled, alpha1, dt, dp, dT, zscale, z);
+    launch_k(KF_PBP_OUT, by, k_pbp_out<2>, gr, dim3(kBlock), 0, s, G, X, v, scaled, alpha1, dt, dp, dT, zscale, z,
+             alpha2, part);
   else
-    launch_k(KF_PBP_OUT, by, k_pbp_out<3>, CELLS(G.N), 0, s, G, X, v, scaled, alpha1, dt, dp, dT, zscale, z);
+    launch_k(KF_PBP_OUT, by, k_pbp_out<3>, gr, dim3(kBlock), 0, s, G, X, v, scaled, alpha1, dt, dp, dT, zscale, z,
+             alpha2, part);
+  if (zn2) launch_finalize_sum(*zn2_ws, red_grid(G.N), 1, zn2, s);
 }
 
 // ---- explicit instantiations ---------------------------------------------------------------

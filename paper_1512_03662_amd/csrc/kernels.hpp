@@ -214,8 +214,11 @@ void launch_pbp_in(const Grid& G, const double* X, const double* v, int scaled, 
                    double dt, int schur, double* rhs_p, hipStream_t s);
 void launch_pbp_rhsT(const Grid& G, const double* X, const double* v, int scaled, double alpha1,
                      double dt, const double* dp, double* rhs_T, hipStream_t s);
+// zn2 (optional): *zn2 = ||R^-1 z||_2^2 with the unknown scaling R (alpha2) of X, reduced
+// through zn2_ws (the scaled norm of the finite-difference step size, computed with z)
 void launch_pbp_out(const Grid& G, const double* X, const double* v, int scaled, double alpha1,
-                    double dt, const double* dp, const double* dT, double zscale, double* z, hipStream_t s);
+                    double dt, const double* dp, const double* dT, double zscale, double* z, hipStream_t s,
+                    double alpha2 = 0.0, const RedWS* zn2_ws = nullptr, double* zn2 = nullptr);
 
 // ---- transposed products (vjp.hip) -----------------------------------------------------
 // out = cU (dU/dX)^T w + cR (dR/dX)^T w at X (optionally each row multiplied by R(X));

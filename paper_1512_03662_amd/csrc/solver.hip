@@ -79,6 +79,7 @@ struct jfnk_ctx {
   CGCtl* ctl = nullptr;    // control block of the running CG solve
   CGCtl* hctl = nullptr;   // pinned host copy
   double* cgpart = nullptr;
+  const double* zn2_of = nullptr;  // the direction whose ||R^-1 z||^2 the preconditioner left in S_ZN2
   int cg_pred[2][2] = {{4, 4}, {4, 4}};  // previous iteration count per operator and precision
   int cg_its = 0;
 
@@ -756,8 +757,9 @@ void ell_solve(jfnk_ctx* c, int o, const double* b, double* x) {
 // scheme is built with tau and its result divided by theta (eq. crank_nicholson).
 double si_dt(const jfnk_ctx* c) { return c->prob.theta * c->dt; }
 
-// Z = M^-1 v (scaled = 1: v is a scaled basis vector, r = L v) at the frozen state X
-void precond(jfnk_ctx* c, const double* X, const double* v, int scaled, double* z) {
+// Z = M^-1 v (scaled = 1: v is a scaled basis vector, r = L v) at the frozen state X;
+// with_norm: also ||R^-1 Z||^2 into S_ZN2 (the finite-difference product's step size)
+void precond(jfnk_ctx* c, const double* X, const double* v, int scaled, double* z, bool with_norm = false) {
   const Grid& G = c->G;
   hipStream_t s = c->stream;
   const jfnk_opts& o = c->opts;
@@ -775,7 +777,9 @@ void precond(jfnk_ctx* c, const double* X, const double* v, int scaled, double* 
     ell_solve(c, 1, c->rhs_T, c->dT);
     dT = c->dT;
   }
-  launch_pbp_out(G, X, v, scaled, o.alpha1, tau, c->dp, dT, 1.0 / c->prob.theta, z, s);
+  launch_pbp_out(G, X, v, scaled, o.alpha1, tau, c->dp, dT, 1.0 / c->prob.theta, z, s, o.alpha2,
+                 with_norm ? &c->red : nullptr, with_norm ? c->scal + S_ZN2 : nullptr);
+  c->zn2_of = with_norm ? z : nullptr;
   check_launch();
 }
 
@@ -822,7 +826,8 @@ void apply_J(jfnk_ctx* c, const double* X, const double* z, double* out) {
   if (c->opts.jv_mode == JFNK_JV_EXACT) {
     launch_resid(G, a, 1, c->stream);
   } else {
-    launch_scaled_norm2(G, X, z, c->opts.alpha2, c->scal + S_ZN2, c->red, c->stream);
+    if (c->zn2_of != z) launch_scaled_norm2(G, X, z, c->opts.alpha2, c->scal + S_ZN2, c->red, c->stream);
+    c->zn2_of = nullptr;
     a.B = c->G0;
     a.fd_norms = c->scal + S_XN2;
     a.fd_lambda = c->opts.fd_lambda;
@@ -907,7 +912,7 @@ GmresOut fgmres(jfnk_ctx* c, const double* X, double beta0, double sign) {
       double* w = c->V + (size_t)(j + 1) * n;
       phase_begin(c);
       if (c->adj) precond_T(c, X, Vj, 1, Zj);
-      else precond(c, X, Vj, 1, Zj);
+      else precond(c, X, Vj, 1, Zj, c->opts.jv_mode == JFNK_JV_FD);
       phase_end(c, PH_PREC);
       phase_begin(c);
       apply_J(c, X, Zj, w);
