@@ -125,14 +125,16 @@ template void launch_dot<float>(size_t, const float*, const float*, double*, con
 // Slots 0..K-2 of V hold the finished orthonormal basis, slot j = K-1 the newest vector q~
 // after one orthogonalisation (normalised by that pass's norm), w the new product.
 // Pass 1: a_i = V_i . q~ and b_i = V_i . w for i <= j (2K sums).
+// qn2 (optional): slot K-1 is kept unnormalised and read as V_{K-1} / sqrt(*qn2)
 template <int K>
 __global__ void __launch_bounds__(kBlock) k_dcgs2_dots(size_t n, const double* V, size_t ld, const double* w,
-                                                       RedWS ws) {
+                                                       const double* qn2, RedWS ws) {
   double acc[2 * K];
 #pragma unroll
   for (int k = 0; k < 2 * K; ++k) acc[k] = 0.0;
+  const double qsc = inv_norm(qn2);
   for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
-    const double qi = V[(K - 1) * ld + i];
+    const double qi = qsc != 0.0 ? mul_nc(V[(K - 1) * ld + i], qsc) : V[(K - 1) * ld + i];
     const double wi = w[i];
 #pragma unroll
     for (int k = 0; k < K - 1; ++k) {
@@ -169,13 +171,15 @@ __device__ __forceinline__ void dcgs2_coef(const double* sums, double* sc, doubl
 // - h_j q, and the partial sums of ||dst||^2.
 template <int K>
 __global__ void __launch_bounds__(kBlock) k_dcgs2_update(size_t n, double* V, size_t ld, const double* sums,
-                                                         const double* w, double* dst, RedWS ws) {
+                                                         const double* w, double* dst, const double* qn2,
+                                                         RedWS ws) {
   constexpr int j = K - 1;
   double sc[K], h[K], inv_nu;
   dcgs2_coef<K>(sums, sc, inv_nu, h);
+  const double qsc = inv_norm(qn2);
   double acc[1] = {0.0};
   for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
-    double q = V[j * ld + i];
+    double q = qsc != 0.0 ? mul_nc(V[j * ld + i], qsc) : V[j * ld + i];
     double wi = w[i];
 #pragma unroll
     for (int k = 0; k < j; ++k) {
@@ -230,22 +234,23 @@ __global__ void __launch_bounds__(kBlock) k_finalize_each(const double* part, in
   if (threadIdx.x == 0) out[blockIdx.x] = v;
 }
 
+// the two Gram-Schmidt passes of one Arnoldi step (K = j + 1 slots), one table entry per K
+using GsFn = void (*)(size_t n, double* V, size_t ld, const double* w, const double* sums, double* dst,
+                      double* out, const double* qn2, const RedWS& ws, hipStream_t s);
 template <int K>
-static void d1_launch(size_t n, const double* V, size_t ld, const double* h, const double* w, double* w_mut,
-                      double* out, const RedWS& ws, hipStream_t s) {
-  (void)h;
-  (void)w_mut;
-  launch_k(KF_GS_DOTS, 8.0 * n * (K + 1), k_dcgs2_dots<K>, dim3(red_blocks(n)), dim3(kBlock), 0, s, n, V, ld,
-           w, ws);
+static void d1_launch(size_t n, double* V, size_t ld, const double* w, const double*, double*, double* out,
+                      const double* qn2, const RedWS& ws, hipStream_t s) {
+  launch_k(KF_GS_DOTS, 8.0 * n * (K + 1), k_dcgs2_dots<K>, dim3(red_blocks(n)), dim3(kBlock), 0, s, n,
+           (const double*)V, ld, w, qn2, ws);
   k_finalize_each<<<2 * K, kBlock, 0, s>>>(ws.part, red_blocks(n), 2 * K, out);
 }
 template <int K>
-static void d2_launch(size_t n, const double* V, size_t ld, const double* sums, const double* w, double* dst,
-                      double* out, const RedWS& ws, hipStream_t s) {
+static void d2_launch(size_t n, double* V, size_t ld, const double* w, const double* sums, double* dst,
+                      double* out, const double* qn2, const RedWS& ws, hipStream_t s) {
   // reads slots 0..j and w; writes slot j (j >= 1) and dst
   const double by = 8.0 * n * (K + 1 + (K > 1 ? 2 : 1));
-  launch_k(KF_GS_UPDATE, by, k_dcgs2_update<K>, dim3(red_blocks(n)), dim3(kBlock), 0, s, n,
-           const_cast<double*>(V), ld, sums, w, dst, ws);
+  launch_k(KF_GS_UPDATE, by, k_dcgs2_update<K>, dim3(red_blocks(n)), dim3(kBlock), 0, s, n, V, ld, sums, w,
+           dst, qn2, ws);
   finalize<OpSum>(ws, red_blocks(n), 1, out, s);
 }
 
@@ -258,18 +263,22 @@ constexpr std::array<MdFn, sizeof...(I)> make_table(std::index_sequence<I...>) {
 template <int K> struct LcT { static void run(size_t n, const double* V, size_t ld, const double* h, const double* w, double* m, double* o, const RedWS& ws, hipStream_t s) { lc_launch<K>(n, V, ld, h, w, m, o, ws, s); } };
 
 static const auto kLc = make_table<LcT>(std::make_index_sequence<kMaxBasis>{});
-template <int K> struct D1T { static void run(size_t n, const double* V, size_t ld, const double* h, const double* w, double* m, double* o, const RedWS& ws, hipStream_t s) { d1_launch<K>(n, V, ld, h, w, m, o, ws, s); } };
-template <int K> struct D2T { static void run(size_t n, const double* V, size_t ld, const double* h, const double* w, double* m, double* o, const RedWS& ws, hipStream_t s) { d2_launch<K>(n, V, ld, h, w, m, o, ws, s); } };
-static const auto kD1 = make_table<D1T>(std::make_index_sequence<kMaxBasis - 1>{});
-static const auto kD2 = make_table<D2T>(std::make_index_sequence<kMaxBasis - 1>{});
+template <int K> struct D1T { static constexpr GsFn run = &d1_launch<K>; };
+template <int K> struct D2T { static constexpr GsFn run = &d2_launch<K>; };
+template <template <int> class F, size_t... I>
+constexpr std::array<GsFn, sizeof...(I)> make_gs_table(std::index_sequence<I...>) {
+  return {{F<(int)I + 1>::run...}};
+}
+static const auto kD1 = make_gs_table<D1T>(std::make_index_sequence<kMaxBasis - 1>{});
+static const auto kD2 = make_gs_table<D2T>(std::make_index_sequence<kMaxBasis - 1>{});
 
 void launch_dcgs2_dots(size_t n, const double* V, size_t ld, int K, const double* w, double* sums,
-                       const RedWS& ws, hipStream_t s) {
-  kD1[K - 1](n, V, ld, nullptr, w, nullptr, sums, ws, s);
+                       const RedWS& ws, hipStream_t s, const double* qn2) {
+  kD1[K - 1](n, const_cast<double*>(V), ld, w, nullptr, nullptr, sums, qn2, ws, s);
 }
 void launch_dcgs2_update(size_t n, double* V, size_t ld, int K, const double* sums, const double* w, double* dst,
-                         double* nrm2, const RedWS& ws, hipStream_t s) {
-  kD2[K - 1](n, V, ld, sums, w, dst, nrm2, ws, s);
+                         double* nrm2, const RedWS& ws, hipStream_t s, const double* qn2) {
+  kD2[K - 1](n, V, ld, w, sums, dst, nrm2, qn2, ws, s);
 }
 
 void launch_lincomb(size_t n, const double* Z, size_t ld, int K, const double* y, double* dst,

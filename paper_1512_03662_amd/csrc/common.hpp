@@ -179,6 +179,19 @@ __device__ __forceinline__ double sound_speed_rt(const Grid& G, double rho, doub
   return G.a_rad == 0.0 ? sound_speed<false>(G, rho, e) : sound_speed<true>(G, rho, e);
 }
 
+// a * b rounded once and never fused into a neighbouring add (bit for bit the product a
+// kernel would have stored); used where a vector is read scaled instead of being stored so
+__device__ __forceinline__ double mul_nc(double a, double b) {
+#pragma clang fp contract(off)
+  return a * b;
+}
+// element i of a basis vector that is kept unnormalised: v[i] / ||v|| read as the product with
+// sc = 1 / sqrt(||v||^2) (as the normalising kernel forms it), or v[i] when sc = 0
+__device__ __forceinline__ double vread(const double* v, int i, double sc) {
+  return sc != 0.0 ? mul_nc(v[i], sc) : v[i];
+}
+__device__ __forceinline__ double inv_norm(const double* nrm2) { return nrm2 ? 1.0 / sqrt(*nrm2) : 0.0; }
+
 // Reciprocal by the hardware estimate refined with two Newton steps (relative error within
 // a few ulp; operands here are far from the overflow and denormal ranges).
 __device__ __forceinline__ double rcp_nr(double d) {

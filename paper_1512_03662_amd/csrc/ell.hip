@@ -1616,8 +1616,8 @@ void launch_uncast_scale_f64(size_t n, const float* src, const double* nrm2, dou
 // ---- transforms of the preconditioner -----------------------------------------------------
 // residual r of the cell (r = L v when scaled); only rho and E rows are needed here
 __device__ __forceinline__ void r_cell(const Grid& G, const double* X, const double* v, int scaled,
-                                       int lin, double* rr, double* rE) {
-  double vr = v[lin], vE = v[G.N + lin];
+                                       int lin, double* rr, double* rE, double vsc = 0.0) {
+  double vr = vread(v, lin, vsc), vE = vread(v, G.N + lin, vsc);
   if (scaled) {
     double rho = X[lin], e = X[G.N + lin];
     vr *= rho;
@@ -1630,11 +1630,11 @@ __device__ __forceinline__ void r_cell(const Grid& G, const double* X, const dou
 // F~_u on the low-d face of cell lf (lower cell lm): (r_m - u_d rbar_rho)/rho_f, r = L v when
 // scaled
 __device__ __forceinline__ double fu_face(const Grid& G, const double* X, const double* v, int scaled,
-                                          double alpha1, int d, int lf, int lm) {
+                                          double alpha1, int d, int lf, int lm, double vsc = 0.0) {
   const double rho = X[lf], rhom = X[lm];
   const double rf = 0.5 * (rhom + rho);
   const double ud = X[(2 + d) * G.N + lf];
-  double rm = v[(2 + d) * G.N + lf], r0m = v[lm], r0c = v[lf];
+  double rm = vread(v, (2 + d) * G.N + lf, vsc), r0m = vread(v, lm, vsc), r0c = vread(v, lf, vsc);
   if (scaled) {
     const double csf = 0.5 * (sound_speed_rt(G, rhom, X[G.N + lm]) + sound_speed_rt(G, rho, X[G.N + lf]));
     rm *= rf * fmax(fabs(ud), alpha1 * csf);
@@ -1647,12 +1647,14 @@ __device__ __forceinline__ double fu_face(const Grid& G, const double* X, const 
 // rhs_p = F_p/(Gamma1 p); schur: minus dt div F~_u (wall faces carry no F~_u)
 template <int ND>
 __global__ void __launch_bounds__(kBlock) k_pbp_in(Grid G, const double* X, const double* v, int scaled,
-                                                   double alpha1, double dt, int schur, double* rhs_p) {
+                                                   double alpha1, double dt, int schur, double* rhs_p,
+                                                   const double* vn2) {
   int lin = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (lin >= G.N) return;
+  const double vsc = inv_norm(vn2);
   double rho = X[lin], e = X[G.N + lin];
   double r0, rE;
-  r_cell(G, X, v, scaled, lin, &r0, &rE);
+  r_cell(G, X, v, scaled, lin, &r0, &rE, vsc);
   const Thermo th = thermo_rt(G, rho, e);
   const double dpdr = th.dpdr, dpde = th.dpde;
   double Fp = (dpdr - (e / rho) * dpde) * r0 + (dpde / rho) * rE;
@@ -1667,12 +1669,12 @@ __global__ void __launch_bounds__(kBlock) k_pbp_in(Grid G, const double* X, cons
       if (!(G.bc[d] == 1 && P.c[d] == 0)) {
         double s;
         const int im = gidx<ND>(G, P, 0, shift(off0(), d, -1), &s);
-        flo = fu_face(G, X, v, scaled, alpha1, d, lin, im);
+        flo = fu_face(G, X, v, scaled, alpha1, d, lin, im, vsc);
       }
       const bool top = (P.c[d] == G.n[d] - 1);
       if (!(G.bc[d] == 1 && top)) {
         const int ip = top ? lin - (G.n[d] - 1) * G.stride[d] : lin + G.stride[d];
-        fhi = fu_face(G, X, v, scaled, alpha1, d, ip, lin);
+        fhi = fu_face(G, X, v, scaled, alpha1, d, ip, lin, vsc);
       }
       div += (fhi - flo) * G.idx[d];
     }
@@ -1682,12 +1684,13 @@ __global__ void __launch_bounds__(kBlock) k_pbp_in(Grid G, const double* X, cons
 }
 
 __global__ void __launch_bounds__(kBlock) k_pbp_rhsT(Grid G, const double* X, const double* v, int scaled,
-                                                     double dt, const double* dp, double* rhs_T) {
+                                                     double dt, const double* dp, double* rhs_T, const double* vn2) {
   int lin = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (lin >= G.N) return;
+  const double vsc = inv_norm(vn2);
   double rho = X[lin], e = X[G.N + lin];
   double r0, rE;
-  r_cell(G, X, v, scaled, lin, &r0, &rE);
+  r_cell(G, X, v, scaled, lin, &r0, &rE, vsc);
   const Thermo th = thermo_rt(G, rho, e);
   const double dpdr = th.dpdr, dpde = th.dpde;
   double Fp = (dpdr - (e / rho) * dpde) * r0 + (dpde / rho) * rE;
@@ -1699,15 +1702,16 @@ template <int ND>
 __global__ void __launch_bounds__(kBlock) k_pbp_out(Grid G, const double* X, const double* v, int scaled,
                                                     double alpha1, double dt, const double* dp,
                                                     const double* dT, double zs, double* z, double alpha2,
-                                                    double* zpart) {
+                                                    double* zpart, const double* vn2) {
   const double gm1 = G.gamma - 1.0;
+  const double vsc = inv_norm(vn2);
   const bool rad = G.a_rad != 0.0;
   double acc = 0.0;  // zpart: sum over the block's cells of (z / R)^2 (R the unknown scaling, alpha2)
   FOR_CELLS(lin, G.N) {
     Pos P = make_pos<ND>(G, lin);
     double rho = X[lin], e = X[G.N + lin];
     double r0, rE;
-    r_cell(G, X, v, scaled, lin, &r0, &rE);
+    r_cell(G, X, v, scaled, lin, &r0, &rE, vsc);
     const Thermo th = thermo_rt(G, rho, e);
     const double dpdr = th.dpdr, dpde = th.dpde;
     double Fp = (dpdr - (e / rho) * dpde) * r0 + (dpde / rho) * rE;
@@ -1730,10 +1734,10 @@ __global__ void __launch_bounds__(kBlock) k_pbp_out(Grid G, const double* X, con
       int im = gidx<ND>(G, P, 0, shift(off0(), d, -1), &s);
       double rhom = X[im];
       double rf = 0.5 * (rhom + rho);
-      double vm = v[(2 + d) * G.N + lin];
+      double vm = vread(v, (2 + d) * G.N + lin, vsc);
       double rm = vm;
-      double r0m = v[im];
-      double r0c = v[lin];
+      double r0m = vread(v, im, vsc);
+      double r0c = vread(v, lin, vsc);
       double ud = X[(2 + d) * G.N + lin];
       double csf = 0.0;
       if (scaled || zpart) csf = 0.5 * (sound_speed_rt(G, rhom, X[G.N + im]) + sound_speed_rt(G, rho, e));
@@ -1757,31 +1761,31 @@ __global__ void __launch_bounds__(kBlock) k_pbp_out(Grid G, const double* X, con
 }
 
 void launch_pbp_in(const Grid& G, const double* X, const double* v, int scaled, double alpha1,
-                   double dt, int schur, double* rhs_p, hipStream_t s) {
+                   double dt, int schur, double* rhs_p, hipStream_t s, const double* vn2) {
   const double by = 8.0 * G.N * (schur ? 2.0 * (2 + G.nd) + 1 : 5.0);
   if (G.nd == 2)
-    launch_k(KF_PBP_IN, by, k_pbp_in<2>, CELLS(G.N), 0, s, G, X, v, scaled, alpha1, dt, schur, rhs_p);
+    launch_k(KF_PBP_IN, by, k_pbp_in<2>, CELLS(G.N), 0, s, G, X, v, scaled, alpha1, dt, schur, rhs_p, vn2);
   else
-    launch_k(KF_PBP_IN, by, k_pbp_in<3>, CELLS(G.N), 0, s, G, X, v, scaled, alpha1, dt, schur, rhs_p);
+    launch_k(KF_PBP_IN, by, k_pbp_in<3>, CELLS(G.N), 0, s, G, X, v, scaled, alpha1, dt, schur, rhs_p, vn2);
 }
 void launch_pbp_rhsT(const Grid& G, const double* X, const double* v, int scaled, double alpha1,
-                     double dt, const double* dp, double* rhs_T, hipStream_t s) {
+                     double dt, const double* dp, double* rhs_T, hipStream_t s, const double* vn2) {
   (void)alpha1;
-  k_pbp_rhsT<<<CELLS(G.N), 0, s>>>(G, X, v, scaled, dt, dp, rhs_T);
+  k_pbp_rhsT<<<CELLS(G.N), 0, s>>>(G, X, v, scaled, dt, dp, rhs_T, vn2);
 }
 void launch_pbp_out(const Grid& G, const double* X, const double* v, int scaled, double alpha1,
                     double dt, const double* dp, const double* dT, double zscale, double* z, hipStream_t s,
-                    double alpha2, const RedWS* zn2_ws, double* zn2) {
+                    double alpha2, const RedWS* zn2_ws, double* zn2, const double* vn2) {
   const double by = 8.0 * G.N * (3.0 * (2 + G.nd) + 1 + (dT ? 1 : 0));
   double* part = zn2 ? zn2_ws->part : nullptr;
   // with the norm, one partial per block of a reduction-sized grid
   const dim3 gr = zn2 ? dim3(red_grid(G.N)) : dim3((G.N + kBlock - 1) / kBlock);
   if (G.nd == 2)
     launch_k(KF_PBP_OUT, by, k_pbp_out<2>, gr, dim3(kBlock), 0, s, G, X, v, scaled, alpha1, dt, dp, dT, zscale, z,
-             alpha2, part);
+             alpha2, part, vn2);
   else
     launch_k(KF_PBP_OUT, by, k_pbp_out<3>, gr, dim3(kBlock), 0, s, G, X, v, scaled, alpha1, dt, dp, dT, zscale, z,
-             alpha2, part);
+             alpha2, part, vn2);
   if (zn2) launch_finalize_sum(*zn2_ws, red_grid(G.N), 1, zn2, s);
 }
 

@@ -46,11 +46,13 @@ void launch_dot(size_t n, const T* a, const T* b, double* out, const RedWS& w, h
 // K-1 the newest vector after one pass, w the new product):
 // sums[k] = V_k . V_{K-1}, sums[K + k] = V_k . w for k < K
 void launch_dcgs2_dots(size_t n, const double* V, size_t ld, int K, const double* w, double* sums,
-                       const RedWS& ws, hipStream_t s);
+                       const RedWS& ws, hipStream_t s, const double* qn2 = nullptr);
 // slot K-1 reorthogonalised and renormalised (K >= 2), dst = w orthogonalised against slots
 // 0..K-1, *nrm2 = ||dst||^2 (coefficients formed on the device from sums)
 void launch_dcgs2_update(size_t n, double* V, size_t ld, int K, const double* sums, const double* w, double* dst,
-                         double* nrm2, const RedWS& ws, hipStream_t s);
+                         double* nrm2, const RedWS& ws, hipStream_t s, const double* qn2 = nullptr);
+// (qn2: slot K-1 is kept unnormalised and read as V_{K-1} / sqrt(*qn2); the update pass writes
+// it back normalised)
 // dst = src / sqrt(*nrm2)
 void launch_scale_by_inv_sqrt(size_t n, const double* src, const double* nrm2, double* dst,
                               hipStream_t s);
@@ -211,14 +213,19 @@ void launch_uncast_scale_f64(size_t n, const float* src, const double* nrm2, dou
 // z = zscale dX from dp (and dT).  scaled != 0: the input is v with r = L v.  For a
 // theta-weighted step dt is the implicit step theta dt and zscale = 1/theta.
 void launch_pbp_in(const Grid& G, const double* X, const double* v, int scaled, double alpha1,
-                   double dt, int schur, double* rhs_p, hipStream_t s);
+                   double dt, int schur, double* rhs_p, hipStream_t s,
+                   const double* vn2 = nullptr);
 void launch_pbp_rhsT(const Grid& G, const double* X, const double* v, int scaled, double alpha1,
-                     double dt, const double* dp, double* rhs_T, hipStream_t s);
+                     double dt, const double* dp, double* rhs_T, hipStream_t s,
+                     const double* vn2 = nullptr);
+// vn2 (optional, also for pbp_in and pbp_rhsT): v is read as v / sqrt(*vn2), an Arnoldi vector
+// kept unnormalised.
 // zn2 (optional): *zn2 = ||R^-1 z||_2^2 with the unknown scaling R (alpha2) of X, reduced
 // through zn2_ws (the scaled norm of the finite-difference step size, computed with z)
 void launch_pbp_out(const Grid& G, const double* X, const double* v, int scaled, double alpha1,
                     double dt, const double* dp, const double* dT, double zscale, double* z, hipStream_t s,
-                    double alpha2 = 0.0, const RedWS* zn2_ws = nullptr, double* zn2 = nullptr);
+                    double alpha2 = 0.0, const RedWS* zn2_ws = nullptr, double* zn2 = nullptr,
+                    const double* vn2 = nullptr);
 
 // ---- transposed products (vjp.hip) -----------------------------------------------------
 // out = cU (dU/dX)^T w + cR (dR/dX)^T w at X (optionally each row multiplied by R(X));

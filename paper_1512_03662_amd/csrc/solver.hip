@@ -759,7 +759,9 @@ double si_dt(const jfnk_ctx* c) { return c->prob.theta * c->dt; }
 
 // Z = M^-1 v (scaled = 1: v is a scaled basis vector, r = L v) at the frozen state X;
 // with_norm: also ||R^-1 Z||^2 into S_ZN2 (the finite-difference product's step size)
-void precond(jfnk_ctx* c, const double* X, const double* v, int scaled, double* z, bool with_norm = false) {
+// vn2: v is an Arnoldi vector kept unnormalised, read as v / sqrt(*vn2)
+void precond(jfnk_ctx* c, const double* X, const double* v, int scaled, double* z, bool with_norm = false,
+             const double* vn2 = nullptr) {
   const Grid& G = c->G;
   hipStream_t s = c->stream;
   const jfnk_opts& o = c->opts;
@@ -769,16 +771,16 @@ void precond(jfnk_ctx* c, const double* X, const double* v, int scaled, double* 
     return;
   }
   const double tau = si_dt(c);
-  launch_pbp_in(G, X, v, scaled, o.alpha1, tau, o.pc_schur, c->rhs_p, s);
+  launch_pbp_in(G, X, v, scaled, o.alpha1, tau, o.pc_schur, c->rhs_p, s, vn2);
   ell_solve(c, 0, c->rhs_p, c->dp);
   const double* dT = nullptr;
   if (o.precond == JFNK_PC_SOUND_THERMAL) {
-    launch_pbp_rhsT(G, X, v, scaled, o.alpha1, tau, c->dp, c->rhs_T, s);
+    launch_pbp_rhsT(G, X, v, scaled, o.alpha1, tau, c->dp, c->rhs_T, s, vn2);
     ell_solve(c, 1, c->rhs_T, c->dT);
     dT = c->dT;
   }
   launch_pbp_out(G, X, v, scaled, o.alpha1, tau, c->dp, dT, 1.0 / c->prob.theta, z, s, o.alpha2,
-                 with_norm ? &c->red : nullptr, with_norm ? c->scal + S_ZN2 : nullptr);
+                 with_norm ? &c->red : nullptr, with_norm ? c->scal + S_ZN2 : nullptr, vn2);
   c->zn2_of = with_norm ? z : nullptr;
   check_launch();
 }
@@ -904,6 +906,11 @@ GmresOut fgmres(jfnk_ctx* c, const double* X, double beta0, double sign) {
     // V_j and its Givens rotation recomputed; the residual estimate of step j uses the
     // once-orthogonalised norm of w (the correction is of the order of rounding).
     double hprev = 0.0;                // norm of w of step j - 1 (V_j = w / hprev)
+    // With the physics-based preconditioner on the forward system, V_{j+1} is left as w and read
+    // as w / ||w|| by its consumers (the preconditioner's input kernels and the next step's two
+    // passes, which store it normalised): one pass over the vector fewer per step, same numbers
+    const bool keep_raw = !c->adj && o.precond != JFNK_PC_NONE;
+    const double* vn2 = nullptr;       // slot j unnormalised: its squared norm
     std::vector<double> hcol(m + 1);   // unrotated column j - 1
     double gsave = 0.0;                // g[j - 1] before the provisional rotation j - 1
     for (int j = 0; j < m; ++j) {
@@ -912,15 +919,16 @@ GmresOut fgmres(jfnk_ctx* c, const double* X, double beta0, double sign) {
       double* w = c->V + (size_t)(j + 1) * n;
       phase_begin(c);
       if (c->adj) precond_T(c, X, Vj, 1, Zj);
-      else precond(c, X, Vj, 1, Zj, c->opts.jv_mode == JFNK_JV_FD);
+      else precond(c, X, Vj, 1, Zj, c->opts.jv_mode == JFNK_JV_FD, vn2);
       phase_end(c, PH_PREC);
       phase_begin(c);
       apply_J(c, X, Zj, w);
       phase_end(c, PH_JV);
       const int K = j + 1;
       phase_begin(c);
-      launch_dcgs2_dots(n, c->V, n, K, w, c->scal + S_H1, c->red, s);
-      launch_dcgs2_update(n, c->V, n, K, c->scal + S_H1, w, w, c->scal + S_NRM3, c->red, s);
+      launch_dcgs2_dots(n, c->V, n, K, w, c->scal + S_H1, c->red, s, vn2);
+      launch_dcgs2_update(n, c->V, n, K, c->scal + S_H1, w, w, c->scal + S_NRM3, c->red, s, vn2);
+      vn2 = nullptr;
       phase_end(c, PH_ORTH);
       pull(c, S_H1, S_NRM3 + 1 - S_H1);
       const double* sums = c->hscal + S_H1;
@@ -959,9 +967,13 @@ GmresOut fgmres(jfnk_ctx* c, const double* X, double beta0, double sign) {
       for (int i = 0; i <= j + 1; ++i) Hx(i, j) = hcol[i];
       hprev = hn;
       if (hn > 0.0) {
-        phase_begin(c);
-        launch_scale_by_inv_sqrt(n, w, c->scal + S_NRM3, w, s);
-        phase_end(c, PH_ORTH);
+        if (keep_raw) {
+          vn2 = c->scal + S_NRM3;
+        } else {
+          phase_begin(c);
+          launch_scale_by_inv_sqrt(n, w, c->scal + S_NRM3, w, s);
+          phase_end(c, PH_ORTH);
+        }
       }
       for (int i = 0; i < j; ++i) {
         double t = cs[i] * Hx(i, j) + sn[i] * Hx(i + 1, j);
