@@ -440,7 +440,9 @@ __global__ void __launch_bounds__(kBlock) k_mg_smooth2(LV<T> L, const T* b, cons
 
 // ---- z-marching forms of the single-level kernels on 3D grids ---------------------------
 // A block owns kZX x kZY columns of cells (x contiguous) and walks them along z through a
-// chunk of planes.  The state a cell's stencil needs from its z neighbours is carried in
+// chunk of planes.  Fields that a kernel reads or writes once per cell (right-hand sides,
+// diagonals, smoother corrections, CG updates) go through non-temporal loads and stores, so
+// that they do not displace the stencil operand's neighbouring rows from the caches.  The state a cell's stencil needs from its z neighbours is carried in
 // registers from one plane to the next, so no plane is fetched a second time for the z+1 or
 // z-1 neighbour of another cell (the grid-stride forms read those planes again, from another
 // XCD's L2 or from memory).  Except for the restriction, which has a grid of its own, a
@@ -488,7 +490,7 @@ __device__ __forceinline__ void zmarch(const LV<T>& L, const ZChunk& zc, const S
     const auto sn = st(ln, zc.cx, zc.cy, zn);
     const T w2n = L.w[2][ln];
     const T pc = val(sc);
-    T out = L.diag[lin] * pc;
+    T out = __builtin_nontemporal_load(&L.diag[lin]) * pc;
 #pragma unroll
     for (int d = 0; d < 2; ++d) {
       const int n = L.n[d], s = L.stride[d];
@@ -543,9 +545,9 @@ __global__ void __launch_bounds__(kBlock) k_cg_update_zm(LV<T> L, const T* rold,
   auto val = [](const UpdSt<T>& u) { return u.x1; };
   T acc = T(0);
   auto emit = [&](int lin, int, const UpdSt<T>& u, T Ax) {
-    const T xo = (it == 1) ? T(0) : x[lin];
-    x[lin] = xo + al * p[lin];
-    rnew[lin] = u.r;
+    const T xo = (it == 1) ? T(0) : __builtin_nontemporal_load(&x[lin]);
+    __builtin_nontemporal_store(xo + al * __builtin_nontemporal_load(&p[lin]), &x[lin]);
+    __builtin_nontemporal_store(u.r, &rnew[lin]);
     acc += u.r * u.r;
     xm[lin] = (T(1.0) + T(kChebC1)) * u.x1 + T(kChebC2) * u.dv * (u.r - Ax);
   };
@@ -579,8 +581,8 @@ __global__ void __launch_bounds__(kBlock) k_cg_apply_zm(LV<T> L, const T* z, con
   auto val = [](T v) { return v; };
   T acc = T(0);
   auto emit = [&](int lin, int, T pc, T qv) {
-    pnew[lin] = pc;
-    q[lin] = qv;
+    __builtin_nontemporal_store(pc, &pnew[lin]);
+    __builtin_nontemporal_store(qv, &q[lin]);
     acc += pc * qv;
   };
   zmarch<T>(L, zchunk(L.n, zc), st, val, emit);
@@ -630,10 +632,11 @@ __global__ void __launch_bounds__(kBlock) k_mg_smooth2_zm(LV<T> L, const T* b, c
   auto val = [](T v) { return v; };
   T acc = T(0);
   auto emit = [&](int lin, int, T x1c, T Ax) {
-    const T r1 = b[lin] - Ax;
-    const T xn = x1c + T(kChebC1) * d0[lin] + T(kChebC2) * L.dinv[lin] * r1;
-    x[lin] = xn;
-    if (RZ) acc += b[lin] * xn;
+    const T bl = __builtin_nontemporal_load(&b[lin]);
+    const T r1 = bl - Ax;
+    const T xn = x1c + T(kChebC1) * __builtin_nontemporal_load(&d0[lin]) + T(kChebC2) * __builtin_nontemporal_load(&L.dinv[lin]) * r1;
+    __builtin_nontemporal_store(xn, &x[lin]);
+    if (RZ) acc += bl * xn;
   };
   zmarch<T>(L, zchunk(L.n, zc), st, val, emit);
   if (RZ) block_partial((double)acc, g.part + kPartRZ * kRedBlocks);
@@ -650,10 +653,10 @@ __global__ void __launch_bounds__(kBlock) k_mg_prolong_smooth1_zm(LV<T> L, const
   };
   auto val = [](T v) { return v; };
   auto emit = [&](int lin, int, T xpc, T Ax) {
-    const T r0 = b[lin] - Ax;
-    const T dd = L.dinv[lin] * r0 * T(1.0 / kChebTheta);
+    const T r0 = __builtin_nontemporal_load(&b[lin]) - Ax;
+    const T dd = __builtin_nontemporal_load(&L.dinv[lin]) * r0 * T(1.0 / kChebTheta);
     x1[lin] = xpc + dd;
-    d0[lin] = dd;
+    __builtin_nontemporal_store(dd, &d0[lin]);
   };
   zmarch<T>(L, zchunk(L.n, zc), st, val, emit);
 }
@@ -734,7 +737,7 @@ __global__ void __launch_bounds__(kBlock) k_mg_restrict_resid_zm(LV<T> L, const 
       const T wl = k ? wC[q] : wB[q];
       const T wu = k ? ((L.bc[2] == 1 && f1 == nz - 1) ? T(0) : wD[q]) : wC[q];
       out -= wu * (zp - xc) - wl * (xc - zm);
-      sum += b[fl] - out;
+      sum += __builtin_nontemporal_load(&b[fl]) - out;
     }
     bc[ccx + ccy * ncx + cz * ncx * ncy] = sum * T(1.0 / 8);
 #pragma unroll
@@ -1479,8 +1482,8 @@ __global__ void __launch_bounds__(kBlock) k_cg_apply(LV<T> L, const T* z, const 
     coords<ND>(L.n, lin, c);
     const T pc = pf(lin);
     const T qv = apply_at<T, ND>(L, c, lin, pf, pc);
-    pnew[lin] = pc;
-    q[lin] = qv;
+    __builtin_nontemporal_store(pc, &pnew[lin]);
+    __builtin_nontemporal_store(qv, &q[lin]);
     acc += pc * qv;
   }
   block_partial((double)acc, g.part + kPartPQ * kRedBlocks);
