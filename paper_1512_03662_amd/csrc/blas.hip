@@ -122,6 +122,7 @@ template void launch_dot<double>(size_t, const double*, const double*, double*, 
 template void launch_dot<float>(size_t, const float*, const float*, double*, const RedWS&, hipStream_t);
 
 // ---- Gram-Schmidt with delayed reorthogonalisation (two passes per Arnoldi step) ----------
+// Each pass streams the basis once: its loads and stores are non-temporal.
 // Slots 0..K-2 of V hold the finished orthonormal basis, slot j = K-1 the newest vector q~
 // after one orthogonalisation (normalised by that pass's norm), w the new product.
 // Pass 1: a_i = V_i . q~ and b_i = V_i . w for i <= j (2K sums).
@@ -134,11 +135,12 @@ __global__ void __launch_bounds__(kBlock) k_dcgs2_dots(size_t n, const double* V
   for (int k = 0; k < 2 * K; ++k) acc[k] = 0.0;
   const double qsc = inv_norm(qn2);
   for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
-    const double qi = qsc != 0.0 ? mul_nc(V[(K - 1) * ld + i], qsc) : V[(K - 1) * ld + i];
-    const double wi = w[i];
+    const double qr = __builtin_nontemporal_load(&V[(K - 1) * ld + i]);
+    const double qi = qsc != 0.0 ? mul_nc(qr, qsc) : qr;
+    const double wi = __builtin_nontemporal_load(&w[i]);
 #pragma unroll
     for (int k = 0; k < K - 1; ++k) {
-      const double v = V[k * ld + i];
+      const double v = __builtin_nontemporal_load(&V[k * ld + i]);
       acc[k] += v * qi;
       acc[K + k] += v * wi;
     }
@@ -179,20 +181,21 @@ __global__ void __launch_bounds__(kBlock) k_dcgs2_update(size_t n, double* V, si
   const double qsc = inv_norm(qn2);
   double acc[1] = {0.0};
   for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
-    double q = qsc != 0.0 ? mul_nc(V[j * ld + i], qsc) : V[j * ld + i];
-    double wi = w[i];
+    const double qr = __builtin_nontemporal_load(&V[j * ld + i]);
+    double q = qsc != 0.0 ? mul_nc(qr, qsc) : qr;
+    double wi = __builtin_nontemporal_load(&w[i]);
 #pragma unroll
     for (int k = 0; k < j; ++k) {
-      const double v = V[k * ld + i];
+      const double v = __builtin_nontemporal_load(&V[k * ld + i]);
       q -= sc[k] * v;
       wi -= h[k] * v;
     }
     if (j > 0) {
       q *= inv_nu;
-      V[j * ld + i] = q;
+      __builtin_nontemporal_store(q, &V[j * ld + i]);
     }
     wi -= h[j] * q;
-    dst[i] = wi;
+    __builtin_nontemporal_store(wi, &dst[i]);
     acc[0] += wi * wi;
   }
   block_finish<OpSum, 1>(acc, nullptr, ws);
