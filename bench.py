@@ -142,7 +142,7 @@ def rel_diff_per_var(A, B):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: the library runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU domain decomposition is a design, not an implementation.",
               file=sys.stderr)
         sys.exit(2)
