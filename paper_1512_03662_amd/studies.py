@@ -1,6 +1,6 @@
 """Iteration-count studies of the paper's test problems, run with this library.
 
-    python -m paper_1512_03662_amd.studies tgv [--steps 10]
+    python -m paper_1512_03662_amd.studies tgv [--steps 10] [--newton-tol 1e-6]
     python -m paper_1512_03662_amd.studies vortex [--steps 5]
     python -m paper_1512_03662_amd.studies si_vortex [--schemes si_schur,jfnk_be]
     python -m paper_1512_03662_amd.studies eta [--steps 10]
@@ -90,10 +90,11 @@ def tgv(args):
         # the finite-difference product limits the linear solves there (Sect. 5.1.1)
         forms = ("fd", "exact") if cfl > 1e5 else ("fd",)
         for jv in forms:
-            ctx = J.Context(w["problem"], precond="sound", jv_mode=jv)
+            ctx = J.Context(w["problem"], precond="sound", jv_mode=jv, newton_tol=args.newton_tol)
             r = _run(ctx, X0, cfl, args.steps, torch)
             ctx.close()
             r.update({"study": "taylor_green_3d_64^3", "mach": mach, "cfl_hydro": cfl, "jv": jv,
+                      "newton_tol": args.newton_tol,
                       "paper": {"cfl_adv": cfl_adv, "newton_per_step": pn, "gmres_per_newton": pg,
                                 "parabolic_per_gmres": pp}})
             print(json.dumps(r), flush=True)
@@ -220,6 +221,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("study", choices=["tgv", "vortex", "si_vortex", "eta"])
     ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--newton-tol", type=float, default=1e-8,
+                    help="tgv: Newton tolerance on ||R^-1 dX||_inf (the paper's runs used 1e-6)")
     ap.add_argument("--schemes", default=",".join(SI_SCHEMES),
                     help="si_vortex: comma-separated subset of " + ",".join(SI_SCHEMES))
     ap.add_argument("--t-end", type=float, default=0.4,
