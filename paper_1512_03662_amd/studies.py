@@ -1,6 +1,6 @@
 """Iteration-count studies of the paper's test problems, run with this library.
 
-    python -m paper_1512_03662_amd.studies tgv [--steps 10] [--newton-tol 1e-6]
+    python -m paper_1512_03662_amd.studies tgv [--steps 10] [--newton-tol 1e-6] [--jv exact]
     python -m paper_1512_03662_amd.studies vortex [--steps 5]
     python -m paper_1512_03662_amd.studies si_vortex [--schemes si_schur,jfnk_be]
     python -m paper_1512_03662_amd.studies eta [--steps 10]
@@ -89,6 +89,8 @@ def tgv(args):
         # the hardest row (Mach 1e-6 at CFL_adv 0.49) also with the exact forward-mode J.v:
         # the finite-difference product limits the linear solves there (Sect. 5.1.1)
         forms = ("fd", "exact") if cfl > 1e5 else ("fd",)
+        if args.jv != "fd":
+            forms = (args.jv,)
         for jv in forms:
             ctx = J.Context(w["problem"], precond="sound", jv_mode=jv, newton_tol=args.newton_tol)
             r = _run(ctx, X0, cfl, args.steps, torch)
@@ -221,6 +223,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("study", choices=["tgv", "vortex", "si_vortex", "eta"])
     ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--jv", choices=["fd", "exact"], default="fd",
+                    help="tgv: J.v form of every row (fd: also the exact form on the hardest row)")
     ap.add_argument("--newton-tol", type=float, default=1e-8,
                     help="tgv: Newton tolerance on ||R^-1 dX||_inf (the paper's runs used 1e-6)")
     ap.add_argument("--schemes", default=",".join(SI_SCHEMES),
