@@ -127,6 +127,9 @@ template void launch_dot<float>(size_t, const float*, const float*, double*, con
 // after one orthogonalisation (normalised by that pass's norm), w the new product.
 // Pass 1: a_i = V_i . q~ and b_i = V_i . w for i <= j (2K sums).
 // qn2 (optional): slot K-1 is kept unnormalised and read as V_{K-1} / sqrt(*qn2)
+// The K + 1 loads of an element are all issued before its first product (a scheduling
+// barrier keeps them together): left to itself the compiler interleaves them with the
+// products for some K, down to one load in flight per wave.
 template <int K>
 __global__ void __launch_bounds__(kBlock) k_dcgs2_dots(size_t n, const double* V, size_t ld, const double* w,
                                                        const double* qn2, RedWS ws) {
@@ -135,14 +138,16 @@ __global__ void __launch_bounds__(kBlock) k_dcgs2_dots(size_t n, const double* V
   for (int k = 0; k < 2 * K; ++k) acc[k] = 0.0;
   const double qsc = inv_norm(qn2);
   for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
-    const double qr = __builtin_nontemporal_load(&V[(K - 1) * ld + i]);
-    const double qi = qsc != 0.0 ? mul_nc(qr, qsc) : qr;
+    double v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = __builtin_nontemporal_load(&V[k * ld + i]);
     const double wi = __builtin_nontemporal_load(&w[i]);
+    __builtin_amdgcn_sched_barrier(0);
+    const double qi = qsc != 0.0 ? mul_nc(v[K - 1], qsc) : v[K - 1];
 #pragma unroll
     for (int k = 0; k < K - 1; ++k) {
-      const double v = __builtin_nontemporal_load(&V[k * ld + i]);
-      acc[k] += v * qi;
-      acc[K + k] += v * wi;
+      acc[k] += v[k] * qi;
+      acc[K + k] += v[k] * wi;
     }
     acc[K - 1] += qi * qi;
     acc[2 * K - 1] += qi * wi;
@@ -181,14 +186,16 @@ __global__ void __launch_bounds__(kBlock) k_dcgs2_update(size_t n, double* V, si
   const double qsc = inv_norm(qn2);
   double acc[1] = {0.0};
   for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
-    const double qr = __builtin_nontemporal_load(&V[j * ld + i]);
-    double q = qsc != 0.0 ? mul_nc(qr, qsc) : qr;
+    double v[K];  // every load of the element before the first product, as in k_dcgs2_dots
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = __builtin_nontemporal_load(&V[k * ld + i]);
     double wi = __builtin_nontemporal_load(&w[i]);
+    __builtin_amdgcn_sched_barrier(0);
+    double q = qsc != 0.0 ? mul_nc(v[j], qsc) : v[j];
 #pragma unroll
     for (int k = 0; k < j; ++k) {
-      const double v = __builtin_nontemporal_load(&V[k * ld + i]);
-      q -= sc[k] * v;
-      wi -= h[k] * v;
+      q -= sc[k] * v[k];
+      wi -= h[k] * v[k];
     }
     if (j > 0) {
       q *= inv_nu;
@@ -208,9 +215,13 @@ __global__ void __launch_bounds__(kBlock) k_lincomb(size_t n, const double* Z, s
 #pragma unroll
   for (int k = 0; k < K; ++k) yk[k] = y[k];
   for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+    double z[K];  // every load of the element before the first product, as in k_dcgs2_dots
+#pragma unroll
+    for (int k = 0; k < K; ++k) z[k] = Z[k * ld + i];
+    __builtin_amdgcn_sched_barrier(0);
     double s = 0.0;
 #pragma unroll
-    for (int k = 0; k < K; ++k) s += yk[k] * Z[k * ld + i];
+    for (int k = 0; k < K; ++k) s += yk[k] * z[k];
     dst[i] = s;
   }
 }
