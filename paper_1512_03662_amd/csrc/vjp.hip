@@ -398,35 +398,37 @@ __device__ __forceinline__ void vjp_axisB(const Grid& G, const PadGrid& PG, cons
     return idx;
   };
   {
+    // Each term's weight is tested only after all of the point's loads have been issued
+    // (every index is in range on every path), and a term of weight zero is dropped by a
+    // select: the loads of a point are then one batch instead of a chain of round trips
+    // behind the weight tests.
     auto coef = [&](const int* f, double* g) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) g[i] = 0.0;
       SH(m2, f, A, -2);
       SH(m1, f, A, -1);
       SH(p1, f, A, 1);
+      const int pf = padded(f);
       const double wv = Ac.u(A, f);
+      const double fbr = fbar[(size_t)A * PG.PN + max(pf, 0)];
+      const double r0 = Ac.rho(m2), r1 = Ac.rho(m1), r2 = Ac.rho(f), r3 = Ac.rho(p1);
+      const double e0 = Ac.e(m2), e1 = Ac.e(m1), e2 = Ac.e(f), e3 = Ac.e(p1);
+      const double Wf = Ac.W(1, f), Wm = Ac.W(1, m1);
+      const double fl = MF(A, f);
       double gg[4];
       // mass flux f_A = u_A rho*: rho at f - 2 .. f + 1
-      const int pf = padded(f);
-      const double fb = (pf >= 0) ? fbar[(size_t)A * PG.PN + pf] : 0.0;
-      if (fb != 0.0) {
-        upwind_grad(Ac.rho(m2), Ac.rho(m1), Ac.rho(f), Ac.rho(p1), wv, gg);
+      const double fb = (pf >= 0) ? fbr : 0.0;
+      upwind_grad(r0, r1, r2, r3, wv, gg);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) g[j] = fb * wv * gg[j];
-      }
+      for (int j = 0; j < 4; ++j) g[j] = (fb != 0.0) ? fb * wv * gg[j] : 0.0;
       // energy flux g_A = f_A e*: e at f - 2 .. f + 1
-      const double gb = (Ac.W(1, f) - Ac.W(1, m1)) * ih;
-      if (gb != 0.0) {
-        const double fl = MF(A, f);
-        upwind_grad(Ac.e(m2), Ac.e(m1), Ac.e(f), Ac.e(p1), wv, gg);
+      const double gb = (Wf - Wm) * ih;
+      upwind_grad(e0, e1, e2, e3, wv, gg);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) g[4 + j] = gb * fl * gg[j];
-      }
+      for (int j = 0; j < 4; ++j) g[4 + j] = (gb != 0.0) ? gb * fl * gg[j] : 0.0;
       // conduction q = chi_f (T0 - Tm) ih with Tm at f - e_A, T0 at f (not on wall faces)
       if (G.chi_model != 0 && !(G.bc[A] == 1 && (f[A] == 0 || f[A] == G.n[A]))) {
-        const double qb = (Ac.W(1, m1) - Ac.W(1, f)) * ih;
+        const double qb = (Wm - Wf) * ih;
         if (qb != 0.0) {
-          const double Tm = eos_T<RAD>(G, Ac.rho(m1), Ac.e(m1)), T0 = eos_T<RAD>(G, Ac.rho(f), Ac.e(f));
+          const double Tm = eos_T<RAD>(G, r1, e1), T0 = eos_T<RAD>(G, r2, e2);
           double chm, ch0, dchm, dch0;
           if (G.chi_model == 1) {
             chm = ch0 = G.chi0;
@@ -443,8 +445,8 @@ __device__ __forceinline__ void vjp_axisB(const Grid& G, const PadGrid& PG, cons
           const double qm = qb * (0.5 * dchm * dT - chif) * ih;  // times dT/dX of cell f - e_A
           const double q0 = qb * (0.5 * dch0 * dT + chif) * ih;  // times dT/dX of cell f
           if constexpr (RAD) {
-            const Thermo tm = thermo<true>(G, Ac.rho(m1), Ac.e(m1));
-            const Thermo t0 = thermo<true>(G, Ac.rho(f), Ac.e(f));
+            const Thermo tm = thermo<true>(G, r1, e1);
+            const Thermo t0 = thermo<true>(G, r2, e2);
             g[1] += qm * tm.dTdr;
             g[2] += q0 * t0.dTdr;
             g[5] += qm * tm.dTde;
@@ -464,19 +466,18 @@ __device__ __forceinline__ void vjp_axisB(const Grid& G, const PadGrid& PG, cons
   // Phi_AA: point q stands for the centre between faces q - e_A and q; u_A at q - 2 .. q + 1
   {
     auto coef = [&](const int* q, double* g) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) g[j] = 0.0;
       SH(qm, q, A, -1);
-      const double Pb = (Ac.W(2 + A, q) - Ac.W(2 + A, qm)) * ih;
-      if (Pb != 0.0) {
-        const double m = 0.5 * (MF(A, qm) + MF(A, q));
-        SH(qm2, q, A, -2);
-        SH(qp1, q, A, 1);
-        double gg[4];
-        upwind_grad(Ac.u(A, qm2), Ac.u(A, qm), Ac.u(A, q), Ac.u(A, qp1), m, gg);
+      SH(qm2, q, A, -2);
+      SH(qp1, q, A, 1);
+      const double Wq = Ac.W(2 + A, q), Wqm = Ac.W(2 + A, qm);
+      const double fm = MF(A, qm), f0 = MF(A, q);
+      const double u0 = Ac.u(A, qm2), u1 = Ac.u(A, qm), u2 = Ac.u(A, q), u3 = Ac.u(A, qp1);
+      const double Pb = (Wq - Wqm) * ih;
+      const double m = 0.5 * (fm + f0);
+      double gg[4];
+      upwind_grad(u0, u1, u2, u3, m, gg);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) g[j] = Pb * m * gg[j];
-      }
+      for (int j = 0; j < 4; ++j) g[j] = (Pb != 0.0) ? Pb * m * gg[j] : 0.0;
     };
     double acc[1] = {0.0};
     bscatter<ND, A, 1>(T, l, own, sC, coef, acc);
@@ -488,20 +489,19 @@ __device__ __forceinline__ void vjp_axisB(const Grid& G, const PadGrid& PG, cons
   for (int d = 0; d < ND; ++d) {
     if (d == A) continue;
     auto coef = [&](const int* q, double* g) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) g[j] = 0.0;
       SH(qm, q, A, -1);
-      const double Pb = (Ac.W(2 + d, q) - Ac.W(2 + d, qm)) * ih;
-      if (Pb != 0.0) {
-        SH(qd, q, d, -1);
-        const double m = 0.5 * (MF(A, qd) + MF(A, q));
-        SH(qm2, q, A, -2);
-        SH(qp1, q, A, 1);
-        double gg[4];
-        upwind_grad(Ac.u(d, qm2), Ac.u(d, qm), Ac.u(d, q), Ac.u(d, qp1), m, gg);
+      SH(qd, q, d, -1);
+      SH(qm2, q, A, -2);
+      SH(qp1, q, A, 1);
+      const double Wq = Ac.W(2 + d, q), Wqm = Ac.W(2 + d, qm);
+      const double fd = MF(A, qd), f0 = MF(A, q);
+      const double u0 = Ac.u(d, qm2), u1 = Ac.u(d, qm), u2 = Ac.u(d, q), u3 = Ac.u(d, qp1);
+      const double Pb = (Wq - Wqm) * ih;
+      const double m = 0.5 * (fd + f0);
+      double gg[4];
+      upwind_grad(u0, u1, u2, u3, m, gg);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) g[j] = Pb * m * gg[j];
-      }
+      for (int j = 0; j < 4; ++j) g[j] = (Pb != 0.0) ? Pb * m * gg[j] : 0.0;
     };
     double acc[1] = {0.0};
     bscatter<ND, A, 1>(T, l, own, sC, coef, acc);
@@ -515,45 +515,56 @@ template <int ND, bool RAD, class AC>
 __device__ __forceinline__ void vjp_localB(const Grid& G, const PadGrid& PG, const AC& Ac, const int* c, int pl,
                                            const double* fbar, double& rb, double& eb, double* ub) {
   const double gm1 = G.gamma - 1.0;
-  double pbar = 0.0;
+  // all loads first (as in the scatter passes).  The terms are added unconditionally: a term
+  // of weight zero adds an exact zero (its factors are finite), and the accumulators start at
+  // +0 and so never hold -0, which is what adding +0 would change
   const double WE = Ac.W(1, c);
-  if (WE != 0.0) {
+  const double rho0 = Ac.rho(c), e0 = Ac.e(c);
+  double uc[3], ucp[3], Wc[3], Wcp[3], fb[3], rm2[3], rm1[3], rp1[3], em1[3], Wm[3];
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    SH(cp, c, d, 1);
+    SH(m2, c, d, -2);
+    SH(m1, c, d, -1);
+    uc[d] = Ac.u(d, c);
+    ucp[d] = Ac.u(d, cp);
+    Wc[d] = Ac.W(2 + d, c);
+    Wcp[d] = Ac.W(2 + d, cp);
+    fb[d] = fbar[(size_t)d * PG.PN + pl];
+    rm2[d] = Ac.rho(m2);
+    rm1[d] = Ac.rho(m1);
+    rp1[d] = Ac.rho(cp);
+    em1[d] = Ac.e(m1);
+    Wm[d] = Ac.W(1, m1);
+  }
+  double pbar = 0.0;
+  {
     double D = 0.0;
 #pragma unroll
-    for (int d = 0; d < ND; ++d) {
-      SH(cp, c, d, 1);
-      D += (Ac.u(d, cp) - Ac.u(d, c)) * G.idx[d];
-    }
+    for (int d = 0; d < ND; ++d) D += (ucp[d] - uc[d]) * G.idx[d];
     pbar -= WE * D;
   }
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
-    SH(cp, c, d, 1);
-    pbar += (Ac.W(2 + d, cp) - Ac.W(2 + d, c)) * G.idx[d];
-    rb += 0.5 * G.g[d] * (Ac.W(2 + d, c) + Ac.W(2 + d, cp));
+    pbar += (Wcp[d] - Wc[d]) * G.idx[d];
+    rb += 0.5 * G.g[d] * (Wc[d] + Wcp[d]);
   }
   if constexpr (RAD) {
-    const Thermo th = thermo<true>(G, Ac.rho(c), Ac.e(c));
+    const Thermo th = thermo<true>(G, rho0, e0);
     rb += pbar * th.dpdr;
     eb += pbar * th.dpde;
   } else if (pbar != 0.0) {
-    rb += pbar * gm1 * Ac.e(c);
-    eb += pbar * gm1 * Ac.rho(c);
+    rb += pbar * gm1 * e0;
+    eb += pbar * gm1 * rho0;
   }
+  const double p0 = eos_p<RAD>(G, rho0, e0);
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
     const double ih = G.idx[d];
-    const double fb = fbar[(size_t)d * PG.PN + pl];
-    if (fb != 0.0) {
-      SH(m2, c, d, -2);
-      SH(m1, c, d, -1);
-      SH(p1, c, d, 1);
-      ub[d] += fb * upwind(Ac.rho(m2), Ac.rho(m1), Ac.rho(c), Ac.rho(p1), Ac.u(d, c));
-    }
-    SH(cm, c, d, -1);
-    const double a0 = Ac.W(1, c), a1 = Ac.W(1, cm);
-    if (a0 != 0.0) ub[d] += a0 * eos_p<RAD>(G, Ac.rho(c), Ac.e(c)) * ih;
-    if (a1 != 0.0) ub[d] -= a1 * eos_p<RAD>(G, Ac.rho(cm), Ac.e(cm)) * ih;
+    // the cell's own mass flux u_d rho*, the pressure gradients of the faces c and c + e_d
+    ub[d] += fb[d] * upwind(rm2[d], rm1[d], rho0, rp1[d], uc[d]);
+    ub[d] += WE * p0 * ih;
+    ub[d] -= Wm[d] * eos_p<RAD>(G, rm1[d], em1[d]) * ih;
   }
 }
 
