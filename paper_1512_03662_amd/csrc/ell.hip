@@ -1712,16 +1712,37 @@ __global__ void __launch_bounds__(kBlock) k_pbp_out(Grid G, const double* X, con
   double acc = 0.0;  // zpart: sum over the block's cells of (z / R)^2 (R the unknown scaling, alpha2)
   FOR_CELLS(lin, G.N) {
     Pos P = make_pos<ND>(G, lin);
-    double rho = X[lin], e = X[G.N + lin];
-    double r0, rE;
-    r_cell(G, X, v, scaled, lin, &r0, &rE, vsc);
+    // every load of the cell goes out first, as one batch (the wall test and the optional
+    // terms below no longer gate any of them); the arithmetic is unchanged
+    int im[ND];
+    double rhom[ND], em[ND], vm_raw[ND], v0m_raw[ND], ud[ND], dpm[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      double s;
+      im[d] = gidx<ND>(G, P, 0, shift(off0(), d, -1), &s);
+      rhom[d] = X[im[d]];
+      em[d] = X[G.N + im[d]];
+      vm_raw[d] = v[(2 + d) * G.N + lin];
+      v0m_raw[d] = v[im[d]];
+      ud[d] = X[(2 + d) * G.N + lin];
+      dpm[d] = dp[im[d]];
+    }
+    const double rho = X[lin], e = X[G.N + lin];
+    const double v0_raw = v[lin], vE_raw = v[G.N + lin];
+    const double dpc = dp[lin];
+    const double dTc = dT ? dT[lin] : 0.0;
+    auto vs = [&](double x) { return vsc != 0.0 ? mul_nc(x, vsc) : x; };
+    double r0 = vs(v0_raw), rE = vs(vE_raw);  // r_cell
+    if (scaled) {
+      r0 *= rho;
+      rE *= rho * e;
+    }
     const Thermo th = thermo_rt(G, rho, e);
     const double dpdr = th.dpdr, dpde = th.dpde;
     double Fp = (dpdr - (e / rho) * dpde) * r0 + (dpde / rho) * rE;
     double Fe = (rE - e * r0) / rho;
-    double dpc = dp[lin];
     double de;
-    if (dT) de = rad ? th.cv * dT[lin] : dT[lin] / gm1;  // de = c_v dT
+    if (dT) de = rad ? th.cv * dTc : dTc / gm1;  // de = c_v dT
     else de = dt * Fe + (dpc - dt * Fp) / (th.G1 * rho);
     const double z0 = zs * ((dpc - dpde * de) / dpdr), z1 = zs * de;
     z[lin] = z0;
@@ -1733,29 +1754,25 @@ __global__ void __launch_bounds__(kBlock) k_pbp_out(Grid G, const double* X, con
     }
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
-      double s;
-      int im = gidx<ND>(G, P, 0, shift(off0(), d, -1), &s);
-      double rhom = X[im];
-      double rf = 0.5 * (rhom + rho);
-      double vm = vread(v, (2 + d) * G.N + lin, vsc);
+      double rf = 0.5 * (rhom[d] + rho);
+      double vm = vs(vm_raw[d]);
       double rm = vm;
-      double r0m = vread(v, im, vsc);
-      double r0c = vread(v, lin, vsc);
-      double ud = X[(2 + d) * G.N + lin];
+      double r0m = vs(v0m_raw[d]);
+      double r0c = vs(v0_raw);
       double csf = 0.0;
-      if (scaled || zpart) csf = 0.5 * (sound_speed_rt(G, rhom, X[G.N + im]) + sound_speed_rt(G, rho, e));
+      if (scaled || zpart) csf = 0.5 * (sound_speed_rt(G, rhom[d], em[d]) + sound_speed_rt(G, rho, e));
       if (scaled) {
-        rm = vm * rf * fmax(fabs(ud), alpha1 * csf);
-        r0m *= rhom;
+        rm = vm * rf * fmax(fabs(ud[d]), alpha1 * csf);
+        r0m *= rhom[d];
         r0c *= rho;
       }
       double rbar = 0.5 * (r0m + r0c);
-      double Fu = (rm - ud * rbar) / rf;
-      double grad = (G.bc[d] == 1 && P.c[d] == 0) ? 0.0 : (dpc - dp[im]) / (rf * G.dx[d]);
+      double Fu = (rm - ud[d] * rbar) / rf;
+      double grad = (G.bc[d] == 1 && P.c[d] == 0) ? 0.0 : (dpc - dpm[d]) / (rf * G.dx[d]);
       const double zu = zs * (dt * (Fu - grad));
       z[(2 + d) * G.N + lin] = zu;
       if (zpart) {
-        const double q = zu / fmax(fabs(ud), alpha2 * csf);
+        const double q = zu / fmax(fabs(ud[d]), alpha2 * csf);
         acc += q * q;
       }
     }
